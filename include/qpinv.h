@@ -1,0 +1,221 @@
+/* qpinv -- Moore--Penrose pseudoinverse of dense quaternion matrices by hyperpower-family iterations
+ * on AMD Instinct MI355X (gfx950).  C ABI of libqpinv.so.
+ *
+ * Methods (Karmakar, Bhadala & Behera, "A Family of Iterative Methods for Computing Generalized
+ * Inverses of Quaternion Matrices and its Applications", Section 3):
+ *   Newton--Schulz (order 2), the hyperpower iteration of order p (definition of the quaternion
+ *   hyperpower iterative method), QSAI (Algorithm 2, order 10), QHPI19 (Algorithm 3, order 19) and
+ *   QRAPID (Algorithm 1, step parameter N).  Every iteration is a chain of quaternion matrix
+ *   products X_{j+1} = X_j p(R_j), R_j = I - A X_j, started from X_0 = alpha A^H (Theorem 1).
+ *
+ * Conventions
+ *   - A quaternion matrix A = A_s + A_x i + A_y j + A_z k (Section 2) is described by qpinv_qmat:
+ *     four real planes in ONE device allocation, plane p (p = 0..3 for s, x, y, z) starting at
+ *     data + p * plane_stride elements, each plane row-major with row stride `ld` elements.
+ *     Requirements: rows >= 0, cols >= 0, ld >= cols, plane_stride >= rows * ld.
+ *   - All matrix pointers are DEVICE pointers owned by the caller; the library never frees or
+ *     retains them beyond the call.  The library owns its workspace (grown on demand, freed by
+ *     qpinv_finalize).
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Calls enqueue their kernels on
+ *     that stream; calls that return host scalars (solve, residuals, features) synchronise it.
+ *   - Every function returns a status code (QPINV_OK = 0 or a negative error) and never throws or
+ *     aborts across the ABI.  The message of the last error on the calling thread is available
+ *     from qpinv_last_error().
+ *   - Overlapping calls on one context from several host threads are not supported.
+ */
+#ifndef QPINV_H
+#define QPINV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------------------------- status codes */
+#define QPINV_OK 0
+#define QPINV_EINVAL (-1)        /* bad argument: shape, order, pointer, dtype, option */
+#define QPINV_ENONFINITE (-2)    /* A (or a given X_0) holds NaN or Inf */
+#define QPINV_EDIVERGED (-3)     /* the iteration diverged (alpha outside (0, 2/sigma_1^2), Theorem 1) */
+#define QPINV_ENOTCONVERGED (-4) /* max_iter reached; X holds the last iterate (not fatal) */
+#define QPINV_EHIP (-5)          /* HIP runtime error (no device, launch failure, ...) */
+#define QPINV_ENOMEM (-6)        /* workspace allocation failed */
+#define QPINV_ETIMEOUT (-7)      /* a persistent kernel hit its bounded wait and exited early */
+
+/* ---------------------------------------------------------------------------------- types */
+typedef enum { QPINV_F64 = 0, QPINV_F32 = 1 } qpinv_dtype; /* storage type of a qpinv_qmat */
+
+typedef struct {
+  void* data;           /* device pointer to element (0,0) of plane s */
+  int64_t rows, cols;   /* matrix shape */
+  int64_t ld;           /* row stride of each plane, in elements */
+  int64_t plane_stride; /* distance between planes, in elements */
+  int32_t dtype;        /* qpinv_dtype */
+} qpinv_qmat;
+
+typedef enum {
+  QPINV_NS = 0,     /* Newton--Schulz X(2I - AX); order must be 2 (or 0 = default) */
+  QPINV_HPI = 1,    /* hyperpower X sum_{k<p} R^k in Horner form; order = p >= 2 */
+  QPINV_QSAI = 2,   /* Algorithm 2; order must be 10 (or 0) */
+  QPINV_QHPI19 = 3, /* Algorithm 3; order must be 19 (or 0) */
+  QPINV_QRAPID = 4  /* Algorithm 1; order = step parameter N >= 0 (-1 = default 5) */
+} qpinv_method;
+
+typedef enum {
+  QPINV_ALPHA_POWER = 0,   /* alpha = mu / sigma1_est^2, sigma1_est^2 from power iteration on A^H A
+                              (option power_steps, default 8); mu = alpha_or_mu if > 0 else 1 */
+  QPINV_ALPHA_FROB = 1,    /* alpha = 1 / ||A||_F^2 (Section 4 experimental setup) */
+  QPINV_ALPHA_GIVEN = 2,   /* alpha = alpha_or_mu (e.g. 1/sigma_max(A^C)^2 of Algorithms 1-3) */
+  QPINV_ALPHA_LEARNED = 3, /* mu predicted by the scaling network (qpinv_mlp_*), clamped; falls back to
+                              POWER when no network is loaded or the first step does not contract */
+  QPINV_X0_GIVEN = 4       /* X holds X_0 on entry (warm start / resume) */
+} qpinv_scaling;
+
+typedef enum {
+  QPINV_STOP_DX_ABS = 0, /* ||X_{j+1} - X_j||_F < tol  (stopping test of Algorithms 1-3) */
+  QPINV_STOP_DX_REL = 1, /* ||X_{j+1} - X_j||_F <= tol ||X_{j+1}||_F */
+  QPINV_STOP_E1_REL = 2, /* ||A X_{j+1} A - A||_F <= tol ||A||_F (two extra products per iteration) */
+  QPINV_STOP_GUARDED = 3 /* relative change <= tol, or the first rise of the relative change after it
+                            dropped below half its running maximum; then the better (smaller
+                            ||XAX - X||_F / ||X||_F, FP64) of the two iterates around the minimum */
+} qpinv_stop;
+
+typedef enum {
+  QPINV_PREC_F64 = 0,          /* every product in FP64 (MFMA f64) */
+  QPINV_PREC_F32 = 1,          /* every product in FP32 (MFMA f32, FP32 accumulate) */
+  QPINV_PREC_F32_F64FINISH = 2,/* FP32 until its stop rule fires, then 1-2 FP64 iterations */
+  QPINV_PREC_MIXED = 3         /* BF16 operands (FP32 accumulate) while ||R||_2 is large, then FP32,
+                                  then FP64 finish */
+} qpinv_precision;
+
+typedef enum { QPINV_GEMM_F64 = 0, QPINV_GEMM_F32 = 1, QPINV_GEMM_BF16 = 2 } qpinv_gemm_prec;
+
+typedef enum { QPINV_SIDE_AUTO = 0, QPINV_SIDE_LEFT = 1, QPINV_SIDE_RIGHT = 2 } qpinv_side;
+
+typedef enum {
+  QPINV_REASON_TOL = 0, QPINV_REASON_RISE = 1, QPINV_REASON_MAX_ITER = 2, QPINV_REASON_DIVERGED = 3
+} qpinv_reason;
+
+typedef struct {
+  int32_t iters;          /* updates performed, including the one that triggered the stop */
+  int32_t iters_bf16, iters_f32, iters_f64; /* per-precision split of iters */
+  int32_t returned;       /* index j of the returned iterate X_j */
+  int32_t stop_reason;    /* qpinv_reason */
+  int32_t side;           /* residual side used: 1 left (I_n - XA), 2 right (I_m - AX) */
+  int32_t alpha_clamped;  /* learned mu was clamped into the admissible interval */
+  int32_t fallback_used;  /* the classical alpha replaced a failed first choice */
+  int32_t reserved;
+  double alpha_used;      /* alpha of X_0 = alpha A^H (0 for X0_GIVEN) */
+  double mu_used;         /* alpha * sigma1_est^2 */
+  double sigma1_sq_est;   /* power-iteration estimate (0 if not computed) */
+  double final_dx_rel;    /* ||X_j - X_{j-1}||_F / ||X_j||_F of the last update */
+  double e1_rel;          /* ||AXA - A||_F / ||A||_F when the stop rule computed it, else -1 */
+  double seconds;         /* host wall time of the call */
+  double gemm_flops;      /* algorithmic flops of the quaternion products (32 M N K each) */
+} qpinv_info;
+
+typedef struct qpinv_ctx qpinv_ctx;
+
+/* ---------------------------------------------------------------------------------- lifecycle */
+
+/* Create a context on HIP device `device`.  `config` is NULL or "key=value;key=value" with the
+ * keys of qpinv_set_option.  Errors: EINVAL (bad key/value), EHIP (no such device). */
+int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
+
+/* Set a numeric option: side (qpinv_side), power_steps (>= 1), power_seed, autotune (0/1),
+ * f64_finish_iters (1..4), mixed_switch (||R||_2 threshold, default 1e-2), mixed_rnorm_steps,
+ * max_bf16_iters, gemm_timing (0/1), verbose (0/1).  Errors: EINVAL for an unknown key or out-of-range value. */
+int qpinv_set_option(qpinv_ctx* ctx, const char* key, double value);
+
+/* Free the workspace and the context.  NULL is accepted. */
+int qpinv_finalize(qpinv_ctx* ctx);
+
+/* Human-readable name of a status code (static storage). */
+const char* qpinv_strerror(int status);
+
+/* Message of the last failing call on this host thread (static per-thread storage). */
+const char* qpinv_last_error(void);
+
+/* ---------------------------------------------------------------------------------- the solve */
+
+/* X ~= A^dagger for A (rows m, cols n) by `method` (Section 3; Algorithms 1-3).
+ *   order        see qpinv_method.
+ *   scaling      how X_0 = alpha A^H is chosen (Theorem 1; scaling step of Algorithms 1-3).
+ *   alpha_or_mu  alpha for ALPHA_GIVEN, mu multiplier for ALPHA_POWER (<= 0 means 1).
+ *   tol, max_iter, stop   stop rule (stopping test of Algorithms 1-3 and variants).
+ *   precision    arithmetic of the products (qpinv_precision).  A may be F32 or F64 storage; the
+ *                library converts into its workspace when the precision needs the other type.
+ *   X            output, shape n x m, F32 or F64; for QPINV_X0_GIVEN it also holds X_0 on entry.
+ *   info         may be NULL.
+ * Return: OK; ENOTCONVERGED (X = last iterate); EDIVERGED (X = last finite iterate);
+ *         ENONFINITE (A has NaN/Inf, X untouched); EINVAL; EHIP; ENOMEM. */
+int qpinv_solve(qpinv_ctx* ctx, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu,
+                double tol, int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info,
+                void* hip_stream);
+
+/* One iteration X_out = X_{j+1} from X_in = X_j (Algorithms 1-3, one pass of the loop body) in the
+ * given product precision (qpinv_gemm_prec) on the given side (LEFT/RIGHT; AUTO picks the smaller).
+ * A, X_in, X_out share one storage dtype (F64 for GEMM_F64, F32 otherwise).  `dx` (host, may be
+ * NULL) receives {||X_out - X_in||_F^2, ||X_out||_F^2}.  Errors: EINVAL, EHIP, ENOMEM. */
+int qpinv_step(qpinv_ctx* ctx, int method, int order, int side, int gemm_prec, const qpinv_qmat* A,
+               const qpinv_qmat* X_in, qpinv_qmat* X_out, double dx[2], void* hip_stream);
+
+/* Penrose residuals (Section 4, error metrics) computed in FP64 on the GPU:
+ *   E_abs = {||AXA - A||_F, ||XAX - X||_F, ||(AX)^H - AX||_F, ||(XA)^H - XA||_F},
+ *   E_rel = E_abs / {||A||_F, ||X||_F, ||AX||_F, ||XA||_F}  (host arrays of 4).
+ * Errors: EINVAL, EHIP, ENOMEM. */
+int qpinv_residuals(qpinv_ctx* ctx, const qpinv_qmat* A, const qpinv_qmat* X, double E_abs[4], double E_rel[4],
+                    void* hip_stream);
+
+/* ---------------------------------------------------------------------------------- building blocks */
+
+/* Quaternion product (Section 2, Hamilton product): C = alpha A B + beta C + gamma I, with
+ * A (M x K), B (K x N), C (M x N) of one storage dtype (F64 for GEMM_F64, F32 otherwise) and I the
+ * quaternion identity (ones on the diagonal of the real plane).  C must not alias A or B.
+ * Errors: EINVAL, EHIP. */
+int qpinv_qgemm(qpinv_ctx* ctx, int gemm_prec, const qpinv_qmat* A, const qpinv_qmat* B, qpinv_qmat* C,
+                double alpha, double beta, double gamma, void* hip_stream);
+
+/* Initial iterate X = alpha A^H (Theorem 1): X (n x m) from A (m x n); dtypes may differ.
+ * Errors: EINVAL, EHIP. */
+int qpinv_x0(qpinv_ctx* ctx, const qpinv_qmat* A, double alpha, qpinv_qmat* X, void* hip_stream);
+
+/* Scaling features of A (used by ALPHA_POWER / ALPHA_LEARNED) into host out[6]:
+ *   {sigma1_est^2 (power_steps steps on A^H A from the SplitMix64 start vector, seed power_seed),
+ *    ||A||_F, ||A||_1, ||A||_inf, rows, cols}.
+ * `power_steps` <= 0 uses the context option.  Errors: EINVAL, ENONFINITE, EHIP. */
+int qpinv_features(qpinv_ctx* ctx, const qpinv_qmat* A, int power_steps, double out[6], void* hip_stream);
+
+/* Time every tile configuration of the product for shape (M, N, K) in `gemm_prec` and remember the
+ * fastest for later solves on this context.  best_ms (host, may be NULL) receives its time.
+ * Returns the chosen configuration id (>= 0) or an error. */
+int qpinv_autotune(qpinv_ctx* ctx, int gemm_prec, int64_t M, int64_t N, int64_t K, double* best_ms,
+                   void* hip_stream);
+
+/* Number of tile configurations for a product precision, and the name of one (static storage). */
+int qpinv_num_tile_configs(int gemm_prec);
+const char* qpinv_tile_config_name(int gemm_prec, int cfg);
+
+/* Same as qpinv_qgemm with an explicit tile configuration (for measurement). */
+int qpinv_qgemm_cfg(qpinv_ctx* ctx, int gemm_prec, int cfg, const qpinv_qmat* A, const qpinv_qmat* B,
+                    qpinv_qmat* C, double alpha, double beta, double gamma, void* hip_stream);
+
+/* Product launch statistics.  With option gemm_timing = 1 every quaternion product this context
+ * launches is bracketed by HIP events on its stream.  out (host, 3 doubles) receives
+ * {launches, algorithmic flops (32 M N K each), summed event milliseconds} since the previous call;
+ * the call waits for those events and resets the counters.  Errors: EINVAL, EHIP. */
+int qpinv_gemm_stats(qpinv_ctx* ctx, double out[3]);
+
+/* Stop-rule controller replay (host only, no GPU use): feed per-update scalars
+ * d_abs[j] = ||X_{j+1}-X_j||_F, x_norm[j] = ||X_{j+1}||_F, e1_rel[j] (may be NULL unless
+ * stop = E1_REL) for j < count into the controller of `stop` with `tol`; writes the decision per
+ * update into decision[j] (0 continue, 1 stop by tol, 2 stop by rise, 3 diverged, 4 new minimum
+ * recorded) and returns the number of updates consumed before stopping (count if none). */
+int qpinv_controller_replay(int stop, double tol, int count, const double* d_abs, const double* x_norm,
+                            const double* e1_rel, int* decision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPINV_H */

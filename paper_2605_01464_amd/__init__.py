@@ -1,0 +1,332 @@
+"""Python binding of libqpinv.so (quaternion Moore--Penrose pseudoinverse on MI355X / gfx950).
+
+Argument marshalling only: every step of a solve runs in the library's HIP kernels.  PyTorch is used
+for device memory and streams.  A quaternion matrix is a CUDA (HIP) tensor of shape (4, rows, cols)
+holding the planes (s, x, y, z), float32 or float64, with unit stride along columns.
+
+The functions named ``qpinv_*`` mirror the C ABI in include/qpinv.h one to one and return its status
+codes; ``solve``, ``step``, ``residuals``, ``qgemm`` and ``features`` are thin conveniences that
+raise ``QpinvError`` on failure.  If the shared library has not been built the import of this
+module fails loudly (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqpinv.so")
+
+# ------------------------------------------------------------------------------------------ constants
+OK, EINVAL, ENONFINITE, EDIVERGED, ENOTCONVERGED, EHIP, ENOMEM, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+F64, F32 = 0, 1
+METHOD = {"ns": 0, "hpi": 1, "qsai": 2, "qhpi19": 3, "qrapid": 4}
+SCALING = {"power": 0, "frob": 1, "given": 2, "learned": 3, "x0": 4}
+STOP = {"dx_abs": 0, "dx_rel": 1, "e1_rel": 2, "guarded": 3}
+PRECISION = {"f64": 0, "f32": 1, "f32_f64finish": 2, "mixed": 3}
+GEMM_PREC = {"f64": 0, "f32": 1, "bf16": 2}
+SIDE = {"auto": 0, "left": 1, "right": 2}
+REASON = {0: "tol", 1: "rise", 2: "max_iter", 3: "diverged"}
+DEFAULT_ORDER = {"ns": 2, "hpi": None, "qsai": 10, "qhpi19": 19, "qrapid": 5}
+
+
+class QMat(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("plane_stride", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("iters_bf16", ctypes.c_int32), ("iters_f32", ctypes.c_int32),
+                ("iters_f64", ctypes.c_int32), ("returned", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
+                ("side", ctypes.c_int32), ("alpha_clamped", ctypes.c_int32), ("fallback_used", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("alpha_used", ctypes.c_double), ("mu_used", ctypes.c_double),
+                ("sigma1_sq_est", ctypes.c_double), ("final_dx_rel", ctypes.c_double),
+                ("e1_rel", ctypes.c_double), ("seconds", ctypes.c_double), ("gemm_flops", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d["reason"] = REASON.get(self.stop_reason, "?")
+        return d
+
+
+class QpinvError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {message} (status {status})")
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    # PyTorch ships its own HIP runtime with the same SONAME as ROCm's; importing it first makes the
+    # library bind to that one runtime instance instead of loading a second one into the process.
+    import torch  # noqa: F401
+
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2605_01464_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    QP = ctypes.POINTER(QMat)
+    DP = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "qpinv_init": (I, [ctypes.POINTER(P), I, ctypes.c_char_p]),
+        "qpinv_set_option": (I, [P, ctypes.c_char_p, D]),
+        "qpinv_finalize": (I, [P]),
+        "qpinv_strerror": (ctypes.c_char_p, [I]),
+        "qpinv_last_error": (ctypes.c_char_p, []),
+        "qpinv_solve": (I, [P, I, I, QP, I, D, D, I, I, I, QP, ctypes.POINTER(Info), P]),
+        "qpinv_step": (I, [P, I, I, I, I, QP, QP, QP, DP, P]),
+        "qpinv_residuals": (I, [P, QP, QP, DP, DP, P]),
+        "qpinv_qgemm": (I, [P, I, QP, QP, QP, D, D, D, P]),
+        "qpinv_qgemm_cfg": (I, [P, I, I, QP, QP, QP, D, D, D, P]),
+        "qpinv_x0": (I, [P, QP, D, QP, P]),
+        "qpinv_features": (I, [P, QP, I, DP, P]),
+        "qpinv_autotune": (I, [P, I, I64, I64, I64, DP, P]),
+        "qpinv_num_tile_configs": (I, [I]),
+        "qpinv_tile_config_name": (ctypes.c_char_p, [I, I]),
+        "qpinv_controller_replay": (I, [I, D, I, DP, DP, DP, ctypes.POINTER(ctypes.c_int)]),
+        "qpinv_gemm_stats": (I, [P, DP]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+# ------------------------------------------------------------------------------------------ marshalling
+def qmat(t) -> QMat:
+    """Describe a (4, rows, cols) float32/float64 device tensor with unit column stride."""
+    import torch
+
+    if t.dim() != 3 or t.shape[0] != 4:
+        raise ValueError("a quaternion matrix is a tensor of shape (4, rows, cols)")
+    if t.dtype not in (torch.float32, torch.float64):
+        raise ValueError("quaternion planes must be float32 or float64")
+    if not t.is_cuda:
+        raise ValueError("quaternion matrices must live in GPU memory")
+    rows, cols = int(t.shape[1]), int(t.shape[2])
+    if cols > 1 and t.stride(2) != 1:
+        raise ValueError("columns must have unit stride")
+    ld = int(t.stride(1)) if rows > 1 else max(cols, 1)
+    ps = int(t.stride(0))
+    return QMat(t.data_ptr(), rows, cols, max(ld, cols, 1), max(ps, rows * max(ld, cols, 1)),
+                F64 if t.dtype == torch.float64 else F32)
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _err(status: int, where: str) -> None:
+    if status != OK:
+        raise QpinvError(status, where, _lib.qpinv_last_error().decode() or _lib.qpinv_strerror(status).decode())
+
+
+# ------------------------------------------------------------------------------------------ C ABI mirror
+def qpinv_init(device: int = 0, config: str | None = None):
+    h = ctypes.c_void_p()
+    st = _lib.qpinv_init(ctypes.byref(h), device, config.encode() if config else None)
+    return st, h
+
+
+def qpinv_set_option(ctx, key: str, value: float) -> int:
+    return _lib.qpinv_set_option(ctx, key.encode(), float(value))
+
+
+def qpinv_finalize(ctx) -> int:
+    return _lib.qpinv_finalize(ctx)
+
+
+def qpinv_strerror(status: int) -> str:
+    return _lib.qpinv_strerror(status).decode()
+
+
+def qpinv_last_error() -> str:
+    return _lib.qpinv_last_error().decode()
+
+
+def qpinv_solve(ctx, method, order, A, scaling, alpha_or_mu, tol, max_iter, stop, precision, X, stream=None):
+    info = Info()
+    st = _lib.qpinv_solve(ctx, method, order, ctypes.byref(qmat(A)), scaling, float(alpha_or_mu), float(tol),
+                          int(max_iter), stop, precision, ctypes.byref(qmat(X)), ctypes.byref(info), _stream(stream))
+    return st, info
+
+
+def qpinv_step(ctx, method, order, side, gemm_prec, A, X_in, X_out, stream=None):
+    dx = (ctypes.c_double * 2)()
+    st = _lib.qpinv_step(ctx, method, order, side, gemm_prec, ctypes.byref(qmat(A)), ctypes.byref(qmat(X_in)),
+                         ctypes.byref(qmat(X_out)), dx, _stream(stream))
+    return st, (dx[0], dx[1])
+
+
+def qpinv_residuals(ctx, A, X, stream=None):
+    Ea = (ctypes.c_double * 4)()
+    Er = (ctypes.c_double * 4)()
+    st = _lib.qpinv_residuals(ctx, ctypes.byref(qmat(A)), ctypes.byref(qmat(X)), Ea, Er, _stream(stream))
+    return st, tuple(Ea), tuple(Er)
+
+
+def qpinv_qgemm(ctx, gemm_prec, A, B, C, alpha=1.0, beta=0.0, gamma=0.0, stream=None) -> int:
+    return _lib.qpinv_qgemm(ctx, gemm_prec, ctypes.byref(qmat(A)), ctypes.byref(qmat(B)), ctypes.byref(qmat(C)),
+                            float(alpha), float(beta), float(gamma), _stream(stream))
+
+
+def qpinv_qgemm_cfg(ctx, gemm_prec, cfg, A, B, C, alpha=1.0, beta=0.0, gamma=0.0, stream=None) -> int:
+    return _lib.qpinv_qgemm_cfg(ctx, gemm_prec, cfg, ctypes.byref(qmat(A)), ctypes.byref(qmat(B)),
+                                ctypes.byref(qmat(C)), float(alpha), float(beta), float(gamma), _stream(stream))
+
+
+def qpinv_x0(ctx, A, alpha, X, stream=None) -> int:
+    return _lib.qpinv_x0(ctx, ctypes.byref(qmat(A)), float(alpha), ctypes.byref(qmat(X)), _stream(stream))
+
+
+def qpinv_features(ctx, A, power_steps=0, stream=None):
+    out = (ctypes.c_double * 6)()
+    st = _lib.qpinv_features(ctx, ctypes.byref(qmat(A)), int(power_steps), out, _stream(stream))
+    return st, tuple(out)
+
+
+def qpinv_autotune(ctx, gemm_prec, M, N, K, stream=None):
+    ms = ctypes.c_double(0.0)
+    r = _lib.qpinv_autotune(ctx, gemm_prec, int(M), int(N), int(K), ctypes.byref(ms), _stream(stream))
+    return r, ms.value
+
+
+def qpinv_num_tile_configs(gemm_prec) -> int:
+    return _lib.qpinv_num_tile_configs(gemm_prec)
+
+
+def qpinv_tile_config_name(gemm_prec, cfg) -> str:
+    return _lib.qpinv_tile_config_name(gemm_prec, cfg).decode()
+
+
+def qpinv_gemm_stats(ctx):
+    out = (ctypes.c_double * 3)()
+    st = _lib.qpinv_gemm_stats(ctx, out)
+    return st, (int(out[0]), out[1], out[2])
+
+
+def qpinv_controller_replay(stop, tol, d_abs, x_norm, e1_rel=None):
+    n = len(d_abs)
+    Da = (ctypes.c_double * n)(*d_abs)
+    Xn = (ctypes.c_double * n)(*x_norm)
+    E1 = (ctypes.c_double * n)(*e1_rel) if e1_rel is not None else None
+    dec = (ctypes.c_int * n)()
+    used = _lib.qpinv_controller_replay(stop, float(tol), n, Da, Xn, E1, dec)
+    return used, list(dec)
+
+
+# ------------------------------------------------------------------------------------------ conveniences
+class Context:
+    """Owns a qpinv context on one device; usable as a context manager."""
+
+    def __init__(self, device: int = 0, config: str | None = None):
+        st, h = qpinv_init(device, config)
+        _err(st, "qpinv_init")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            qpinv_finalize(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, key: str, value: float):
+        _err(qpinv_set_option(self.handle, key, value), f"set_option({key})")
+
+
+def _order(method: str, order):
+    if order is not None:
+        return int(order)
+    d = DEFAULT_ORDER[method]
+    if d is None:
+        raise ValueError(f"method {method!r} needs an explicit order")
+    return d
+
+
+def solve(ctx: Context, A, method="qhpi19", order=None, scaling="power", alpha=0.0, tol=1e-6, max_iter=500,
+          stop="guarded", precision=None, X=None, out_dtype=None, stream=None, check=True):
+    """X ~= A^dagger.  Returns (X, info dict).  ENOTCONVERGED is reported in info, not raised."""
+    import torch
+
+    if precision is None:
+        precision = "f64" if A.dtype == torch.float64 else "f32"
+    if X is None:
+        X = torch.empty((4, A.shape[2], A.shape[1]), dtype=out_dtype or A.dtype, device=A.device)
+    st, info = qpinv_solve(ctx.handle, METHOD[method], _order(method, order), A, SCALING[scaling], alpha, tol,
+                           max_iter, STOP[stop], PRECISION[precision], X, stream)
+    d = info.as_dict()
+    d["status"] = st
+    if check and st not in (OK, ENOTCONVERGED):
+        _err(st, "qpinv_solve")
+    return X, d
+
+
+def step(ctx: Context, A, X, method="qhpi19", order=None, side="auto", gemm_prec=None, out=None, stream=None):
+    import torch
+
+    if gemm_prec is None:
+        gemm_prec = "f64" if A.dtype == torch.float64 else "f32"
+    out = torch.empty_like(X) if out is None else out
+    st, dx = qpinv_step(ctx.handle, METHOD[method], _order(method, order), SIDE[side], GEMM_PREC[gemm_prec], A, X,
+                        out, stream)
+    _err(st, "qpinv_step")
+    return out, dx
+
+
+def residuals(ctx: Context, A, X, stream=None):
+    st, Ea, Er = qpinv_residuals(ctx.handle, A, X, stream)
+    _err(st, "qpinv_residuals")
+    return Ea, Er
+
+
+def qgemm(ctx: Context, A, B, C=None, alpha=1.0, beta=0.0, gamma=0.0, gemm_prec=None, cfg=None, stream=None):
+    import torch
+
+    if gemm_prec is None:
+        gemm_prec = "f64" if A.dtype == torch.float64 else "f32"
+    if C is None:
+        C = torch.zeros((4, A.shape[1], B.shape[2]), dtype=A.dtype, device=A.device)
+    if cfg is None:
+        st = qpinv_qgemm(ctx.handle, GEMM_PREC[gemm_prec], A, B, C, alpha, beta, gamma, stream)
+    else:
+        st = qpinv_qgemm_cfg(ctx.handle, GEMM_PREC[gemm_prec], cfg, A, B, C, alpha, beta, gamma, stream)
+    _err(st, "qpinv_qgemm")
+    return C
+
+
+def features(ctx: Context, A, power_steps=0, stream=None):
+    st, out = qpinv_features(ctx.handle, A, power_steps, stream)
+    _err(st, "qpinv_features")
+    return {"sigma1_sq": out[0], "fro": out[1], "norm1": out[2], "norminf": out[3], "m": int(out[4]),
+            "n": int(out[5])}
+
+
+def x0(ctx: Context, A, alpha, out_dtype=None, stream=None):
+    import torch
+
+    X = torch.empty((4, A.shape[2], A.shape[1]), dtype=out_dtype or A.dtype, device=A.device)
+    _err(qpinv_x0(ctx.handle, A, alpha, X, stream), "qpinv_x0")
+    return X

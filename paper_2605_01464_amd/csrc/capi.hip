@@ -1,0 +1,342 @@
+// extern "C" boundary of libqpinv.so: argument checks, error codes, no exceptions across the ABI.
+#include <cstring>
+#include <string>
+
+#include "../../include/qpinv.h"
+#include "aux.hpp"
+#include "controller.hpp"
+#include "mlp.hpp"
+#include "solver.hpp"
+
+struct qpinv_ctx {
+  qp::Ctx* impl;
+};
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const qp::Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return QPINV_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return QPINV_EHIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return QPINV_EHIP;
+  }
+}
+
+qp::Ctx& ctx_of(qpinv_ctx* c) {
+  if (!c || !c->impl) throw qp::Error(QPINV_EINVAL, "null context");
+  QP_HIP(hipSetDevice(c->impl->device));
+  return *c->impl;
+}
+
+hipStream_t stream_of(void* s) { return static_cast<hipStream_t>(s); }
+
+int prec_check(int gemm_prec) {
+  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16) throw qp::Error(QPINV_EINVAL, "bad product precision");
+  return gemm_prec;
+}
+
+int storage_for(int gemm_prec) { return gemm_prec == QPINV_GEMM_F64 ? QPINV_F64 : QPINV_F32; }
+
+void set_option(qp::Ctx& c, const std::string& key, double v) {
+  auto need = [&](bool ok) {
+    if (!ok) throw qp::Error(QPINV_EINVAL, "option " + key + ": value out of range");
+  };
+  if (key == "side") {
+    need(v == 0 || v == 1 || v == 2);
+    c.opt.side = (int)v;
+  } else if (key == "power_steps") {
+    need(v >= 1 && v <= 1000);
+    c.opt.power_steps = (int)v;
+  } else if (key == "power_seed") {
+    need(v >= 0);
+    c.opt.power_seed = (uint64_t)v;
+  } else if (key == "autotune") {
+    need(v == 0 || v == 1);
+    c.opt.autotune = (int)v;
+  } else if (key == "f64_finish_iters") {
+    need(v >= 1 && v <= 4);
+    c.opt.f64_finish_iters = (int)v;
+  } else if (key == "mixed_switch") {
+    need(v > 0 && v < 1);
+    c.opt.mixed_switch = v;
+  } else if (key == "mixed_rnorm_steps") {
+    need(v >= 1 && v <= 100);
+    c.opt.mixed_rnorm_steps = (int)v;
+  } else if (key == "max_bf16_iters") {
+    need(v >= 0 && v <= 100);
+    c.opt.max_bf16_iters = (int)v;
+  } else if (key == "gemm_timing") {
+    need(v == 0 || v == 1);
+    c.opt.gemm_timing = (int)v;
+  } else if (key == "verbose") {
+    c.opt.verbose = v != 0;
+  } else {
+    throw qp::Error(QPINV_EINVAL, "unknown option " + key);
+  }
+}
+}  // namespace
+
+extern "C" {
+
+const char* qpinv_strerror(int status) {
+  switch (status) {
+    case QPINV_OK: return "ok";
+    case QPINV_EINVAL: return "invalid argument";
+    case QPINV_ENONFINITE: return "non-finite input";
+    case QPINV_EDIVERGED: return "iteration diverged";
+    case QPINV_ENOTCONVERGED: return "not converged within max_iter";
+    case QPINV_EHIP: return "HIP runtime error";
+    case QPINV_ENOMEM: return "out of memory";
+    case QPINV_ETIMEOUT: return "bounded wait expired";
+    default: return "unknown status";
+  }
+}
+
+const char* qpinv_last_error(void) { return g_last_error.c_str(); }
+
+int qpinv_init(qpinv_ctx** out, int device, const char* config) {
+  return guarded([&]() {
+    if (!out) throw qp::Error(QPINV_EINVAL, "null output pointer");
+    *out = nullptr;
+    int count = 0;
+    QP_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) throw qp::Error(QPINV_EINVAL, "no such device");
+    auto* impl = new qp::Ctx(device);
+    try {
+      if (config) {
+        std::string cfg(config);
+        size_t pos = 0;
+        while (pos < cfg.size()) {
+          size_t end = cfg.find(';', pos);
+          if (end == std::string::npos) end = cfg.size();
+          std::string item = cfg.substr(pos, end - pos);
+          pos = end + 1;
+          if (item.empty()) continue;
+          const size_t eq = item.find('=');
+          if (eq == std::string::npos) throw qp::Error(QPINV_EINVAL, "config item without '=': " + item);
+          char* tail = nullptr;
+          const std::string val = item.substr(eq + 1);
+          const double v = std::strtod(val.c_str(), &tail);
+          if (!tail || *tail != '\0') throw qp::Error(QPINV_EINVAL, "config value not numeric: " + item);
+          set_option(*impl, item.substr(0, eq), v);
+        }
+      }
+    } catch (...) {
+      delete impl;
+      throw;
+    }
+    *out = new qpinv_ctx{impl};
+    return QPINV_OK;
+  });
+}
+
+int qpinv_set_option(qpinv_ctx* c, const char* key, double value) {
+  return guarded([&]() {
+    if (!key) throw qp::Error(QPINV_EINVAL, "null key");
+    set_option(ctx_of(c), key, value);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_finalize(qpinv_ctx* c) {
+  return guarded([&]() {
+    if (!c) return QPINV_OK;
+    if (c->impl) qp::mlp_free(c->impl);
+    delete c->impl;
+    delete c;
+    return QPINV_OK;
+  });
+}
+
+int qpinv_solve(qpinv_ctx* c, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu, double tol,
+                int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info, void* hip_stream) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    return qp::solve(cx, method, order, A, scaling, alpha_or_mu, tol, max_iter, stop, precision, X, info,
+                     stream_of(hip_stream));
+  });
+}
+
+int qpinv_step(qpinv_ctx* c, int method, int order, int side, int gemm_prec, const qpinv_qmat* A, const qpinv_qmat* X_in,
+               qpinv_qmat* X_out, double dx[2], void* hip_stream) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    prec_check(gemm_prec);
+    qp::check_method(method, order);
+    qp::validate(A, "A");
+    qp::validate(X_in, "X_in");
+    qp::validate(X_out, "X_out");
+    const int st = storage_for(gemm_prec);
+    if (A->dtype != st || X_in->dtype != st || X_out->dtype != st)
+      throw qp::Error(QPINV_EINVAL, "step: A and X must have the storage type of the product precision");
+    if (X_in->rows != A->cols || X_in->cols != A->rows || X_out->rows != A->cols || X_out->cols != A->rows)
+      throw qp::Error(QPINV_EINVAL, "step: X must be n x m");
+    if (X_in->data == X_out->data && X_in->rows * X_in->cols > 0) throw qp::Error(QPINV_EINVAL, "step: X_out aliases X_in");
+    if (side != QPINV_SIDE_LEFT && side != QPINV_SIDE_RIGHT && side != QPINV_SIDE_AUTO)
+      throw qp::Error(QPINV_EINVAL, "bad side");
+    if (side == QPINV_SIDE_AUTO) side = A->rows > A->cols ? QPINV_SIDE_LEFT : QPINV_SIDE_RIGHT;
+    if (A->rows == 0 || A->cols == 0) {
+      if (dx) dx[0] = dx[1] = 0.0;
+      return QPINV_OK;
+    }
+    hipStream_t s = stream_of(hip_stream);
+    qp::chain(cx, method, order, side, (qp::Prec)gemm_prec, qp::from_abi(*A), qp::from_abi(*X_in),
+              qp::from_abi(*X_out), cx.dsc, s);
+    QP_HIP(hipMemcpyAsync(cx.hsc, cx.dsc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    QP_HIP(hipStreamSynchronize(s));
+    if (dx) {
+      dx[0] = cx.hsc[0];
+      dx[1] = cx.hsc[1];
+    }
+    return QPINV_OK;
+  });
+}
+
+int qpinv_residuals(qpinv_ctx* c, const qpinv_qmat* A, const qpinv_qmat* X, double E_abs[4], double E_rel[4],
+                    void* hip_stream) {
+  return guarded([&]() {
+    if (!E_abs || !E_rel) throw qp::Error(QPINV_EINVAL, "null output arrays");
+    qp::residuals(ctx_of(c), A, X, E_abs, E_rel, stream_of(hip_stream));
+    return QPINV_OK;
+  });
+}
+
+static int qgemm_impl(qpinv_ctx* c, int gemm_prec, int cfg, const qpinv_qmat* A, const qpinv_qmat* B, qpinv_qmat* C,
+                      double alpha, double beta, double gamma, void* hip_stream) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    prec_check(gemm_prec);
+    qp::validate(A, "A");
+    qp::validate(B, "B");
+    qp::validate(C, "C");
+    const int st = storage_for(gemm_prec);
+    if (A->dtype != st || B->dtype != st || C->dtype != st)
+      throw qp::Error(QPINV_EINVAL, "qgemm: operands must have the storage type of the product precision");
+    if (A->cols != B->rows || C->rows != A->rows || C->cols != B->cols) throw qp::Error(QPINV_EINVAL, "qgemm: shape mismatch");
+    if (C->data && (C->data == A->data || C->data == B->data)) throw qp::Error(QPINV_EINVAL, "qgemm: C aliases an operand");
+    const int ncfg = (int)qp::tile_configs((qp::Prec)gemm_prec).size();
+    if (cfg >= ncfg) throw qp::Error(QPINV_EINVAL, "qgemm: bad tile configuration");
+    const qp::Mat Am = qp::from_abi(*A), Bm = qp::from_abi(*B), Cm = qp::from_abi(*C);
+    qp::Epilogue e;
+    e.nout = 1;
+    e.out[0] = Cm.v;
+    e.a[0] = alpha;
+    e.g[0] = gamma;
+    if (beta != 0.0) {
+      e.nin = 1;
+      e.in[0] = Cm.v;
+      e.b[0][0] = beta;
+    }
+    const int64_t M = A->rows, N = B->cols, K = A->cols;
+    if (cfg < 0) cfg = cx.config_for((qp::Prec)gemm_prec, M, N, K, stream_of(hip_stream));
+    cx.flops += 32.0 * (double)M * (double)N * (double)K;
+    qp::qgemm((qp::Prec)gemm_prec, Am.v, Bm.v, M, N, K, e, nullptr, cx.scratch, stream_of(hip_stream), cfg);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_qgemm(qpinv_ctx* c, int gemm_prec, const qpinv_qmat* A, const qpinv_qmat* B, qpinv_qmat* C, double alpha,
+                double beta, double gamma, void* hip_stream) {
+  return qgemm_impl(c, gemm_prec, -1, A, B, C, alpha, beta, gamma, hip_stream);
+}
+
+int qpinv_qgemm_cfg(qpinv_ctx* c, int gemm_prec, int cfg, const qpinv_qmat* A, const qpinv_qmat* B, qpinv_qmat* C,
+                    double alpha, double beta, double gamma, void* hip_stream) {
+  if (cfg < 0) {
+    g_last_error = "qgemm_cfg: cfg must be >= 0";
+    return QPINV_EINVAL;
+  }
+  return qgemm_impl(c, gemm_prec, cfg, A, B, C, alpha, beta, gamma, hip_stream);
+}
+
+int qpinv_x0(qpinv_ctx* c, const qpinv_qmat* A, double alpha, qpinv_qmat* X, void* hip_stream) {
+  return guarded([&]() {
+    ctx_of(c);
+    qp::validate(A, "A");
+    qp::validate(X, "X");
+    if (X->rows != A->cols || X->cols != A->rows) throw qp::Error(QPINV_EINVAL, "x0: X must be n x m");
+    const qp::Mat Am = qp::from_abi(*A), Xm = qp::from_abi(*X);
+    hipStream_t s = stream_of(hip_stream);
+    if (Am.dtype == QPINV_F32 && Xm.dtype == QPINV_F32)
+      qp::x0_scaled_adjoint<float, float>(Am.v, Am.rows, Am.cols, alpha, Xm.v, s);
+    else if (Am.dtype == QPINV_F32)
+      qp::x0_scaled_adjoint<float, double>(Am.v, Am.rows, Am.cols, alpha, Xm.v, s);
+    else if (Xm.dtype == QPINV_F32)
+      qp::x0_scaled_adjoint<double, float>(Am.v, Am.rows, Am.cols, alpha, Xm.v, s);
+    else
+      qp::x0_scaled_adjoint<double, double>(Am.v, Am.rows, Am.cols, alpha, Xm.v, s);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_features(qpinv_ctx* c, const qpinv_qmat* A, int power_steps, double out[6], void* hip_stream) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    if (!out) throw qp::Error(QPINV_EINVAL, "null output");
+    qp::validate(A, "A");
+    if (A->rows == 0 || A->cols == 0) throw qp::Error(QPINV_EINVAL, "features of an empty matrix");
+    qp::features(cx, qp::from_abi(*A), power_steps, out, stream_of(hip_stream));
+    return QPINV_OK;
+  });
+}
+
+int qpinv_autotune(qpinv_ctx* c, int gemm_prec, int64_t M, int64_t N, int64_t K, double* best_ms, void* hip_stream) {
+  int cfg = -1;
+  const int st = guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    prec_check(gemm_prec);
+    cfg = qp::autotune(cx, (qp::Prec)gemm_prec, M, N, K, best_ms, stream_of(hip_stream));
+    return QPINV_OK;
+  });
+  return st == QPINV_OK ? cfg : st;
+}
+
+int qpinv_num_tile_configs(int gemm_prec) {
+  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16) return QPINV_EINVAL;
+  return (int)qp::tile_configs((qp::Prec)gemm_prec).size();
+}
+
+const char* qpinv_tile_config_name(int gemm_prec, int cfg) {
+  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16) return "";
+  const auto& t = qp::tile_configs((qp::Prec)gemm_prec);
+  if (cfg < 0 || cfg >= (int)t.size()) return "";
+  return t[cfg].name;
+}
+
+int qpinv_gemm_stats(qpinv_ctx* c, double out[3]) {
+  return guarded([&]() {
+    if (!out) throw qp::Error(QPINV_EINVAL, "null output");
+    qp::gemm_stats(ctx_of(c), out);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_controller_replay(int stop, double tol, int count, const double* d_abs, const double* x_norm,
+                            const double* e1_rel, int* decision) {
+  if (stop < qp::STOP_DX_ABS || stop > qp::STOP_GUARDED || count < 0 || !d_abs || !x_norm || !decision ||
+      (stop == qp::STOP_E1_REL && !e1_rel) || !(tol >= 0.0)) {
+    g_last_error = "controller_replay: bad argument";
+    return QPINV_EINVAL;
+  }
+  qp::StopController ctl(stop, tol);
+  for (int j = 0; j < count; ++j) {
+    const int d = ctl.update(j + 1, d_abs[j], x_norm[j], e1_rel ? e1_rel[j] : -1.0);
+    decision[j] = d;
+    if (d == qp::D_TOL || d == qp::D_RISE || d == qp::D_DIVERGED) return j + 1;
+  }
+  return count;
+}
+
+}  // extern "C"

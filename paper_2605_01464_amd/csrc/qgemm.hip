@@ -1,0 +1,413 @@
+// Quaternion GEMM kernels for gfx950 (CDNA4): FP32 and FP64 MFMA, with fused epilogues.
+//
+// Work decomposition
+//   * one workgroup computes a BM x BN tile of all four output planes;
+//   * per K-step of BK it stages the four A planes (BM x BK, stored k-major so that a fragment
+//     read is 32/16 consecutive words) and the four B planes (BK x BN) in LDS, prefetching the
+//     next K-step into registers while the MFMAs run on the current one;
+//   * each wave owns a (BM/WM) x (BN/WN) sub-tile as MFMA blocks; for every fragment set it issues
+//     the 16 signed plane products of the Hamilton product (a sign flip of an A fragment is one
+//     VALU op, so the 4x-expanded real representation never exists anywhere);
+//   * the epilogue applies up to three output combinations and optional reductions.
+// Block ids are remapped so that the workgroups resident on one XCD (the hardware deals ids
+// round-robin over the 8 XCDs) take neighbouring tiles, grouped 8 tile-rows at a time, to share
+// that XCD's L2.
+#include <algorithm>
+#include <vector>
+
+#include "qgemm_kern.hpp"
+
+namespace qp {
+
+template <class MM, int BM, int BN, int BK, int WM, int WN>
+struct GemmCfg {
+  using T = typename MM::T;
+  static constexpr int NW = WM * WN, NT = 64 * NW;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int TM = WTM / MM::BLK, TN = WTN / MM::BLK;
+  static constexpr int PADA = (sizeof(T) == 4) ? 4 : 2;
+  static constexpr int PADB = (sizeof(T) == 4) ? 4 : 2;
+  static constexpr int LDA = BM + PADA, LDB = BN + PADB;
+  static constexpr int VA = V16<T>::n;
+  static constexpr int ACH = BM * BK / VA;  // 16-byte chunks per plane of an A tile
+  static constexpr int BCH = BK * BN / VA;
+  static constexpr int NA = (ACH + NT - 1) / NT;
+  static constexpr int NB = (BCH + NT - 1) / NT;
+  static_assert(TM >= 1 && TN >= 1 && WTM % MM::BLK == 0 && WTN % MM::BLK == 0, "wave tile");
+  static_assert(BK % MM::KS == 0 && BK % VA == 0 && BN % VA == 0, "k tile");
+  static constexpr size_t LDS_BYTES = sizeof(T) * 4 * BK * (LDA + LDB);
+  static_assert(LDS_BYTES <= 65536, "LDS budget");
+};
+
+// out_t = a_t v + sum_u b_tu in_u + g_t I for plane p at one element, plus the reduction terms.
+template <class T>
+__device__ __forceinline__ void epilogue_plane(const GemmParams<T>& P, int p, int row, int col, T v, double& s_d,
+                                               double& s_x) {
+  if (row >= P.M || col >= P.N) return;
+  T inv[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) inv[u] = (u < P.nin) ? P.in[u][p * P.psi[u] + (int64_t)row * P.ldi[u] + col] : T(0);
+  const T eye = (p == 0 && row == col) ? T(1) : T(0);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t < P.nout) {
+      const T o = P.ca[t] * v + P.cg[t] * eye + P.cb[t][0] * inv[0] + P.cb[t][1] * inv[1] + P.cb[t][2] * inv[2];
+      P.out[t][p * P.pso[t] + (int64_t)row * P.ldo[t] + col] = o;
+      if (t == 0 && P.partial) {
+        const double od = (double)o;
+        const double ref = P.ref == 0 ? (double)inv[0] : P.ref == 1 ? (double)inv[1] : P.ref == 2 ? (double)inv[2] : 0.0;
+        const double dd = od - ref;
+        s_d += dd * dd;
+        s_x += od * od;
+      }
+    }
+  }
+}
+
+template <class MM, int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename MM::T> P) {
+  using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
+  using T = typename MM::T;
+  using Acc = typename MM::Acc;
+  using VT = typename V16<T>::type;
+  constexpr int VA = C::VA;
+
+  __shared__ T smem[4 * BK * (C::LDA + C::LDB)];
+  T* const As = smem;
+  T* const Bs = smem + 4 * BK * C::LDA;
+  static_assert(C::NW * MM::BLK * MM::BLK <= 4 * BK * (C::LDA + C::LDB), "epilogue staging fits in LDS");
+  __shared__ double red_lds[C::NW][2];
+
+  int tm, tn;
+  tile_of_block(blockIdx.x, P.tiles_m * P.tiles_n, P.tiles_m, P.tiles_n, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wm = w % WM, wn = w / WM;
+
+  Acc acc[4][C::TM][C::TN];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+        for (int r = 0; r < MM::NR; ++r) acc[p][i][j][r] = T(0);
+
+  T ra[4][C::NA][VA];
+  T rb[4][C::NB][VA];
+
+  auto load = [&](int k0) {
+    const bool fullA = P.vec && (m0 + BM <= P.M) && (k0 + BK <= P.K);
+    const bool fullB = P.vec && (n0 + BN <= P.N) && (k0 + BK <= P.K);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T* Aq = P.A + q * P.psa;
+#pragma unroll
+      for (int t = 0; t < C::NA; ++t) {
+        const int c = tid + t * C::NT;
+        const int i = c / (BK / VA), kc = (c % (BK / VA)) * VA;
+        if (C::ACH % C::NT == 0 || c < C::ACH) {
+          const int gi = m0 + i, gk = k0 + kc;
+          if (fullA) {
+            const VT v = *reinterpret_cast<const VT*>(Aq + (int64_t)gi * P.lda + gk);
+            const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+            for (int e = 0; e < VA; ++e) ra[q][t][e] = pv[e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+              ra[q][t][e] = (gi < P.M && gk + e < P.K) ? Aq[(int64_t)gi * P.lda + gk + e] : T(0);
+          }
+        }
+      }
+      const T* Bq = P.B + q * P.psb;
+#pragma unroll
+      for (int t = 0; t < C::NB; ++t) {
+        const int c = tid + t * C::NT;
+        const int k = c / (BN / VA), jc = (c % (BN / VA)) * VA;
+        if (C::BCH % C::NT == 0 || c < C::BCH) {
+          const int gk = k0 + k, gj = n0 + jc;
+          if (fullB) {
+            const VT v = *reinterpret_cast<const VT*>(Bq + (int64_t)gk * P.ldb + gj);
+            const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+            for (int e = 0; e < VA; ++e) rb[q][t][e] = pv[e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e)
+              rb[q][t][e] = (gk < P.K && gj + e < P.N) ? Bq[(int64_t)gk * P.ldb + gj + e] : T(0);
+          }
+        }
+      }
+    }
+  };
+
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int t = 0; t < C::NA; ++t) {
+        const int c = tid + t * C::NT;
+        if (C::ACH % C::NT == 0 || c < C::ACH) {
+          const int i = c / (BK / VA), kc = (c % (BK / VA)) * VA;
+#pragma unroll
+          for (int e = 0; e < VA; ++e) As[(q * BK + kc + e) * C::LDA + i] = ra[q][t][e];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < C::NB; ++t) {
+        const int c = tid + t * C::NT;
+        if (C::BCH % C::NT == 0 || c < C::BCH) {
+          const int k = c / (BN / VA), jc = (c % (BN / VA)) * VA;
+          VT v;
+          T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+          for (int e = 0; e < VA; ++e) pv[e] = rb[q][t][e];
+          *reinterpret_cast<VT*>(&Bs[(q * BK + k) * C::LDB + jc]) = v;
+        }
+      }
+    }
+  };
+
+  const int fr = MM::fr(lane), fk = MM::fk(lane);
+  if (P.K > 0) load(0);
+  for (int k0 = 0; k0 < P.K; k0 += BK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + BK < P.K) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += MM::KS) {
+      T a[C::TM][4], b[C::TN][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int i = 0; i < C::TM; ++i)
+          a[i][q] = As[(q * BK + kk + fk) * C::LDA + wm * C::WTM + i * MM::BLK + fr];
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j)
+          b[j][q] = Bs[(q * BK + kk + fk) * C::LDB + wn * C::WTN + j * MM::BLK + fr];
+      }
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j) {
+          Acc t4[4] = {acc[0][i][j], acc[1][i][j], acc[2][i][j], acc[3][i][j]};
+          quat_mma<MM>(t4, a[i], b[j]);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) acc[p][i][j] = t4[p];
+        }
+    }
+  }
+
+  // ---------------------------------------------------------------- epilogue
+  // Each MFMA block of each plane goes through a per-wave LDS slab, so the accumulators are only
+  // read with compile-time indices and the output pass runs row-contiguous.
+  double s_d = 0.0, s_x = 0.0;
+  T* const slab = smem + w * MM::BLK * MM::BLK;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < MM::NR; ++r) slab[MM::crow(lane, r) * MM::BLK + MM::ccol(lane)] = acc[p][i][j][r];
+        __syncthreads();
+        const int rb = m0 + wm * C::WTM + i * MM::BLK, cb = n0 + wn * C::WTN + j * MM::BLK;
+        for (int e = lane; e < MM::BLK * MM::BLK; e += 64)
+          epilogue_plane(P, p, rb + e / MM::BLK, cb + e % MM::BLK, slab[e], s_d, s_x);
+      }
+  if (P.partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s_d += __shfl_xor(s_d, off, 64);
+      s_x += __shfl_xor(s_x, off, 64);
+    }
+    if (lane == 0) {
+      red_lds[w][0] = s_d;
+      red_lds[w][1] = s_x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a0 = 0.0, a1 = 0.0;
+      for (int q = 0; q < C::NW; ++q) {
+        a0 += red_lds[q][0];
+        a1 += red_lds[q][1];
+      }
+      P.partial[2 * (int64_t)blockIdx.x] = a0;
+      P.partial[2 * (int64_t)blockIdx.x + 1] = a1;
+    }
+  }
+}
+
+// Deterministic sum of `count` (d, x) pairs: one workgroup, fixed strided order, fixed tree.
+__global__ void __launch_bounds__(256) reduce_pairs_kernel(const double* __restrict__ partial, int64_t count,
+                                                           double* __restrict__ red) {
+  __shared__ double s0[256], s1[256];
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) {
+    a0 += partial[2 * i];
+    a1 += partial[2 * i + 1];
+  }
+  s0[threadIdx.x] = a0;
+  s1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    red[0] = s0[0];
+    red[1] = s1[0];
+  }
+}
+
+void reduce_pairs(const double* partial, int64_t count, double* red, hipStream_t stream) {
+  hipLaunchKernelGGL(reduce_pairs_kernel, dim3(1), dim3(256), 0, stream, partial, count, red);
+  QP_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------------------------------------
+// configuration table and dispatch
+// ------------------------------------------------------------------------------------------------
+template <class MM, int BM, int BN, int BK, int WM, int WN>
+static void launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
+  using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
+  GemmParams<typename MM::T> P = P0;
+  P.tiles_m = (P.M + BM - 1) / BM;
+  P.tiles_n = (P.N + BN - 1) / BN;
+  const int nb = P.tiles_m * P.tiles_n;
+  if (nb == 0) return;
+  hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN>), dim3(nb), dim3(C::NT), 0, s, P);
+  QP_HIP(hipGetLastError());
+}
+
+using F32Launch = void (*)(const GemmParams<float>&, hipStream_t);
+using F64Launch = void (*)(const GemmParams<double>&, hipStream_t);
+
+struct F32Entry {
+  TileConfig cfg;
+  F32Launch fn;
+};
+struct F64Entry {
+  TileConfig cfg;
+  F64Launch fn;
+};
+
+static const std::vector<F32Entry>& f32_table() {
+  static const std::vector<F32Entry> t = {
+      {{0, 128, 128, 8, 256, "f32_128x128x8_w2x2_mfma32"}, launch_cfg<MM32F, 128, 128, 8, 2, 2>},
+      {{1, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 64, 16, 2, 2>},
+      {{2, 32, 32, 16, 256, "f32_32x32x16_w2x2_mfma16"}, launch_cfg<MM16F, 32, 32, 16, 2, 2>},
+      {{3, 128, 64, 16, 256, "f32_128x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 128, 64, 16, 2, 2>},
+      {{4, 64, 128, 16, 256, "f32_64x128x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 128, 16, 2, 2>},
+      {{5, 96, 96, 16, 576, "f32_96x96x16_w3x3_mfma32"}, launch_cfg<MM32F, 96, 96, 16, 3, 3>},
+      {{6, 128, 128, 8, 512, "f32_128x128x8_w4x2_mfma32"}, launch_cfg<MM32F, 128, 128, 8, 4, 2>},
+  };
+  return t;
+}
+
+static const std::vector<F64Entry>& f64_table() {
+  static const std::vector<F64Entry> t = {
+      {{0, 64, 64, 8, 256, "f64_64x64x8_w2x2_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 2, 2>},
+      {{1, 32, 32, 16, 256, "f64_32x32x16_w2x2_mfma16"}, launch_cfg<MM16D, 32, 32, 16, 2, 2>},
+      {{2, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 4, 4>},
+  };
+  return t;
+}
+
+const std::vector<TileConfig>& tile_configs(Prec p) {
+  static std::vector<TileConfig> f32, f64;
+  if (f32.empty()) {
+    for (auto& e : f32_table()) f32.push_back(e.cfg);
+    for (auto& e : f64_table()) f64.push_back(e.cfg);
+  }
+  return p == P_F64 ? f64 : f32;
+}
+
+static int64_t blocks_for(const TileConfig& c, int64_t M, int64_t N) {
+  return ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
+}
+
+int64_t qgemm_blocks(Prec p, int cfg, int64_t M, int64_t N) {
+  const auto& t = tile_configs(p);
+  return blocks_for(t.at(cfg), M, N);
+}
+
+int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
+  (void)K;
+  if (p == P_F64) {
+    return blocks_for(tile_configs(p)[0], M, N) >= 256 ? 0 : 1;
+  }
+  const auto& t = tile_configs(p);
+  if (blocks_for(t[0], M, N) >= 512) return 0;
+  if (blocks_for(t[1], M, N) >= 256) return 1;
+  return 2;
+}
+
+template <class T>
+static GemmParams<T> make_params(const QView& A, const QView& B, int64_t M, int64_t N, int64_t K,
+                                 const Epilogue& e, double* partial) {
+  GemmParams<T> P{};
+  P.A = static_cast<const T*>(A.p);
+  P.lda = A.ld;
+  P.psa = A.ps;
+  P.B = static_cast<const T*>(B.p);
+  P.ldb = B.ld;
+  P.psb = B.ps;
+  P.M = (int)M;
+  P.N = (int)N;
+  P.K = (int)K;
+  P.nout = e.nout;
+  P.nin = e.nin;
+  P.ref = e.ref;
+  constexpr int VA = V16<T>::n;
+  auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  P.vec = al(A.p) && al(B.p) && A.ld % VA == 0 && B.ld % VA == 0 && A.ps % VA == 0 && B.ps % VA == 0;
+  for (int t = 0; t < 3; ++t) {
+    P.out[t] = t < e.nout ? static_cast<T*>(e.out[t].p) : nullptr;
+    P.ldo[t] = e.out[t].ld;
+    P.pso[t] = e.out[t].ps;
+    P.in[t] = t < e.nin ? static_cast<const T*>(e.in[t].p) : nullptr;
+    P.ldi[t] = e.in[t].ld;
+    P.psi[t] = e.in[t].ps;
+    P.ca[t] = (T)e.a[t];
+    P.cg[t] = (T)e.g[t];
+    for (int u = 0; u < 3; ++u) P.cb[t][u] = (T)e.b[t][u];
+  }
+  P.partial = e.reduce ? partial : nullptr;
+  return P;
+}
+
+void bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s);  // qgemm_bf16.hip
+int64_t bf16_blocks(int cfg, int64_t M, int64_t N);
+
+void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t K, const Epilogue& epi,
+           double* red, GemmScratch& scratch, hipStream_t stream, int cfg) {
+  if (M < 0 || N < 0 || K < 0) throw Error(-1, "qgemm: negative size");
+  if (epi.nout < 1 || epi.nout > 3 || epi.nin < 0 || epi.nin > 3) throw Error(-1, "qgemm: bad epilogue");
+  if (epi.reduce && (!red || epi.ref >= epi.nin)) throw Error(-1, "qgemm: bad reduction");
+  if (cfg < 0) cfg = default_config(p, M, N, K);
+  const auto& cfgs = tile_configs(p);
+  if (cfg >= (int)cfgs.size()) throw Error(-1, "qgemm: bad tile config");
+  const int64_t nb = p == P_BF16 ? bf16_blocks(cfg, M, N) : blocks_for(cfgs[cfg], M, N);
+  if (epi.reduce && nb > scratch.capacity / 2) throw Error(-1, "qgemm: reduction scratch too small");
+  double* partial = epi.reduce ? scratch.partial : nullptr;
+  if (p == P_F64) {
+    f64_table()[cfg].fn(make_params<double>(A, B, M, N, K, epi, partial), stream);
+  } else if (p == P_F32) {
+    f32_table()[cfg].fn(make_params<float>(A, B, M, N, K, epi, partial), stream);
+  } else {
+    bf16_launch(make_params<float>(A, B, M, N, K, epi, partial), cfg, stream);
+  }
+  if (epi.reduce) reduce_pairs(partial, nb, red, stream);
+}
+
+}  // namespace qp

@@ -1,0 +1,66 @@
+// Quaternion GEMM with a fused multi-output epilogue (host interface).
+//
+// C = A B for quaternion matrices (Hamilton product, Section 2).  In real form the four output
+// planes are [C_s C_x C_y C_z] = [A_s A_x A_y A_z] Rrep(B), where Rrep(B) is the 4x4 block matrix of
+// signed B planes; one quaternion product of shape (M x K)(K x N) is 32 M K N real flops.  The
+// kernels never build Rrep(B): each workgroup stages the four planes of an A tile and a B tile in
+// LDS and issues the 16 signed plane products on MFMA.
+//
+// The epilogue writes up to three outputs of shape M x N, each
+//     out_t = a_t (A B) + sum_u b_tu in_u + g_t I
+// (I = quaternion identity: ones on the diagonal of the real plane), and can reduce
+// sum |out_0 - in_ref|^2 and sum |out_0|^2 (for the change ||X_{j+1} - X_j||_F of an update).
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace qp {
+
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+struct Epilogue {
+  int nout = 1;
+  QView out[3];
+  double a[3] = {1.0, 1.0, 1.0};
+  int nin = 0;
+  QView in[3];
+  double b[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double g[3] = {0.0, 0.0, 0.0};
+  bool reduce = false;
+  int ref = -1;  // input compared with out_0 in the reduction (-1: none)
+};
+
+// Per-stream scratch for the epilogue reduction (per-workgroup partial sums).
+struct GemmScratch {
+  double* partial = nullptr;  // device, capacity doubles
+  int64_t capacity = 0;
+};
+
+struct TileConfig {
+  int id;
+  int bm, bn, bk, threads;
+  const char* name;
+};
+
+// Tile configurations available for a compute precision (F32/BF16 take float storage,
+// F64 takes double storage).
+const std::vector<TileConfig>& tile_configs(Prec p);
+
+// Heuristic choice of tile configuration for a shape (used when no tuned choice exists).
+int default_config(Prec p, int64_t M, int64_t N, int64_t K);
+
+// Launch C = A B with the epilogue.  A is M x K, B is K x N, outputs/inputs M x N.
+// If epi.reduce, `red` (device, 2 doubles) receives {sum |out0 - in_ref|^2, sum |out0|^2}.
+// cfg < 0 selects the default configuration.
+void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t K, const Epilogue& epi,
+           double* red, GemmScratch& scratch, hipStream_t stream, int cfg = -1);
+
+// Number of workgroups a configuration launches for an M x N output (sizes scratch).
+int64_t qgemm_blocks(Prec p, int cfg, int64_t M, int64_t N);
+
+// Sum `count` pairs of partial sums at `partial` into red[0..1] (fixed order, deterministic).
+void reduce_pairs(const double* partial, int64_t count, double* red, hipStream_t stream);
+
+}  // namespace qp

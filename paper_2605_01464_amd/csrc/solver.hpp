@@ -1,0 +1,99 @@
+// Solver driver: context, workspace, method chains and the solve loop.
+#pragma once
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/qpinv.h"
+#include "common.hpp"
+#include "qgemm.hpp"
+
+namespace qp {
+
+// Grow-only named device allocations, freed with the context.
+struct Workspace {
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  void* get(const std::string& key, size_t bytes);
+  void release();
+  ~Workspace() { release(); }
+};
+
+struct Options {
+  int side = QPINV_SIDE_AUTO;
+  int power_steps = 8;
+  uint64_t power_seed = 0x5EED;
+  int autotune = 0;
+  int f64_finish_iters = 2;
+  double mixed_switch = 1e-2;
+  int mixed_rnorm_steps = 6;
+  int max_bf16_iters = 8;
+  int verbose = 0;
+  int gemm_timing = 0;
+};
+
+struct MlpState;  // scaling network (mlp.hip)
+
+struct Ctx {
+  int device = 0;
+  Options opt;
+  Workspace ws;
+  GemmScratch scratch;
+  double* dsc = nullptr;  // device scalars
+  double* hsc = nullptr;  // pinned host scalars
+  std::map<std::tuple<int, int64_t, int64_t, int64_t>, int> tuned;
+  MlpState* mlp = nullptr;
+  double flops = 0.0;  // running count of algorithmic product flops
+  // event pairs around product launches (option gemm_timing)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<double> event_flops;
+  size_t events_used = 0;
+
+  explicit Ctx(int dev);
+  ~Ctx();
+  int config_for(Prec p, int64_t M, int64_t N, int64_t K, hipStream_t s);
+};
+
+// A quaternion matrix with its shape and element type.
+struct Mat {
+  QView v;
+  int64_t rows = 0, cols = 0;
+  int dtype = QPINV_F32;
+};
+
+Mat from_abi(const qpinv_qmat& q);
+void validate(const qpinv_qmat* q, const char* what);
+
+// Workspace matrix of the given shape/type (ld padded to a multiple of 8 elements).
+Mat ws_mat(Ctx& c, const std::string& key, int64_t rows, int64_t cols, int dtype);
+
+// C = A B with epilogue (adds the flops to c.flops; uses tuned/default tile configuration).
+void gemm(Ctx& c, Prec p, const Mat& A, const Mat& B, const Epilogue& e, hipStream_t s, double* red = nullptr);
+
+// One iteration of `method` from Xc into Xn.  A and X share the element type of `p`'s storage.
+// If red != nullptr, red (device, 2 doubles) receives {||Xn - Xc||^2, ||Xn||^2}.
+// If Rout != nullptr it receives a view of R_j = I - (side product) (s x s) for norm estimates.
+void chain(Ctx& c, int method, int order, int side, Prec p, const Mat& A, const Mat& Xc, const Mat& Xn, double* red,
+           hipStream_t s, Mat* Rout = nullptr);
+
+int solve(Ctx& c, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu, double tol,
+          int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info, hipStream_t s);
+
+void residuals(Ctx& c, const qpinv_qmat* A, const qpinv_qmat* X, double E_abs[4], double E_rel[4], hipStream_t s);
+
+void features(Ctx& c, const Mat& A, int steps, double out[6], hipStream_t s);
+
+// {launches, flops, milliseconds} of the timed product launches since the last call (resets).
+void gemm_stats(Ctx& c, double out[3]);
+
+int autotune(Ctx& c, Prec p, int64_t M, int64_t N, int64_t K, double* best_ms, hipStream_t s);
+
+// Normalised method parameters; throws EINVAL on a bad order.
+void check_method(int method, int& order);
+
+}  // namespace qp

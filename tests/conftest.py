@@ -38,3 +38,29 @@ def load_example1():
 @pytest.fixture(scope="session")
 def example1():
     return load_example1()
+
+
+# ------------------------------------------------------------------ GPU helpers (used by -m gpu tests)
+@pytest.fixture(scope="session")
+def qctx():
+    import paper_2605_01464_amd as q
+
+    ctx = q.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def to_dev(A, dtype="f32"):
+    """numpy (4, m, n) float64 -> contiguous device tensor of float32/float64 (the values both sides see)."""
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(A)).to(torch.float32 if dtype == "f32" else torch.float64)
+    return t.cuda()
+
+
+def to_np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def rel_fro(X, Y):
+    return float(np.linalg.norm(X - Y) / max(np.linalg.norm(Y), 1e-300))

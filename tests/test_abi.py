@@ -1,0 +1,104 @@
+"""The C-ABI library loads and exports what include/*.h declares; host-side logic (CPU only)."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qsynth
+from oracle import methods as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2605_01464_amd", "libqpinv.so")
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(qpinv_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("qpinv_init", "qpinv_solve", "qpinv_residuals", "qpinv_finalize", "qpinv_step", "qpinv_qgemm"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_mirrors_abi_names():
+    import paper_2605_01464_amd as q
+
+    for n in declared_functions():
+        assert hasattr(q, n), n
+
+
+def test_strerror_and_bad_arguments_without_gpu():
+    import paper_2605_01464_amd as q
+
+    assert q.qpinv_strerror(0) == "ok"
+    assert q.qpinv_strerror(q.EDIVERGED) == "iteration diverged"
+    assert q.qpinv_num_tile_configs(7) == q.EINVAL
+    assert q.qpinv_num_tile_configs(q.GEMM_PREC["f32"]) >= 3
+    assert q.qpinv_tile_config_name(q.GEMM_PREC["f64"], 0).startswith("f64")
+    used, _ = q.qpinv_controller_replay(9, 1e-6, [1.0], [1.0])
+    assert used == q.EINVAL
+
+
+# ------------------------------------------------------------------ stop-rule controller (host logic)
+def test_controller_dx_abs_and_rel():
+    import paper_2605_01464_amd as q
+
+    d = [1.0, 1e-3, 1e-9, 1e-12]
+    x = [2.0, 2.0, 2.0, 2.0]
+    used, dec = q.qpinv_controller_replay(q.STOP["dx_abs"], 1e-10, d, x)
+    assert used == 4 and dec[-1] == 1
+    used, dec = q.qpinv_controller_replay(q.STOP["dx_rel"], 1e-9, d, x)
+    assert used == 3 and dec[2] == 1  # 1e-9 <= 1e-9 * 2
+
+
+def test_controller_divergence_and_e1():
+    import paper_2605_01464_amd as q
+
+    used, dec = q.qpinv_controller_replay(q.STOP["guarded"], 1e-6, [1.0, float("nan")], [1.0, 1.0])
+    assert used == 2 and dec[1] == 3
+    used, dec = q.qpinv_controller_replay(q.STOP["e1_rel"], 1e-12, [1, 1, 1], [1, 1, 1], [1e-3, 1e-9, 1e-13])
+    assert used == 3 and dec == [0, 0, 1]
+
+
+def test_controller_guarded_rise_matches_scripted_sequence():
+    import paper_2605_01464_amd as q
+
+    # relative changes: fall, reach a floor at update 5, rise at update 6
+    rel = [0.9, 0.7, 0.2, 1e-3, 1e-5, 4e-5, 1e-3]
+    used, dec = q.qpinv_controller_replay(q.STOP["guarded"], 1e-8, rel, [1.0] * len(rel))
+    assert used == 6
+    assert dec[5] == 2
+    assert dec[4] == 4  # update 5 recorded as the minimum
+    # an early wiggle before d fell below half its maximum is not a rise
+    rel = [0.5, 0.6, 0.55, 0.1, 0.01, 0.001]
+    used, dec = q.qpinv_controller_replay(q.STOP["guarded"], 1e-8, rel, [1.0] * len(rel))
+    assert used == len(rel) and 2 not in dec
+
+
+def test_controller_agrees_with_oracle_stop_decision():
+    """Feed the oracle's own per-update scalars (FP64 run on a rounded rank-deficient matrix whose
+    relative change eventually rises) to the library controller: both stop at the same update."""
+    import paper_2605_01464_amd as q
+
+    inst = qsynth.small_spectral_instance(5, 40, 30, qsynth.geometric(20, 1.0, 1e-4))
+    A = qsynth.round_f32(inst["A"])
+    r = M.solve(A, "qhpi19", alpha=M.alpha_sigma(A), tol=1e-14, stop="guarded", side="left", max_iter=60)
+    assert r.reason in ("rise", "tol")
+    used, dec = q.qpinv_controller_replay(q.STOP["guarded"], 1e-14, r.dx, r.xn)
+    assert used == r.iters
+    assert dec[used - 1] == (2 if r.reason == "rise" else 1)

@@ -1,0 +1,137 @@
+"""GPU kernels vs the FP64 oracle: quaternion GEMM (every tile configuration), X_0, features."""
+import numpy as np
+import pytest
+
+from conftest import to_dev, to_np
+from oracle import quat as Q
+from oracle import methods as M
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+SHAPES = [(1, 1, 1), (7, 5, 3), (33, 65, 17), (100, 37, 129), (128, 128, 128), (130, 250, 70), (257, 129, 300)]
+
+
+def gemm_bound(A, B, C0, alpha, beta, gamma, u):
+    """Elementwise rounding bound of fl(alpha A B + beta C0 + gamma I): every component of (A B)_ij is a
+    sum of 4K signed plane products, so |error| <= gamma_{4K+3} (|alpha| S_ij + |beta| |C0| + |gamma|) with
+    S_ij = sum_k (sum_q |A_q,ik|)(sum_r |B_r,kj|)."""
+    K = A.shape[2]
+    n = 4 * K + 3
+    g = n * u / (1 - n * u)
+    S = np.abs(A).sum(axis=0) @ np.abs(B).sum(axis=0)
+    extra = abs(beta) * np.abs(C0) + abs(gamma)
+    return g * (abs(alpha) * S[None] + extra) + 1e-300
+
+
+def rng_planes(seed, m, n, dtype):
+    A = np.random.default_rng(seed).standard_normal((4, m, n))
+    return A.astype(np.float32).astype(np.float64) if dtype == "f32" else A
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_qgemm_every_config_within_rounding_bound(qctx, prec, shape):
+    import paper_2605_01464_amd as q
+
+    M_, N_, K_ = shape
+    A = rng_planes(1, M_, K_, prec)
+    B = rng_planes(2, K_, N_, prec)
+    C0 = rng_planes(3, M_, N_, prec)
+    alpha, beta, gamma = 0.75, -0.5, 2.0
+    ref = alpha * Q.qmul(A, B) + beta * C0
+    ref[0] += gamma * np.eye(M_, N_)
+    u = U32 if prec == "f32" else U64
+    bound = gemm_bound(A, B, C0, alpha, beta, gamma, u)
+    gp = q.GEMM_PREC[prec]
+    for cfg in range(q.qpinv_num_tile_configs(gp)):
+        Ad, Bd = to_dev(A, prec), to_dev(B, prec)
+        Cd = to_dev(C0, prec)
+        q.qgemm(qctx, Ad, Bd, Cd, alpha, beta, gamma, gemm_prec=prec, cfg=cfg)
+        err = np.abs(to_np(Cd) - ref)
+        name = q.qpinv_tile_config_name(gp, cfg)
+        assert np.all(err <= bound), (name, float(err.max()), float((err / bound).max()))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_qgemm_strided_views_and_ragged_ld(qctx, prec):
+    import torch
+    import paper_2605_01464_amd as q
+
+    A = rng_planes(4, 45, 70, prec)
+    B = rng_planes(5, 70, 33, prec)
+    # operands embedded in larger buffers: ld and plane stride differ from cols / rows*cols
+    big = torch.zeros((4, 50, 77), dtype=torch.float32 if prec == "f32" else torch.float64, device="cuda")
+    big[:, :45, :70] = to_dev(A, prec)
+    Av = big[:, :45, :70]
+    Bd = to_dev(B, prec)
+    Cbig = torch.zeros((4, 47, 35), dtype=big.dtype, device="cuda")
+    Cv = Cbig[:, 1:46, 1:34]
+    q.qgemm(qctx, Av, Bd, Cv, gemm_prec=prec)
+    ref = Q.qmul(A, B)
+    bound = gemm_bound(A, B, np.zeros_like(ref), 1.0, 0.0, 0.0, U32 if prec == "f32" else U64)
+    assert np.all(np.abs(to_np(Cv) - ref) <= bound)
+    # the padding around the view is untouched
+    assert float(Cbig[:, 0, :].abs().max()) == 0.0 and float(Cbig[:, :, 0].abs().max()) == 0.0
+
+
+def test_qgemm_empty_and_k_zero(qctx):
+    import torch
+    import paper_2605_01464_amd as q
+
+    A = torch.zeros((4, 5, 0), device="cuda")
+    B = torch.zeros((4, 0, 6), device="cuda")
+    C = torch.full((4, 5, 6), 3.0, device="cuda")
+    q.qgemm(qctx, A, B, C, alpha=1.0, beta=0.5, gamma=1.0)
+    ref = np.full((4, 5, 6), 1.5)
+    ref[0] += np.eye(5, 6)
+    assert np.array_equal(to_np(C), ref)
+
+
+def test_qgemm_bad_arguments(qctx):
+    import torch
+    import paper_2605_01464_amd as q
+
+    A = torch.zeros((4, 5, 4), device="cuda")
+    B = torch.zeros((4, 3, 6), device="cuda")
+    C = torch.zeros((4, 5, 6), device="cuda")
+    assert q.qpinv_qgemm(qctx.handle, q.GEMM_PREC["f32"], A, B, C) == q.EINVAL
+    assert q.qpinv_qgemm(qctx.handle, q.GEMM_PREC["f64"], A, A.transpose(1, 2).contiguous(), C) == q.EINVAL
+
+
+@pytest.mark.parametrize("src,dst", [("f64", "f64"), ("f32", "f32"), ("f32", "f64"), ("f64", "f32")])
+def test_x0_bit_exact(qctx, src, dst):
+    import paper_2605_01464_amd as q
+
+    A = rng_planes(7, 70, 45, src)
+    alpha = 0.0123
+    X = q.x0(qctx, to_dev(A, src), alpha, out_dtype=to_dev(A[:, :1, :1], dst).dtype)
+    ref = M.x0(A, alpha)
+    if dst == "f32":
+        ref = ref.astype(np.float32).astype(np.float64)
+    assert np.array_equal(to_np(X), ref)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (64, 48), (300, 77), (77, 300)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_features_match_oracle(qctx, shape, prec):
+    import paper_2605_01464_amd as q
+
+    A = rng_planes(8, *shape, prec)
+    f = q.features(qctx, to_dev(A, prec), power_steps=6)
+    o = M.features(A, 6)
+    for k in ("fro", "norm1", "norminf"):
+        assert f[k] == pytest.approx(o[k], rel=1e-12)
+    assert f["sigma1_sq"] == pytest.approx(o["sigma1_sq"], rel=1e-10)
+    assert (f["m"], f["n"]) == shape
+
+
+def test_features_reject_nonfinite(qctx):
+    import paper_2605_01464_amd as q
+
+    A = rng_planes(9, 20, 10, "f64")
+    A[2, 3, 4] = np.nan
+    st, _ = q.qpinv_features(qctx.handle, to_dev(A, "f64"))
+    assert st == q.ENONFINITE

@@ -1,0 +1,160 @@
+"""One iteration and full solves on the GPU vs the FP64 oracle (same inputs, same alpha, same side)."""
+import numpy as np
+import pytest
+
+import qsynth
+from conftest import rel_fro, to_dev, to_np
+from oracle import quat as Q
+from oracle import methods as M
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("ns", None), ("hpi", 5), ("qsai", None), ("qhpi19", None), ("qrapid", 0), ("qrapid", 2), ("qrapid", 5)]
+
+
+def _order(method, order):
+    return {"ns": 2, "qsai": 10, "qhpi19": 19, "qrapid": 5}.get(method) if order is None else order
+
+
+@pytest.mark.parametrize("method,order", CASES)
+@pytest.mark.parametrize("side", ["left", "right"])
+@pytest.mark.parametrize("shape", [(70, 45), (45, 70), (64, 64)])
+def test_one_step_fp64(qctx, method, order, side, shape):
+    import paper_2605_01464_amd as q
+
+    A = np.random.default_rng(11).standard_normal((4,) + shape)
+    X0 = M.x0(A, 0.9 * M.alpha_sigma(A))
+    X1 = M.step(A, X0, method, _order(method, order), side)
+    Xd, dx = q.step(qctx, to_dev(A, "f64"), to_dev(X0, "f64"), method, _order(method, order), side=side)
+    assert rel_fro(to_np(Xd), X1) <= 1e-12
+    assert dx[0] == pytest.approx(Q.fro(X1 - X0) ** 2, rel=1e-9)
+    assert dx[1] == pytest.approx(Q.fro(X1) ** 2, rel=1e-12)
+
+
+@pytest.mark.parametrize("method,order", CASES)
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_one_step_fp32(qctx, method, order, side):
+    import paper_2605_01464_amd as q
+
+    A = qsynth.round_f32(np.random.default_rng(12).standard_normal((4, 150, 97)))
+    X0 = qsynth.round_f32(M.x0(A, 0.9 * M.alpha_sigma(A)))
+    X1 = M.step(A, X0, method, _order(method, order), side)
+    Xd, _ = q.step(qctx, to_dev(A, "f32"), to_dev(X0, "f32"), method, _order(method, order), side=side)
+    # up to 8 + 2N chained FP32 products of well-scaled operands
+    assert rel_fro(to_np(Xd), X1) <= 2e-5
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_residual_law_on_gpu_iterate(qctx, side):
+    """I - A X_{j+1} = (I - A X_j)^19 holds for the GPU's QHPI19 iterate from a generic X_j (FP64)."""
+    import paper_2605_01464_amd as q
+
+    A = np.random.default_rng(13).standard_normal((4, 40, 30))
+    X = Q.pinv_svd(A) + 0.01 / Q.fro(A) * np.random.default_rng(14).standard_normal((4, 30, 40))
+    Xd, _ = q.step(qctx, to_dev(A, "f64"), to_dev(X, "f64"), "qhpi19", side=side)
+    I = Q.qeye(40)
+    R = I - Q.qmul(A, X)
+    R19 = I.copy()
+    for _ in range(19):
+        R19 = Q.qmul(R19, R)
+    Rn = I - Q.qmul(A, to_np(Xd))
+    assert Q.fro(Rn - R19) <= 1e-11
+
+
+def test_residuals_match_oracle(qctx):
+    import paper_2605_01464_amd as q
+
+    A = np.random.default_rng(15).standard_normal((4, 50, 35))
+    X = Q.pinv_svd(A) + 1e-3 * np.random.default_rng(16).standard_normal((4, 35, 50))
+    Ea, Er = q.residuals(qctx, to_dev(A, "f64"), to_dev(X, "f64"))
+    o = M.residuals(A, X)
+    np.testing.assert_allclose(Ea, o["E"], rtol=1e-9)
+    np.testing.assert_allclose(Er, o["E_rel"], rtol=1e-9)
+    # FP32 inputs are widened exactly
+    Ea32, _ = q.residuals(qctx, to_dev(A, "f32"), to_dev(X, "f32"))
+    o32 = M.residuals(qsynth.round_f32(A), qsynth.round_f32(X))
+    np.testing.assert_allclose(Ea32, o32["E"], rtol=1e-9)
+
+
+# ------------------------------------------------------------------ small workload: 64 x 48, FP64
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("method,order", [("ns", None), ("qsai", None), ("qhpi19", None), ("qrapid", 5)])
+def test_small_workload_fp64(qctx, seed, method, order):
+    import paper_2605_01464_amd as q
+
+    A = qsynth.c1_instance(seed)
+    alpha = M.alpha_sigma(A)
+    ro = M.solve(A, method, _order(method, order), alpha=alpha, tol=1e-12, stop="e1_rel", side="left")
+    X, info = q.solve(qctx, to_dev(A, "f64"), method, _order(method, order), scaling="given", alpha=alpha,
+                      tol=1e-12, stop="e1_rel", precision="f64")
+    assert info["status"] == q.OK and info["reason"] == "tol"
+    assert info["side"] == q.SIDE["left"]
+    assert info["iters"] == ro.iters
+    Xg = to_np(X)
+    assert rel_fro(Xg, ro.X) <= 1e-12
+    assert rel_fro(Xg, Q.pinv_full_column_rank(A)) <= 1e-10
+    Ea, Er = q.residuals(qctx, to_dev(A, "f64"), X)
+    assert Er[0] <= 1e-12 and max(Er) <= 1e-12
+
+
+def test_small_workload_power_alpha(qctx):
+    import paper_2605_01464_amd as q
+
+    A = qsynth.c1_instance(3)
+    f = M.features(A, 8)
+    ro = M.solve(A, "qhpi19", alpha=1.0 / f["sigma1_sq"], tol=1e-12, stop="e1_rel", side="left")
+    X, info = q.solve(qctx, to_dev(A, "f64"), "qhpi19", scaling="power", tol=1e-12, stop="e1_rel", precision="f64")
+    assert info["alpha_used"] == pytest.approx(1.0 / f["sigma1_sq"], rel=1e-12)
+    assert info["iters"] == ro.iters
+    assert rel_fro(to_np(X), ro.X) <= 1e-12
+
+
+def test_worked_example_on_gpu(qctx, example1):
+    """Section 4, Example 1 through the GPU path: printed pseudoinverse and iteration counts."""
+    import paper_2605_01464_amd as q
+
+    A, P, _, iters = example1
+    alpha = M.alpha_sigma(A)
+    qctx.set("side", q.SIDE["right"])
+    try:
+        for method, order in [("qsai", 10), ("qhpi19", 19), ("qrapid", 2)]:
+            X, info = q.solve(qctx, to_dev(A, "f64"), method, order, scaling="given", alpha=alpha, tol=1e-10,
+                              stop="dx_abs", precision="f64")
+            assert info["iters"] == iters[method]
+            assert np.max(np.abs(to_np(X) - P)) <= 5e-5 + 1e-9
+    finally:
+        qctx.set("side", q.SIDE["auto"])
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_paths(qctx):
+    import torch
+    import paper_2605_01464_amd as q
+
+    A = np.random.default_rng(17).standard_normal((4, 30, 20))
+    Ad = to_dev(A, "f64")
+    s1 = Q.singular_values(A)[0]
+    # alpha outside (0, 2/sigma_1^2): Theorem 1 -> divergence
+    _, info = q.solve(qctx, Ad, "qhpi19", scaling="given", alpha=2.5 / s1 ** 2, tol=1e-12, stop="dx_rel",
+                      precision="f64", check=False)
+    assert info["status"] == q.EDIVERGED
+    # max_iter exhausted
+    _, info = q.solve(qctx, Ad, "ns", scaling="given", alpha=1.0 / s1 ** 2, tol=0.0, max_iter=2, stop="dx_rel",
+                      precision="f64", check=False)
+    assert info["status"] == q.ENOTCONVERGED and info["iters"] == 2
+    # non-finite input
+    Abad = A.copy()
+    Abad[1, 4, 5] = np.inf
+    _, info = q.solve(qctx, to_dev(Abad, "f64"), "qhpi19", precision="f64", check=False)
+    assert info["status"] == q.ENONFINITE
+    # bad order / shape
+    X = torch.empty((4, 20, 30), dtype=torch.float64, device="cuda")
+    st, _ = q.qpinv_solve(qctx.handle, q.METHOD["qsai"], 7, Ad, 0, 0.0, 1e-6, 10, 3, 0, X)
+    assert st == q.EINVAL
+    Xbad = torch.empty((4, 30, 20), dtype=torch.float64, device="cuda")
+    st, _ = q.qpinv_solve(qctx.handle, q.METHOD["qhpi19"], 19, Ad, 0, 0.0, 1e-6, 10, 3, 0, Xbad)
+    assert st == q.EINVAL
+    # zero matrix: pseudoinverse is zero
+    Z = torch.zeros((4, 6, 4), dtype=torch.float64, device="cuda")
+    Xz, info = q.solve(qctx, Z, "qhpi19", precision="f64")
+    assert float(Xz.abs().max()) == 0.0
