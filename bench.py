@@ -55,6 +55,7 @@ def main() -> int:
     ap.add_argument("--method", default="qhpi19", choices=["ns", "qsai", "qhpi19", "qrapid"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gemm", action="store_true", help="skip the standalone square-product measurement")
+    ap.add_argument("--no-autotune", action="store_true", help="use the heuristic tile choice instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -76,9 +77,11 @@ def main() -> int:
     order = {"ns": 2, "qsai": 10, "qhpi19": 19, "qrapid": 5}[args.method]
 
     ctx = q.Context(0)
+    if not args.no_autotune:
+        ctx.set("autotune", 1)  # tile configurations are timed on the solve's own shapes during warm-up
     solve_kw = dict(method=args.method, order=order, scaling="power", tol=1e-6, max_iter=100, stop="guarded",
                     precision="f32", X=X)
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1 if not args.no_autotune else 0)):
         q.solve(ctx, A, **solve_kw)
     torch.cuda.synchronize()
     ctx.set("gemm_timing", 1)
@@ -91,11 +94,15 @@ def main() -> int:
         infos.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    st, (launches, gflops, gms) = q.qpinv_gemm_stats(ctx.handle)
+    _, rows = q.qpinv_gemm_stats(ctx.handle)
     ctx.set("gemm_timing", 0)
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps / elapsed
-    achieved = gflops / (gms * 1e-3) / 1e12 if gms > 0 else 0.0
+    # dominant kernel: the (precision, tile configuration) with the most product time
+    dom = max(rows, key=lambda r: r["ms"])
+    prec_name = {0: "f64", 1: "f32", 2: "bf16"}[dom["prec"]]
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    gemm_ms = sum(r["ms"] for r in rows)
     info = infos[-1]
 
     out = {
@@ -114,15 +121,19 @@ def main() -> int:
         "config": {"workload": f"rank-1024 quaternion pseudoinverse 2048x1536 (s geometric 1..1e-4, FP32 input), "
                                f"{args.method.upper()} FP32, power-iteration alpha, guarded stop tol 1e-6",
                    "m": m, "n": n, "rank": 1024, "method": args.method, "precision": "f32"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f32"], "traffic": None,
-                     "kernel": "qgemm_kernel (FP32 MFMA, every quaternion product of the solve)",
-                     "launches_per_step": launches / args.steps,
-                     "flops_per_launch": gflops / max(launches, 1),
-                     "avg_launch_ms": gms / max(launches, 1)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK[prec_name], "traffic": None,
+                     "kernel": f"qgemm_kernel {q.qpinv_tile_config_name(dom['prec'], dom['cfg'])}",
+                     "launches_per_step": dom["launches"] / args.steps,
+                     "flops_per_launch": dom["flops"] / max(dom["launches"], 1),
+                     "avg_launch_ms": dom["ms"] / max(dom["launches"], 1),
+                     "all_kernels": [{"kernel": q.qpinv_tile_config_name(r["prec"], r["cfg"]),
+                                      "launches_per_step": r["launches"] / args.steps,
+                                      "avg_launch_ms": r["ms"] / r["launches"],
+                                      "tflops": r["flops"] / (r["ms"] * 1e-3) / 1e12} for r in rows]},
         "solve": {"iters": info["iters"], "returned": info["returned"], "reason": info["reason"],
                   "side": info["side"], "alpha": info["alpha_used"], "gemm_flops": info["gemm_flops"],
-                  "gemm_ms_share": (gms / args.steps) / ms_per_step},
+                  "gemm_ms_share": (gemm_ms / args.steps) / ms_per_step},
         "input_generation_s": t_gen,
     }
 

@@ -77,7 +77,10 @@ typedef enum {
   QPINV_STOP_E1_REL = 2, /* ||A X_{j+1} A - A||_F <= tol ||A||_F (two extra products per iteration) */
   QPINV_STOP_GUARDED = 3 /* relative change <= tol, or the first rise of the relative change after it
                             dropped below half its running maximum; then the better (smaller
-                            ||XAX - X||_F / ||X||_F, FP64) of the two iterates around the minimum */
+                            ||XAX - X||_F / ||X||_F) of the two iterates around the minimum.  That
+                            Penrose residual is formed from the residuals the iteration already
+                            computed (in the solve's precision) when the minimum is the last update,
+                            otherwise from scratch in FP64. */
 } qpinv_stop;
 
 typedef enum {
@@ -201,10 +204,12 @@ int qpinv_qgemm_cfg(qpinv_ctx* ctx, int gemm_prec, int cfg, const qpinv_qmat* A,
                     qpinv_qmat* C, double alpha, double beta, double gamma, void* hip_stream);
 
 /* Product launch statistics.  With option gemm_timing = 1 every quaternion product this context
- * launches is bracketed by HIP events on its stream.  out (host, 3 doubles) receives
- * {launches, algorithmic flops (32 M N K each), summed event milliseconds} since the previous call;
- * the call waits for those events and resets the counters.  Errors: EINVAL, EHIP. */
-int qpinv_gemm_stats(qpinv_ctx* ctx, double out[3]);
+ * launches is bracketed by HIP events on its stream.  For each kernel used since the previous call
+ * (product precision x tile configuration) one row of 5 doubles is written to `out` (host):
+ * {gemm_prec, tile configuration, launches, algorithmic flops (32 M N K each), summed event ms}.
+ * At most max_rows rows; returns the number of rows (>= 0) or an error (EINVAL, EHIP).  The call
+ * waits for the recorded events and resets the counters. */
+int qpinv_gemm_stats(qpinv_ctx* ctx, double* out, int max_rows);
 
 /* Stop-rule controller replay (host only, no GPU use): feed per-update scalars
  * d_abs[j] = ||X_{j+1}-X_j||_F, x_norm[j] = ||X_{j+1}||_F, e1_rel[j] (may be NULL unless

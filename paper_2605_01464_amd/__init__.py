@@ -84,7 +84,7 @@ def _load() -> ctypes.CDLL:
         "qpinv_num_tile_configs": (I, [I]),
         "qpinv_tile_config_name": (ctypes.c_char_p, [I, I]),
         "qpinv_controller_replay": (I, [I, D, I, DP, DP, DP, ctypes.POINTER(ctypes.c_int)]),
-        "qpinv_gemm_stats": (I, [P, DP]),
+        "qpinv_gemm_stats": (I, [P, DP, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -211,10 +211,15 @@ def qpinv_tile_config_name(gemm_prec, cfg) -> str:
     return _lib.qpinv_tile_config_name(gemm_prec, cfg).decode()
 
 
-def qpinv_gemm_stats(ctx):
-    out = (ctypes.c_double * 3)()
-    st = _lib.qpinv_gemm_stats(ctx, out)
-    return st, (int(out[0]), out[1], out[2])
+def qpinv_gemm_stats(ctx, max_rows=32):
+    """Rows {gemm_prec, cfg, launches, flops, ms} per kernel since the last call (status < 0 on error)."""
+    out = (ctypes.c_double * (5 * max_rows))()
+    n = _lib.qpinv_gemm_stats(ctx, out, max_rows)
+    if n < 0:
+        return n, []
+    rows = [dict(prec=int(out[5 * i]), cfg=int(out[5 * i + 1]), launches=int(out[5 * i + 2]),
+                 flops=out[5 * i + 3], ms=out[5 * i + 4]) for i in range(n)]
+    return OK, rows
 
 
 def qpinv_controller_replay(stop, tol, d_abs, x_norm, e1_rel=None):

@@ -315,12 +315,14 @@ const char* qpinv_tile_config_name(int gemm_prec, int cfg) {
   return t[cfg].name;
 }
 
-int qpinv_gemm_stats(qpinv_ctx* c, double out[3]) {
-  return guarded([&]() {
-    if (!out) throw qp::Error(QPINV_EINVAL, "null output");
-    qp::gemm_stats(ctx_of(c), out);
+int qpinv_gemm_stats(qpinv_ctx* c, double* out, int max_rows) {
+  int rows = 0;
+  const int st = guarded([&]() {
+    if (!out || max_rows < 1) throw qp::Error(QPINV_EINVAL, "null output or max_rows < 1");
+    rows = qp::gemm_stats(ctx_of(c), out, max_rows);
     return QPINV_OK;
   });
+  return st == QPINV_OK ? rows : st;
 }
 
 int qpinv_controller_replay(int stop, double tol, int count, const double* d_abs, const double* x_norm,

@@ -64,9 +64,10 @@ __device__ __forceinline__ void epilogue_plane(const GemmParams<T>& P, int p, in
   }
 }
 
-template <class MM, int BM, int BN, int BK, int WM, int WN>
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH>
 __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename MM::T> P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
+  static_assert(FLUSH == 0 || FLUSH % BK == 0, "flush interval is a whole number of K tiles");
   using T = typename MM::T;
   using Acc = typename MM::Acc;
   using VT = typename V16<T>::type;
@@ -94,6 +95,36 @@ __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename
       for (int j = 0; j < C::TN; ++j)
 #pragma unroll
         for (int r = 0; r < MM::NR; ++r) acc[p][i][j][r] = T(0);
+
+  // Two-level accumulation: the MFMA accumulators cover FLUSH consecutive k and are then added into
+  // `tot`, so no FP32 rounding chain is longer than FLUSH/KS + K/FLUSH additions.
+  constexpr int TT = FLUSH > 0 ? 4 : 1;  // a 1-element placeholder when the flush is off
+  Acc tot[TT][FLUSH > 0 ? C::TM : 1][FLUSH > 0 ? C::TN : 1];
+  if constexpr (FLUSH > 0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+          for (int r = 0; r < MM::NR; ++r) tot[p][i][j][r] = T(0);
+  }
+  auto flush = [&]() {
+    if constexpr (FLUSH > 0) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+            for (int r = 0; r < MM::NR; ++r) {
+              tot[p][i][j][r] += acc[p][i][j][r];
+              acc[p][i][j][r] = T(0);
+            }
+    }
+  };
 
   T ra[4][C::NA][VA];
   T rb[4][C::NB][VA];
@@ -200,7 +231,11 @@ __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename
           for (int p = 0; p < 4; ++p) acc[p][i][j] = t4[p];
         }
     }
+    if constexpr (FLUSH > 0) {
+      if ((k0 + BK) % FLUSH == 0) flush();
+    }
   }
+  flush();
 
   // ---------------------------------------------------------------- epilogue
   // Each MFMA block of each plane goes through a per-wave LDS slab, so the accumulators are only
@@ -215,7 +250,14 @@ __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename
       for (int p = 0; p < 4; ++p) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < MM::NR; ++r) slab[MM::crow(lane, r) * MM::BLK + MM::ccol(lane)] = acc[p][i][j][r];
+        for (int r = 0; r < MM::NR; ++r) {
+          T v;
+          if constexpr (FLUSH > 0)
+            v = tot[p][i][j][r];
+          else
+            v = acc[p][i][j][r];
+          slab[MM::crow(lane, r) * MM::BLK + MM::ccol(lane)] = v;
+        }
         __syncthreads();
         const int rb = m0 + wm * C::WTM + i * MM::BLK, cb = n0 + wn * C::WTN + j * MM::BLK;
         for (int e = lane; e < MM::BLK * MM::BLK; e += 64)
@@ -277,7 +319,7 @@ void reduce_pairs(const double* partial, int64_t count, double* red, hipStream_t
 // ------------------------------------------------------------------------------------------------
 // configuration table and dispatch
 // ------------------------------------------------------------------------------------------------
-template <class MM, int BM, int BN, int BK, int WM, int WN>
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH>
 static void launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   GemmParams<typename MM::T> P = P0;
@@ -285,7 +327,7 @@ static void launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
   P.tiles_n = (P.N + BN - 1) / BN;
   const int nb = P.tiles_m * P.tiles_n;
   if (nb == 0) return;
-  hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN>), dim3(nb), dim3(C::NT), 0, s, P);
+  hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH>), dim3(nb), dim3(C::NT), 0, s, P);
   QP_HIP(hipGetLastError());
 }
 
@@ -301,24 +343,23 @@ struct F64Entry {
   F64Launch fn;
 };
 
+// FP32 configurations accumulate in two levels (flush every 128 k); FP64 needs no flush.
 static const std::vector<F32Entry>& f32_table() {
   static const std::vector<F32Entry> t = {
-      {{0, 128, 128, 8, 256, "f32_128x128x8_w2x2_mfma32"}, launch_cfg<MM32F, 128, 128, 8, 2, 2>},
-      {{1, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 64, 16, 2, 2>},
-      {{2, 32, 32, 16, 256, "f32_32x32x16_w2x2_mfma16"}, launch_cfg<MM16F, 32, 32, 16, 2, 2>},
-      {{3, 128, 64, 16, 256, "f32_128x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 128, 64, 16, 2, 2>},
-      {{4, 64, 128, 16, 256, "f32_64x128x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 128, 16, 2, 2>},
-      {{5, 96, 96, 16, 576, "f32_96x96x16_w3x3_mfma32"}, launch_cfg<MM32F, 96, 96, 16, 3, 3>},
-      {{6, 128, 128, 8, 512, "f32_128x128x8_w4x2_mfma32"}, launch_cfg<MM32F, 128, 128, 8, 4, 2>},
+      {{0, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 64, 16, 2, 2, 128>},
+      {{1, 32, 32, 16, 256, "f32_32x32x16_w2x2_mfma16"}, launch_cfg<MM16F, 32, 32, 16, 2, 2, 128>},
+      {{2, 128, 64, 16, 256, "f32_128x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 128, 64, 16, 2, 2, 128>},
+      {{3, 64, 128, 16, 256, "f32_64x128x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 128, 16, 2, 2, 128>},
+      {{4, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma16"}, launch_cfg<MM16F, 64, 64, 16, 2, 2, 128>},
   };
   return t;
 }
 
 static const std::vector<F64Entry>& f64_table() {
   static const std::vector<F64Entry> t = {
-      {{0, 64, 64, 8, 256, "f64_64x64x8_w2x2_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 2, 2>},
-      {{1, 32, 32, 16, 256, "f64_32x32x16_w2x2_mfma16"}, launch_cfg<MM16D, 32, 32, 16, 2, 2>},
-      {{2, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 4, 4>},
+      {{0, 64, 64, 8, 256, "f64_64x64x8_w2x2_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 2, 2, 0>},
+      {{1, 32, 32, 16, 256, "f64_32x32x16_w2x2_mfma16"}, launch_cfg<MM16D, 32, 32, 16, 2, 2, 0>},
+      {{2, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 4, 4, 0>},
   };
   return t;
 }
@@ -347,9 +388,7 @@ int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
     return blocks_for(tile_configs(p)[0], M, N) >= 256 ? 0 : 1;
   }
   const auto& t = tile_configs(p);
-  if (blocks_for(t[0], M, N) >= 512) return 0;
-  if (blocks_for(t[1], M, N) >= 256) return 1;
-  return 2;
+  return blocks_for(t[0], M, N) >= 512 ? 0 : 1;
 }
 
 template <class T>

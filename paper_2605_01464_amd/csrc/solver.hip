@@ -5,6 +5,7 @@
 // X p(A X) = p(X A) X (true for every polynomial p) gives the same iterate from R'_j = I_n - X_j A
 // (n x n).  Side LEFT uses I_n - X A and X_{j+1} = p(R') X; side RIGHT uses I_m - A X and
 // X_{j+1} = X p(R).  AUTO takes the smaller of m and n, which is where all the s^3 products live.
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -160,28 +161,41 @@ void gemm(Ctx& c, Prec p, const Mat& A, const Mat& B, const Epilogue& e, hipStre
     QP_HIP(hipEventCreate(&b));
     c.events.emplace_back(a, b);
     c.event_flops.push_back(0.0);
+    c.event_key.push_back(0);
   }
   auto& ev = c.events[c.events_used];
   c.event_flops[c.events_used] = f;
+  c.event_key[c.events_used] = (int)p * 64 + cfg;
   ++c.events_used;
   QP_HIP(hipEventRecord(ev.first, s));
   qgemm(p, A.v, B.v, M, N, K, e, red, c.scratch, s, cfg);
   QP_HIP(hipEventRecord(ev.second, s));
 }
 
-void gemm_stats(Ctx& c, double out[3]) {
-  double ms = 0.0, fl = 0.0;
+int gemm_stats(Ctx& c, double* out, int max_rows) {
+  std::map<int, std::array<double, 3>> agg;  // key -> launches, flops, ms
   for (size_t i = 0; i < c.events_used; ++i) {
     QP_HIP(hipEventSynchronize(c.events[i].second));
     float t = 0.f;
     QP_HIP(hipEventElapsedTime(&t, c.events[i].first, c.events[i].second));
-    ms += t;
-    fl += c.event_flops[i];
+    auto& a = agg[c.event_key[i]];
+    a[0] += 1.0;
+    a[1] += c.event_flops[i];
+    a[2] += t;
   }
-  out[0] = (double)c.events_used;
-  out[1] = fl;
-  out[2] = ms;
   c.events_used = 0;
+  int rows = 0;
+  for (auto& kv : agg) {
+    if (rows >= max_rows) break;
+    double* r = out + 5 * rows;
+    r[0] = kv.first / 64;
+    r[1] = kv.first % 64;
+    r[2] = kv.second[0];
+    r[3] = kv.second[1];
+    r[4] = kv.second[2];
+    ++rows;
+  }
+  return rows;
 }
 
 void check_method(int method, int& order) {
@@ -556,6 +570,20 @@ double e2_sq(Ctx& c, const Mat& A64, const Mat& X64, hipStream_t s) {
   return c.hsc[0];
 }
 
+// ||X A X - X||_F^2 from the residual of X: R = I - X A (left, n x n) gives X A X - X = -R X,
+// R = I - A X (right, m x m) gives -X R.  Computed in the precision p of the stored R and X.
+double e2_sq_from_residual(Ctx& c, Prec p, int side, const Mat& R, const Mat& X, hipStream_t s) {
+  Mat O = ws_mat(c, "e2r_out", X.rows, X.cols, X.dtype);
+  Epilogue e = epi1(O);
+  e.reduce = true;
+  if (side == QPINV_SIDE_LEFT)
+    gemm(c, p, R, X, e, s, c.dsc + 28);
+  else
+    gemm(c, p, X, R, e, s, c.dsc + 28);
+  to_host(c, c.dsc + 28, 2, s);
+  return c.hsc[0];
+}
+
 // ||A X A - A||_F^2 in the precision p (A and X of p's storage)
 double e1_sq(Ctx& c, Prec p, const Mat& A, const Mat& X, hipStream_t s) {
   const int64_t m = A.rows, n = A.cols;
@@ -707,6 +735,8 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
   int j = 0;
   double d_prev_finish = -1.0;
 
+  Mat rsave[2];
+  int rsave_j[2] = {-1, -1};  // index k of the iterate X_k whose residual R_k sits in each slot
   auto pick_free = [&](int a, int b, int cc) {
     for (int i = 0; i < 4; ++i)
       if (i != a && i != b && i != cc) return i;
@@ -725,8 +755,17 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     const int nxt = pick_free(best_pair[0], best_pair[1], cur);
     const Mat Adt = A_of(store_of(p));
     Mat R;
-    const bool want_R = (p == P_BF16);
+    const bool main_phase = p != P_BF16 && !(has_finish && ph == phases.size() - 1);
+    const bool keep_R = main_phase && stop == STOP_GUARDED;
+    const bool want_R = (p == P_BF16) || keep_R;
     chain(c, method, order, side, p, Adt, S->b[cur], S->b[nxt], red, s, want_R ? &R : nullptr);
+    if (keep_R) {
+      // keep R_{j} = residual of the iterate X_j this update started from (slot j % 2)
+      const int slot = j % 2;
+      rsave[slot] = ws_mat(c, "Rsave" + std::to_string(slot), R.rows, R.cols, R.dtype);
+      QP_HIP(hipMemcpyAsync(rsave[slot].v.p, R.v.p, 4 * R.v.ps * esize(R.dtype), hipMemcpyDeviceToDevice, s));
+      rsave_j[slot] = j;
+    }
     double rnorm = -1.0;
     if (want_R) rnorm = std::sqrt(std::max(0.0, power_host(c, R, c.opt.mixed_rnorm_steps, s)));
     to_host(c, red, 2, s);
@@ -823,12 +862,22 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     } else if (dec == D_RISE) {
       // choose between X_{j*-1} and X_{j*} by ||XAX - X||_F / ||X||_F in FP64
       reason = QPINV_REASON_RISE;
-      const Mat A64 = A_of(QPINV_F64);
-      Mat Xa64 = ws_mat(c, "cand", n, m, QPINV_F64);
-      convert_mat(S->b[best_pair[0]], Xa64, s);
-      const double ea = std::sqrt(e2_sq(c, A64, Xa64, s)) / std::max(xnorm_hist[best_j - 1], 1e-300);
-      convert_mat(S->b[best_pair[1]], Xa64, s);
-      const double eb = std::sqrt(e2_sq(c, A64, Xa64, s)) / std::max(xnorm_hist[best_j], 1e-300);
+      double ea, eb;
+      const int ka = best_j - 1, kb = best_j;
+      if (rsave_j[ka % 2] == ka && rsave_j[kb % 2] == kb) {
+        // X A X - X = -R X (left) or -X R (right) with the residuals the chain already formed
+        ea = std::sqrt(e2_sq_from_residual(c, p, side, rsave[ka % 2], S->b[best_pair[0]], s)) /
+             std::max(xnorm_hist[ka], 1e-300);
+        eb = std::sqrt(e2_sq_from_residual(c, p, side, rsave[kb % 2], S->b[best_pair[1]], s)) /
+             std::max(xnorm_hist[kb], 1e-300);
+      } else {
+        const Mat A64 = A_of(QPINV_F64);
+        Mat Xa64 = ws_mat(c, "cand", n, m, QPINV_F64);
+        convert_mat(S->b[best_pair[0]], Xa64, s);
+        ea = std::sqrt(e2_sq(c, A64, Xa64, s)) / std::max(xnorm_hist[ka], 1e-300);
+        convert_mat(S->b[best_pair[1]], Xa64, s);
+        eb = std::sqrt(e2_sq(c, A64, Xa64, s)) / std::max(xnorm_hist[kb], 1e-300);
+      }
       if (best_j - 1 >= 1 && ea < eb) {
         chosen_buf = best_pair[0];
         chosen_j = best_j - 1;

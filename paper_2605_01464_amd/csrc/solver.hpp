@@ -52,6 +52,7 @@ struct Ctx {
   // event pairs around product launches (option gemm_timing)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   std::vector<double> event_flops;
+  std::vector<int> event_key;  // prec * 64 + tile configuration
   size_t events_used = 0;
 
   explicit Ctx(int dev);
@@ -88,8 +89,9 @@ void residuals(Ctx& c, const qpinv_qmat* A, const qpinv_qmat* X, double E_abs[4]
 
 void features(Ctx& c, const Mat& A, int steps, double out[6], hipStream_t s);
 
-// {launches, flops, milliseconds} of the timed product launches since the last call (resets).
-void gemm_stats(Ctx& c, double out[3]);
+// Per kernel (precision, tile configuration): rows of {prec, cfg, launches, flops, milliseconds} of the
+// timed product launches since the last call; returns the row count (at most max_rows) and resets.
+int gemm_stats(Ctx& c, double* out, int max_rows);
 
 int autotune(Ctx& c, Prec p, int64_t M, int64_t N, int64_t K, double* best_ms, hipStream_t s);
 

@@ -135,3 +135,23 @@ def test_features_reject_nonfinite(qctx):
     A[2, 3, 4] = np.nan
     st, _ = q.qpinv_features(qctx.handle, to_dev(A, "f64"))
     assert st == q.ENONFINITE
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_qgemm_square_relative_error_le_1e6(qctx, n):
+    """Square FP32 quaternion product: relative Frobenius error vs the FP64 product of the same FP32
+    inputs, on 24 sampled rows (the oracle computes those rows exactly), must be <= 1e-6."""
+    import torch
+    import paper_2605_01464_amd as q
+
+    g = torch.Generator(device="cuda").manual_seed(400)
+    A = torch.randn((4, n, n), device="cuda", generator=g)
+    B = torch.randn((4, n, n), device="cuda", generator=g)
+    C = q.qgemm(qctx, A, B)
+    rows = np.random.default_rng(n).choice(n, 24, replace=False)
+    Ah = A[:, rows, :].double().cpu().numpy()
+    Bh = B.double().cpu().numpy()
+    ref = Q.qmul(Ah, Bh)
+    err = np.linalg.norm(C[:, rows, :].double().cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"n={n} rel err {err:.3e}")
+    assert err <= 1e-6
