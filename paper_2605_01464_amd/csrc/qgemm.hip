@@ -39,31 +39,6 @@ struct GemmCfg {
   static_assert(LDS_BYTES <= 65536, "LDS budget");
 };
 
-// out_t = a_t v + sum_u b_tu in_u + g_t I for plane p at one element, plus the reduction terms.
-template <class T>
-__device__ __forceinline__ void epilogue_plane(const GemmParams<T>& P, int p, int row, int col, T v, double& s_d,
-                                               double& s_x) {
-  if (row >= P.M || col >= P.N) return;
-  T inv[3];
-#pragma unroll
-  for (int u = 0; u < 3; ++u) inv[u] = (u < P.nin) ? P.in[u][p * P.psi[u] + (int64_t)row * P.ldi[u] + col] : T(0);
-  const T eye = (p == 0 && row == col) ? T(1) : T(0);
-#pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    if (t < P.nout) {
-      const T o = P.ca[t] * v + P.cg[t] * eye + P.cb[t][0] * inv[0] + P.cb[t][1] * inv[1] + P.cb[t][2] * inv[2];
-      P.out[t][p * P.pso[t] + (int64_t)row * P.ldo[t] + col] = o;
-      if (t == 0 && P.partial) {
-        const double od = (double)o;
-        const double ref = P.ref == 0 ? (double)inv[0] : P.ref == 1 ? (double)inv[1] : P.ref == 2 ? (double)inv[2] : 0.0;
-        const double dd = od - ref;
-        s_d += dd * dd;
-        s_x += od * od;
-      }
-    }
-  }
-}
-
 template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH>
 __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename MM::T> P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
@@ -263,27 +238,7 @@ __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename
         for (int e = lane; e < MM::BLK * MM::BLK; e += 64)
           epilogue_plane(P, p, rb + e / MM::BLK, cb + e % MM::BLK, slab[e], s_d, s_x);
       }
-  if (P.partial) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      s_d += __shfl_xor(s_d, off, 64);
-      s_x += __shfl_xor(s_x, off, 64);
-    }
-    if (lane == 0) {
-      red_lds[w][0] = s_d;
-      red_lds[w][1] = s_x;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double a0 = 0.0, a1 = 0.0;
-      for (int q = 0; q < C::NW; ++q) {
-        a0 += red_lds[q][0];
-        a1 += red_lds[q][1];
-      }
-      P.partial[2 * (int64_t)blockIdx.x] = a0;
-      P.partial[2 * (int64_t)blockIdx.x + 1] = a1;
-    }
-  }
+  store_partials<C::NW>(P.partial, s_d, s_x, red_lds, lane, w, tid);
 }
 
 // Deterministic sum of `count` (d, x) pairs: one workgroup, fixed strided order, fixed tree.
@@ -364,12 +319,15 @@ static const std::vector<F64Entry>& f64_table() {
   return t;
 }
 
+const std::vector<TileConfig>& bf16_configs();  // qgemm_bf16.hip
+
 const std::vector<TileConfig>& tile_configs(Prec p) {
   static std::vector<TileConfig> f32, f64;
   if (f32.empty()) {
     for (auto& e : f32_table()) f32.push_back(e.cfg);
     for (auto& e : f64_table()) f64.push_back(e.cfg);
   }
+  if (p == P_BF16) return bf16_configs();
   return p == P_F64 ? f64 : f32;
 }
 
@@ -388,6 +346,7 @@ int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
     return blocks_for(tile_configs(p)[0], M, N) >= 256 ? 0 : 1;
   }
   const auto& t = tile_configs(p);
+  if (p == P_BF16) return blocks_for(t[0], M, N) >= 256 ? 0 : 1;
   return blocks_for(t[0], M, N) >= 512 ? 0 : 1;
 }
 

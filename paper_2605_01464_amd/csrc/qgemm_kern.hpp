@@ -115,4 +115,55 @@ __device__ __forceinline__ void tile_of_block(int bid, int nb, int tiles_m, int 
 }
 
 
+// out_t = a_t v + sum_u b_tu in_u + g_t I for plane p at one element, plus the reduction terms.
+template <class T>
+__device__ __forceinline__ void epilogue_plane(const GemmParams<T>& P, int p, int row, int col, T v, double& s_d,
+                                               double& s_x) {
+  if (row >= P.M || col >= P.N) return;
+  T inv[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) inv[u] = (u < P.nin) ? P.in[u][p * P.psi[u] + (int64_t)row * P.ldi[u] + col] : T(0);
+  const T eye = (p == 0 && row == col) ? T(1) : T(0);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t < P.nout) {
+      const T o = P.ca[t] * v + P.cg[t] * eye + P.cb[t][0] * inv[0] + P.cb[t][1] * inv[1] + P.cb[t][2] * inv[2];
+      P.out[t][p * P.pso[t] + (int64_t)row * P.ldo[t] + col] = o;
+      if (t == 0 && P.partial) {
+        const double od = (double)o;
+        const double ref = P.ref == 0 ? (double)inv[0] : P.ref == 1 ? (double)inv[1] : P.ref == 2 ? (double)inv[2] : 0.0;
+        const double dd = od - ref;
+        s_d += dd * dd;
+        s_x += od * od;
+      }
+    }
+  }
+}
+
+// Workgroup sum of the epilogue reduction terms, written to partial[2 * blockIdx.x + {0, 1}].
+template <int NW>
+__device__ __forceinline__ void store_partials(double* partial, double s_d, double s_x, double (*red_lds)[2], int lane,
+                                               int w, int tid) {
+  if (!partial) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s_d += __shfl_xor(s_d, off, 64);
+    s_x += __shfl_xor(s_x, off, 64);
+  }
+  if (lane == 0) {
+    red_lds[w][0] = s_d;
+    red_lds[w][1] = s_x;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int q = 0; q < NW; ++q) {
+      a0 += red_lds[q][0];
+      a1 += red_lds[q][1];
+    }
+    partial[2 * (int64_t)blockIdx.x] = a0;
+    partial[2 * (int64_t)blockIdx.x + 1] = a1;
+  }
+}
+
 }  // namespace qp

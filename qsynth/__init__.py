@@ -65,6 +65,21 @@ def stiefel(seed: int, m: int, r: int) -> np.ndarray:
     return _from_cplx(Qc)
 
 
+def householder_unitary(seed: int, n: int, k: int = 64) -> np.ndarray:
+    """n x n unitary quaternion matrix: the product of k quaternion Householder reflectors
+    H = I - 2 v v^H / (v^H v), v with iid N(0,1) components.  Built in the complex-adjoint form, where a
+    reflector is the rank-2 update I - 2 chi(v) chi(v)^H / ||v||^2 (O(n^2) each), so large factors cost
+    seconds instead of an O(n^3) orthonormalisation.  Used for square matrices with a prescribed spectrum."""
+    rng = np.random.default_rng(seed)
+    Q = np.eye(2 * n, dtype=np.complex128)
+    for _ in range(k):
+        v = rng.standard_normal((4, n, 1))
+        vc = _to_cplx(v)  # 2n x 2
+        nv2 = float(np.sum(v * v))
+        Q -= (2.0 / nv2) * (Q @ vc) @ vc.conj().T
+    return _from_cplx(Q)
+
+
 def from_factors(U: np.ndarray, s: np.ndarray, V: np.ndarray) -> np.ndarray:
     """A = U diag(s) V^H for U (4,m,r), real s (r,), V (4,n,r) -> planes (4,m,n)."""
     Uc, Vc = _to_cplx(U), _to_cplx(V)
@@ -113,13 +128,15 @@ def c2_instance(m: int = 2048, n: int = 1536, r: int = 1024, seeds=(100, 101),
     return {"A": round_f32(A64), "A64": A64, "U": U, "s": s, "V": V}
 
 
-def c3_instance(n: int = 4096, seeds=(200, 201), cond: float = 1e3) -> dict:
+def c3_instance(n: int = 4096, seeds=(200, 201), cond: float = 1e3, reflectors: int = 64) -> dict:
     """Square case with condition number `cond`, geometric spectrum, component variance ~1.
 
-    c = 2n / sqrt(sum s_i^2) makes E|a_ij component|^2 = c^2 sum s^2 / (4 n^2) = 1.
+    Factors are products of `reflectors` random quaternion Householder reflectors (see
+    householder_unitary).  c = 2n / sqrt(sum s_i^2) makes the mean squared component
+    c^2 sum s^2 / (4 n^2) equal to 1.
     """
-    U = stiefel(seeds[0], n, n)
-    V = stiefel(seeds[1], n, n)
+    U = householder_unitary(seeds[0], n, reflectors)
+    V = householder_unitary(seeds[1], n, reflectors)
     s = geometric(n, 1.0, 1.0 / cond)
     c = 2.0 * n / np.sqrt(np.sum(s * s))
     s = c * s

@@ -155,3 +155,38 @@ def test_qgemm_square_relative_error_le_1e6(qctx, n):
     err = np.linalg.norm(C[:, rows, :].double().cpu().numpy() - ref) / np.linalg.norm(ref)
     print(f"n={n} rel err {err:.3e}")
     assert err <= 1e-6
+
+
+def round_bf16(x):
+    """Round float32 values to the nearest bfloat16 (ties to even), returned as float64."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_round_bf16_helper():
+    assert round_bf16(np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5]))[0] == 1.0
+    v = round_bf16(np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8]))
+    assert v[0] == 1.0 and v[1] == 1.0 + 2 ** -6  # ties go to the even mantissa
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_qgemm_bf16_every_config(qctx, shape):
+    """BF16-operand product = exact product of the BF16-rounded FP32 inputs up to FP32 accumulation."""
+    import paper_2605_01464_amd as q
+
+    M_, N_, K_ = shape
+    A = rng_planes(21, M_, K_, "f32")
+    B = rng_planes(22, K_, N_, "f32")
+    C0 = rng_planes(23, M_, N_, "f32")
+    alpha, beta, gamma = 0.75, -0.5, 2.0
+    Ab, Bb = round_bf16(A), round_bf16(B)
+    ref = alpha * Q.qmul(Ab, Bb) + beta * C0
+    ref[0] += gamma * np.eye(M_, N_)
+    bound = gemm_bound(Ab, Bb, C0, alpha, beta, gamma, U32)
+    for cfg in range(q.qpinv_num_tile_configs(q.GEMM_PREC["bf16"])):
+        Cd = to_dev(C0, "f32")
+        q.qgemm(qctx, to_dev(A, "f32"), to_dev(B, "f32"), Cd, alpha, beta, gamma, gemm_prec="bf16", cfg=cfg)
+        err = np.abs(to_np(Cd) - ref)
+        name = q.qpinv_tile_config_name(q.GEMM_PREC["bf16"], cfg)
+        assert np.all(err <= bound), (name, float(err.max()), float((err / bound).max()))

@@ -1,0 +1,77 @@
+"""Precision ladder (BF16 -> FP32 -> FP64) on square matrices of condition 1e3 vs the FP64 oracle."""
+import numpy as np
+import pytest
+
+import qsynth
+from conftest import rel_fro, to_dev, to_np
+from oracle import quat as Q
+from oracle import methods as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sq512():
+    return qsynth.c3_instance(n=512, seeds=(210, 211))
+
+
+@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("qrapid", 5)])
+@pytest.mark.parametrize("precision", ["mixed", "f32_f64finish"])
+def test_ladder_reaches_1e6_vs_oracle(qctx, sq512, method, order, precision):
+    import paper_2605_01464_amd as q
+
+    A = sq512["A"]  # FP32 values
+    ref = Q.pinv_svd(A)  # the FP64 pseudoinverse of exactly the matrix the GPU sees
+    X, info = q.solve(qctx, to_dev(A, "f32"), method, order, scaling="power", tol=1e-6, stop="guarded",
+                      precision=precision, out_dtype=__import__("torch").float64)
+    err = rel_fro(to_np(X), ref)
+    assert err <= 1e-6, (info, err)
+    assert 1 <= info["iters_f64"] <= 2
+    if precision == "mixed":
+        assert info["iters_bf16"] >= 1
+    assert info["iters_f32"] >= 1
+
+
+def test_plain_f32_floor_vs_oracle(qctx, sq512):
+    """Plain FP32 stops at its rounding floor (about kappa * u32 * growth), above 1e-6."""
+    import paper_2605_01464_amd as q
+
+    A = sq512["A"]
+    ref = Q.pinv_svd(A)
+    X, info = q.solve(qctx, to_dev(A, "f32"), "qhpi19", scaling="power", tol=1e-6, stop="guarded", precision="f32")
+    err = rel_fro(to_np(X), ref)
+    assert 1e-7 < err <= 1e-3
+
+
+def test_bf16_phase_alone_stalls(qctx, sq512):
+    """BF16 products alone stall far from the inverse (the reason for the ladder)."""
+    import paper_2605_01464_amd as q
+
+    A = sq512["A"]
+    ref = Q.pinv_svd(A)
+    Ad = to_dev(A, "f32")
+    X = q.x0(qctx, Ad, 1.0 / q.features(qctx, Ad, 8)["sigma1_sq"])
+    for _ in range(12):
+        X, _ = q.step(qctx, Ad, X, "qhpi19", gemm_prec="bf16")
+    assert rel_fro(to_np(X), ref) > 1e-3
+
+
+def test_full_size_mixed_sampled_rows(qctx):
+    """4096 x 4096, condition 1e3: rows i of A X - I computed on the host for sampled i must be at FP64
+    level after the FP64 finish (relative error <= kappa * residual)."""
+    import torch
+    import paper_2605_01464_amd as q
+
+    inst = qsynth.c3_instance()
+    A = inst["A"]
+    X, info = q.solve(qctx, to_dev(A, "f32"), "qhpi19", scaling="power", tol=1e-6, stop="guarded",
+                      precision="mixed", out_dtype=torch.float64)
+    Xh = to_np(X)
+    rows = np.random.default_rng(5).choice(A.shape[1], 16, replace=False)
+    AXr = Q.qmul(A[:, rows, :], Xh)
+    I = np.zeros_like(AXr)
+    I[0, np.arange(16), rows] = 1.0
+    res = np.linalg.norm(AXr - I) / np.sqrt(16)
+    s = inst["s"]
+    assert res * (s[0] / s[-1]) <= 1e-6, (res, info)
+    assert info["iters_bf16"] >= 1 and 1 <= info["iters_f64"] <= 2
