@@ -56,6 +56,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gemm", action="store_true", help="skip the standalone square-product measurement")
     ap.add_argument("--no-autotune", action="store_true", help="use the heuristic tile choice instead of tuning")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 4096^2 mixed-vs-plain precision comparison")
+    ap.add_argument("--mixed-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -143,6 +145,37 @@ def main() -> int:
             tf, ms = qgemm_tflops(q, ctx, nn)
             out["qgemm_square"][f"f32_n{nn}"] = {"tflops": tf, "ms": ms, "frac_peak": tf / PEAK["f32"]}
 
+    mixed_inst = None
+    if not args.no_mixed:
+        # 4096 x 4096, condition 1e3, geometric spectrum, components of unit variance: solves/s of
+        # the precision ladder vs the plain forms, each reaching relative error <= 1e-6 (FP64 finish)
+        t_g = time.time()
+        mixed_inst = qsynth.c3_instance()
+        t_g = time.time() - t_g
+        A3 = torch.from_numpy(mixed_inst["A"].astype(np.float32)).cuda()
+        A3d = A3.double()
+        X3 = torch.empty((4, A3.shape[2], A3.shape[1]), dtype=torch.float64, device="cuda")
+        res = {}
+        for label, prec, Ain in (("mixed_bf16_f32_f64", "mixed", A3), ("plain_f32_f64finish", "f32_f64finish", A3),
+                                 ("plain_f64", "f64", A3d)):
+            for method in ("qhpi19", "qrapid"):
+                kw = dict(method=method, order=None, scaling="power", tol=1e-6, max_iter=100, stop="guarded",
+                          precision=prec, X=X3)
+                q.solve(ctx, Ain, **kw)  # warm-up (and tile tuning)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(args.mixed_steps):
+                    _, inf3 = q.solve(ctx, Ain, **kw)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t) / args.mixed_steps
+                Ea, Er = q.residuals(ctx, A3, X3)
+                res[f"{label}:{method}"] = {"pinv_per_s": 1.0 / dt, "ms": 1e3 * dt, "iters_bf16": inf3["iters_bf16"],
+                                            "iters_f32": inf3["iters_f32"], "iters_f64": inf3["iters_f64"],
+                                            "E_rel_fp64": Er}
+        out["mixed_vs_plain"] = {"workload": "4096x4096 quaternion, cond 1e3, geometric spectrum, unit-variance "
+                                             "components (FP32 input), guarded stop tol 1e-6",
+                                 "input_generation_s": t_g, "results": res}
+
     if not args.no_cpu_baseline:
         # FP64 oracle on the host: one iteration of the same method on the same input (left side),
         # scaled by the GPU solve's iteration count -> solves/s.  Bounded sample of the workload.
@@ -167,6 +200,16 @@ def main() -> int:
         Xd = X.detach().cpu().double().numpy()
         Xc = Q.pinv_from_factors(inst["U"], inst["s"], inst["V"])
         out["rel_err_vs_rank1024_pinv"] = float(np.linalg.norm(Xd - Xc) / np.linalg.norm(Xc))
+        if mixed_inst is not None:
+            # sampled rows of the last mixed-section result (QRAPID, FP64) vs the exact inverse of the
+            # FP32 input: relative residual of rows of A X - I, times the condition number
+            A3h = mixed_inst["A"]
+            X3h = X3.detach().cpu().numpy()
+            rows = np.random.default_rng(5).choice(A3h.shape[1], 8, replace=False)
+            AXr = Q.qmul(A3h[:, rows, :], X3h)
+            AXr[0, np.arange(8), rows] -= 1.0
+            out["mixed_vs_plain"]["row_residual_bound_last"] = float(
+                np.linalg.norm(AXr) / np.sqrt(8) * mixed_inst["s"][0] / mixed_inst["s"][-1])
 
     ctx.close()
     print(json.dumps(out))

@@ -156,6 +156,23 @@ int qpinv_solve(qpinv_ctx* ctx, int method, int order, const qpinv_qmat* A, int 
                 double tol, int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info,
                 void* hip_stream);
 
+/* Many independent solves in ONE persistent kernel launch (replayed from a captured hipGraph when the
+ * batch signature repeats).  Each workgroup takes matrices from a device queue, largest work first,
+ * and runs the whole method on each (power-iteration or given alpha, X_0 = alpha A^H, the product chain,
+ * the stop rule) on the residual side of the smaller dimension.
+ *   method       NS, QSAI or QHPI19 (order as for qpinv_solve).
+ *   batch        number of matrices; A and X are HOST arrays of `batch` descriptors of DEVICE data.
+ *   A[b]         m_b x n_b, FP32, 1 <= m_b, n_b <= 512;  X[b]: n_b x m_b, FP32 (output).
+ *   scaling      ALPHA_POWER (option power_steps / power_seed) or ALPHA_GIVEN with alpha[b] > 0.
+ *   stop         DX_ABS, DX_REL or GUARDED with tol; max_iter bounds every solve.
+ *   infos        host array of `batch` (may be NULL); infos[b].reserved holds that solve's status.
+ * The tile configuration is timed on the batch when option autotune = 1 (once per batch signature).
+ * Return: OK; ENOTCONVERGED / EDIVERGED / ENONFINITE if any solve ended that way (see infos);
+ *         EINVAL; EHIP; ENOMEM.  The call waits for the batch to finish. */
+int qpinv_solve_batched(qpinv_ctx* ctx, int method, int order, int batch, const qpinv_qmat* A, qpinv_qmat* X,
+                        int scaling, const double* alpha, double tol, int max_iter, int stop, qpinv_info* infos,
+                        void* hip_stream);
+
 /* One iteration X_out = X_{j+1} from X_in = X_j (Algorithms 1-3, one pass of the loop body) in the
  * given product precision (qpinv_gemm_prec) on the given side (LEFT/RIGHT; AUTO picks the smaller).
  * A, X_in, X_out share one storage dtype (F64 for GEMM_F64, F32 otherwise).  `dx` (host, may be

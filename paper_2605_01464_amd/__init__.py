@@ -75,6 +75,7 @@ def _load() -> ctypes.CDLL:
         "qpinv_last_error": (ctypes.c_char_p, []),
         "qpinv_solve": (I, [P, I, I, QP, I, D, D, I, I, I, QP, ctypes.POINTER(Info), P]),
         "qpinv_step": (I, [P, I, I, I, I, QP, QP, QP, DP, P]),
+        "qpinv_solve_batched": (I, [P, I, I, I, QP, QP, I, DP, D, I, I, ctypes.POINTER(Info), P]),
         "qpinv_residuals": (I, [P, QP, QP, DP, DP, P]),
         "qpinv_qgemm": (I, [P, I, QP, QP, QP, D, D, D, P]),
         "qpinv_qgemm_cfg": (I, [P, I, I, QP, QP, QP, D, D, D, P]),
@@ -161,6 +162,17 @@ def qpinv_solve(ctx, method, order, A, scaling, alpha_or_mu, tol, max_iter, stop
     st = _lib.qpinv_solve(ctx, method, order, ctypes.byref(qmat(A)), scaling, float(alpha_or_mu), float(tol),
                           int(max_iter), stop, precision, ctypes.byref(qmat(X)), ctypes.byref(info), _stream(stream))
     return st, info
+
+
+def qpinv_solve_batched(ctx, method, order, As, Xs, scaling, alphas, tol, max_iter, stop, stream=None):
+    n = len(As)
+    Aq = (QMat * max(n, 1))(*[qmat(a) for a in As])
+    Xq = (QMat * max(n, 1))(*[qmat(x) for x in Xs])
+    al = (ctypes.c_double * max(n, 1))(*(alphas if alphas is not None else [0.0] * n))
+    infos = (Info * max(n, 1))()
+    st = _lib.qpinv_solve_batched(ctx, method, order, n, Aq, Xq, scaling, al if alphas is not None else None,
+                                  float(tol), int(max_iter), stop, infos, _stream(stream))
+    return st, [infos[i] for i in range(n)]
 
 
 def qpinv_step(ctx, method, order, side, gemm_prec, A, X_in, X_out, stream=None):
@@ -287,6 +299,25 @@ def solve(ctx: Context, A, method="qhpi19", order=None, scaling="power", alpha=0
     if check and st not in (OK, ENOTCONVERGED):
         _err(st, "qpinv_solve")
     return X, d
+
+
+def solve_batched(ctx: Context, As, method="qhpi19", order=None, scaling="power", alphas=None, tol=1e-6,
+                  max_iter=100, stop="guarded", Xs=None, stream=None, check=True):
+    """X_b ~= A_b^dagger for every FP32 matrix of the list, in one persistent launch.  Returns (Xs, infos)."""
+    import torch
+
+    if Xs is None:
+        Xs = [torch.empty((4, a.shape[2], a.shape[1]), dtype=torch.float32, device=a.device) for a in As]
+    st, infos = qpinv_solve_batched(ctx.handle, METHOD[method], _order(method, order), As, Xs, SCALING[scaling],
+                                    alphas, tol, max_iter, STOP[stop], stream)
+    out = []
+    for inf in infos:
+        d = inf.as_dict()
+        d["status"] = inf.reserved
+        out.append(d)
+    if check and st not in (OK, ENOTCONVERGED):
+        _err(st, "qpinv_solve_batched")
+    return Xs, out
 
 
 def step(ctx: Context, A, X, method="qhpi19", order=None, side="auto", gemm_prec=None, out=None, stream=None):

@@ -1,0 +1,60 @@
+// Batched persistent solver (host interface).
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace qp {
+
+// One matrix of a batch (device pointers, FP32 storage).  X_b is n x m.
+struct BDesc {
+  const float* A;
+  int64_t lda, psa;
+  float* X;
+  int64_t ldx, psx;
+  int m, n;
+};
+
+// Per-matrix outcome written by the kernel.
+struct BInfo {
+  int iters, returned, reason, status;
+  double alpha, dx_rel, sigma1_sq;
+};
+
+// Everything the captured graph bakes in.
+struct BKey {
+  int count = 0, D = 0, cfg = 0, method = 0, stop = 0, max_iter = 0, scaling = 0, power_steps = 0;
+  double tol = 0.0;
+  unsigned long long seed = 0;
+  bool operator==(const BKey& o) const {
+    return count == o.count && D == o.D && cfg == o.cfg && method == o.method && stop == o.stop &&
+           max_iter == o.max_iter && scaling == o.scaling && power_steps == o.power_steps && tol == o.tol &&
+           seed == o.seed;
+  }
+};
+
+// Device buffers, pinned staging buffers and the captured graph of the last batch signature.
+struct BatchedState {
+  BKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  BDesc* h_desc = nullptr;
+  BInfo* h_info = nullptr;
+  int* h_order = nullptr;
+  double* h_alpha = nullptr;
+  int grid = 0;
+  std::vector<void*> dev;
+  ~BatchedState();
+};
+
+// Upload the batch, replay (or build) the graph and wait for it; infos receives the outcomes.
+void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& desc, const std::vector<int>& order,
+                 const std::vector<double>& alphas, std::vector<BInfo>& infos, hipStream_t caller);
+
+int batched_num_configs();
+const char* batched_config_name(int cfg);
+
+}  // namespace qp

@@ -169,6 +169,16 @@ int qpinv_solve(qpinv_ctx* c, int method, int order, const qpinv_qmat* A, int sc
   });
 }
 
+int qpinv_solve_batched(qpinv_ctx* c, int method, int order, int batch, const qpinv_qmat* A, qpinv_qmat* X,
+                        int scaling, const double* alpha, double tol, int max_iter, int stop, qpinv_info* infos,
+                        void* hip_stream) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    return qp::solve_batched(cx, method, order, batch, A, X, scaling, alpha, tol, max_iter, stop, infos,
+                             stream_of(hip_stream));
+  });
+}
+
 int qpinv_step(qpinv_ctx* c, int method, int order, int side, int gemm_prec, const qpinv_qmat* A, const qpinv_qmat* X_in,
                qpinv_qmat* X_out, double dx[2], void* hip_stream) {
   return guarded([&]() {

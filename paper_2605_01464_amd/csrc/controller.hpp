@@ -10,10 +10,11 @@
 // An absolute or relative change that is not finite is divergence.
 #pragma once
 
-#include <cmath>
-#include <limits>
+#include <hip/hip_runtime.h>
 
 namespace qp {
+
+#define QP_HD __host__ __device__
 
 enum StopRule : int { STOP_DX_ABS = 0, STOP_DX_REL = 1, STOP_E1_REL = 2, STOP_GUARDED = 3 };
 enum Decision : int { D_CONTINUE = 0, D_TOL = 1, D_RISE = 2, D_DIVERGED = 3, D_NEWMIN = 4 };
@@ -23,21 +24,21 @@ struct StopController {
   double tol;
   double dmax = 0.0;
   double dprev = -1.0;
-  double best_d = std::numeric_limits<double>::infinity();
+  double best_d = __builtin_huge_val();
   int best_j = -1;
 
-  StopController(int r, double t) : rule(r), tol(t) {}
+  QP_HD StopController(int r, double t) : rule(r), tol(t) {}
 
   // j = index of the new iterate X_j (1-based update count).
-  int update(int j, double d_abs, double x_norm, double e1_rel) {
-    if (!std::isfinite(d_abs) || !std::isfinite(x_norm)) return D_DIVERGED;
+  QP_HD int update(int j, double d_abs, double x_norm, double e1_rel) {
+    if (!__builtin_isfinite(d_abs) || !__builtin_isfinite(x_norm)) return D_DIVERGED;
     switch (rule) {
       case STOP_DX_ABS:
         return d_abs < tol ? D_TOL : D_CONTINUE;
       case STOP_DX_REL:
         return d_abs <= tol * x_norm ? D_TOL : D_CONTINUE;
       case STOP_E1_REL:
-        if (!std::isfinite(e1_rel)) return D_DIVERGED;
+        if (!__builtin_isfinite(e1_rel)) return D_DIVERGED;
         return e1_rel <= tol ? D_TOL : D_CONTINUE;
       default: {
         const double d = x_norm > 0.0 ? d_abs / x_norm : 0.0;

@@ -19,226 +19,16 @@
 
 namespace qp {
 
-template <class MM, int BM, int BN, int BK, int WM, int WN>
-struct GemmCfg {
-  using T = typename MM::T;
-  static constexpr int NW = WM * WN, NT = 64 * NW;
-  static constexpr int WTM = BM / WM, WTN = BN / WN;
-  static constexpr int TM = WTM / MM::BLK, TN = WTN / MM::BLK;
-  static constexpr int PADA = (sizeof(T) == 4) ? 4 : 2;
-  static constexpr int PADB = (sizeof(T) == 4) ? 4 : 2;
-  static constexpr int LDA = BM + PADA, LDB = BN + PADB;
-  static constexpr int VA = V16<T>::n;
-  static constexpr int ACH = BM * BK / VA;  // 16-byte chunks per plane of an A tile
-  static constexpr int BCH = BK * BN / VA;
-  static constexpr int NA = (ACH + NT - 1) / NT;
-  static constexpr int NB = (BCH + NT - 1) / NT;
-  static_assert(TM >= 1 && TN >= 1 && WTM % MM::BLK == 0 && WTN % MM::BLK == 0, "wave tile");
-  static_assert(BK % MM::KS == 0 && BK % VA == 0 && BN % VA == 0, "k tile");
-  static constexpr size_t LDS_BYTES = sizeof(T) * 4 * BK * (LDA + LDB);
-  static_assert(LDS_BYTES <= 65536, "LDS budget");
-};
-
 template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH>
 __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename MM::T> P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
-  static_assert(FLUSH == 0 || FLUSH % BK == 0, "flush interval is a whole number of K tiles");
-  using T = typename MM::T;
-  using Acc = typename MM::Acc;
-  using VT = typename V16<T>::type;
-  constexpr int VA = C::VA;
-
-  __shared__ T smem[4 * BK * (C::LDA + C::LDB)];
-  T* const As = smem;
-  T* const Bs = smem + 4 * BK * C::LDA;
-  static_assert(C::NW * MM::BLK * MM::BLK <= 4 * BK * (C::LDA + C::LDB), "epilogue staging fits in LDS");
+  __shared__ typename MM::T smem[C::SMEM];
   __shared__ double red_lds[C::NW][2];
-
   int tm, tn;
   tile_of_block(blockIdx.x, P.tiles_m * P.tiles_n, P.tiles_m, P.tiles_n, tm, tn);
-  const int m0 = tm * BM, n0 = tn * BN;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
-  const int wm = w % WM, wn = w / WM;
-
-  Acc acc[4][C::TM][C::TN];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-        for (int r = 0; r < MM::NR; ++r) acc[p][i][j][r] = T(0);
-
-  // Two-level accumulation: the MFMA accumulators cover FLUSH consecutive k and are then added into
-  // `tot`, so no FP32 rounding chain is longer than FLUSH/KS + K/FLUSH additions.
-  constexpr int TT = FLUSH > 0 ? 4 : 1;  // a 1-element placeholder when the flush is off
-  Acc tot[TT][FLUSH > 0 ? C::TM : 1][FLUSH > 0 ? C::TN : 1];
-  if constexpr (FLUSH > 0) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-          for (int r = 0; r < MM::NR; ++r) tot[p][i][j][r] = T(0);
-  }
-  auto flush = [&]() {
-    if constexpr (FLUSH > 0) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-          for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-            for (int r = 0; r < MM::NR; ++r) {
-              tot[p][i][j][r] += acc[p][i][j][r];
-              acc[p][i][j][r] = T(0);
-            }
-    }
-  };
-
-  T ra[4][C::NA][VA];
-  T rb[4][C::NB][VA];
-
-  auto load = [&](int k0) {
-    const bool fullA = P.vec && (m0 + BM <= P.M) && (k0 + BK <= P.K);
-    const bool fullB = P.vec && (n0 + BN <= P.N) && (k0 + BK <= P.K);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T* Aq = P.A + q * P.psa;
-#pragma unroll
-      for (int t = 0; t < C::NA; ++t) {
-        const int c = tid + t * C::NT;
-        const int i = c / (BK / VA), kc = (c % (BK / VA)) * VA;
-        if (C::ACH % C::NT == 0 || c < C::ACH) {
-          const int gi = m0 + i, gk = k0 + kc;
-          if (fullA) {
-            const VT v = *reinterpret_cast<const VT*>(Aq + (int64_t)gi * P.lda + gk);
-            const T* pv = reinterpret_cast<const T*>(&v);
-#pragma unroll
-            for (int e = 0; e < VA; ++e) ra[q][t][e] = pv[e];
-          } else {
-#pragma unroll
-            for (int e = 0; e < VA; ++e)
-              ra[q][t][e] = (gi < P.M && gk + e < P.K) ? Aq[(int64_t)gi * P.lda + gk + e] : T(0);
-          }
-        }
-      }
-      const T* Bq = P.B + q * P.psb;
-#pragma unroll
-      for (int t = 0; t < C::NB; ++t) {
-        const int c = tid + t * C::NT;
-        const int k = c / (BN / VA), jc = (c % (BN / VA)) * VA;
-        if (C::BCH % C::NT == 0 || c < C::BCH) {
-          const int gk = k0 + k, gj = n0 + jc;
-          if (fullB) {
-            const VT v = *reinterpret_cast<const VT*>(Bq + (int64_t)gk * P.ldb + gj);
-            const T* pv = reinterpret_cast<const T*>(&v);
-#pragma unroll
-            for (int e = 0; e < VA; ++e) rb[q][t][e] = pv[e];
-          } else {
-#pragma unroll
-            for (int e = 0; e < VA; ++e)
-              rb[q][t][e] = (gk < P.K && gj + e < P.N) ? Bq[(int64_t)gk * P.ldb + gj + e] : T(0);
-          }
-        }
-      }
-    }
-  };
-
-  auto store = [&]() {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int t = 0; t < C::NA; ++t) {
-        const int c = tid + t * C::NT;
-        if (C::ACH % C::NT == 0 || c < C::ACH) {
-          const int i = c / (BK / VA), kc = (c % (BK / VA)) * VA;
-#pragma unroll
-          for (int e = 0; e < VA; ++e) As[(q * BK + kc + e) * C::LDA + i] = ra[q][t][e];
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < C::NB; ++t) {
-        const int c = tid + t * C::NT;
-        if (C::BCH % C::NT == 0 || c < C::BCH) {
-          const int k = c / (BN / VA), jc = (c % (BN / VA)) * VA;
-          VT v;
-          T* pv = reinterpret_cast<T*>(&v);
-#pragma unroll
-          for (int e = 0; e < VA; ++e) pv[e] = rb[q][t][e];
-          *reinterpret_cast<VT*>(&Bs[(q * BK + k) * C::LDB + jc]) = v;
-        }
-      }
-    }
-  };
-
-  const int fr = MM::fr(lane), fk = MM::fk(lane);
-  if (P.K > 0) load(0);
-  for (int k0 = 0; k0 < P.K; k0 += BK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + BK < P.K) load(k0 + BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += MM::KS) {
-      T a[C::TM][4], b[C::TN][4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int i = 0; i < C::TM; ++i)
-          a[i][q] = As[(q * BK + kk + fk) * C::LDA + wm * C::WTM + i * MM::BLK + fr];
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j)
-          b[j][q] = Bs[(q * BK + kk + fk) * C::LDB + wn * C::WTN + j * MM::BLK + fr];
-      }
-#pragma unroll
-      for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j) {
-          Acc t4[4] = {acc[0][i][j], acc[1][i][j], acc[2][i][j], acc[3][i][j]};
-          quat_mma<MM>(t4, a[i], b[j]);
-#pragma unroll
-          for (int p = 0; p < 4; ++p) acc[p][i][j] = t4[p];
-        }
-    }
-    if constexpr (FLUSH > 0) {
-      if ((k0 + BK) % FLUSH == 0) flush();
-    }
-  }
-  flush();
-
-  // ---------------------------------------------------------------- epilogue
-  // Each MFMA block of each plane goes through a per-wave LDS slab, so the accumulators are only
-  // read with compile-time indices and the output pass runs row-contiguous.
   double s_d = 0.0, s_x = 0.0;
-  T* const slab = smem + w * MM::BLK * MM::BLK;
-#pragma unroll
-  for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-    for (int j = 0; j < C::TN; ++j)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < MM::NR; ++r) {
-          T v;
-          if constexpr (FLUSH > 0)
-            v = tot[p][i][j][r];
-          else
-            v = acc[p][i][j][r];
-          slab[MM::crow(lane, r) * MM::BLK + MM::ccol(lane)] = v;
-        }
-        __syncthreads();
-        const int rb = m0 + wm * C::WTM + i * MM::BLK, cb = n0 + wn * C::WTN + j * MM::BLK;
-        for (int e = lane; e < MM::BLK * MM::BLK; e += 64)
-          epilogue_plane(P, p, rb + e / MM::BLK, cb + e % MM::BLK, slab[e], s_d, s_x);
-      }
-  store_partials<C::NW>(P.partial, s_d, s_x, red_lds, lane, w, tid);
+  gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH>(P, tm, tn, smem, s_d, s_x);
+  store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
 }
 
 // Deterministic sum of `count` (d, x) pairs: one workgroup, fixed strided order, fixed tree.
@@ -381,6 +171,7 @@ static GemmParams<T> make_params(const QView& A, const QView& B, int64_t M, int6
     for (int u = 0; u < 3; ++u) P.cb[t][u] = (T)e.b[t][u];
   }
   P.partial = e.reduce ? partial : nullptr;
+  P.reduce = e.reduce ? 1 : 0;
   return P;
 }
 

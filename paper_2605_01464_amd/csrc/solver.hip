@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "aux.hpp"
+#include "batched.hpp"
 #include "controller.hpp"
 #include "solver.hpp"
 
@@ -95,6 +96,7 @@ Ctx::~Ctx() {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  delete batched;
   ws.release();
   if (scratch.partial) (void)hipFree(scratch.partial);
   if (dsc) (void)hipFree(dsc);
@@ -925,6 +927,117 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
   convert_mat(S->b[returned_buf], Xout, s);
   QP_HIP(hipStreamSynchronize(s));
   return finish(status);
+}
+
+// ------------------------------------------------------------------------------------------------
+// batched solves: one persistent launch per batch (batched.hip)
+// ------------------------------------------------------------------------------------------------
+int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A, qpinv_qmat* X, int scaling,
+                  const double* alpha, double tol, int max_iter, int stop, qpinv_info* infos, hipStream_t s) {
+  const double t0 = now_s();
+  check_method(method, order);
+  if (method != QPINV_NS && method != QPINV_QSAI && method != QPINV_QHPI19)
+    throw Error(QPINV_EINVAL, "batched solves support NS, QSAI and QHPI19");
+  if (batch < 0 || (batch > 0 && (!A || !X))) throw Error(QPINV_EINVAL, "bad batch arrays");
+  if (scaling != QPINV_ALPHA_POWER && scaling != QPINV_ALPHA_GIVEN)
+    throw Error(QPINV_EINVAL, "batched solves take ALPHA_POWER or ALPHA_GIVEN");
+  if (scaling == QPINV_ALPHA_GIVEN && !alpha) throw Error(QPINV_EINVAL, "ALPHA_GIVEN needs the alpha array");
+  if (!(tol >= 0.0) || max_iter < 1) throw Error(QPINV_EINVAL, "tol must be >= 0 and max_iter >= 1");
+  if (stop != STOP_DX_ABS && stop != STOP_DX_REL && stop != STOP_GUARDED)
+    throw Error(QPINV_EINVAL, "batched solves take the DX_ABS, DX_REL or GUARDED stop rule");
+  if (batch == 0) return QPINV_OK;
+  std::vector<BDesc> desc(batch);
+  std::vector<double> work(batch);
+  int64_t D = 8;
+  for (int b = 0; b < batch; ++b) {
+    validate(&A[b], "A[b]");
+    validate(&X[b], "X[b]");
+    if (A[b].dtype != QPINV_F32 || X[b].dtype != QPINV_F32) throw Error(QPINV_EINVAL, "batched solves use FP32 storage");
+    const int64_t m = A[b].rows, n = A[b].cols;
+    if (m < 1 || n < 1 || m > 512 || n > 512) throw Error(QPINV_EINVAL, "batched matrices must have 1..512 rows and cols");
+    if (X[b].rows != n || X[b].cols != m) throw Error(QPINV_EINVAL, "X[b] must be n x m");
+    if (scaling == QPINV_ALPHA_GIVEN && !(alpha[b] > 0.0)) throw Error(QPINV_EINVAL, "alpha[b] must be > 0");
+    desc[b] = BDesc{static_cast<const float*>(A[b].data), A[b].ld, A[b].plane_stride, static_cast<float*>(X[b].data),
+                    X[b].ld, X[b].plane_stride, (int)m, (int)n};
+    const double sd = (double)std::min(m, n), od = (double)std::max(m, n);
+    work[b] = sd * sd * od;
+    D = std::max<int64_t>(D, std::max(m, n));
+  }
+  D = round8(D);
+  // largest work first
+  std::vector<int> order_v(batch);
+  for (int b = 0; b < batch; ++b) order_v[b] = b;
+  std::stable_sort(order_v.begin(), order_v.end(), [&](int a, int b2) { return work[a] > work[b2]; });
+  std::vector<double> alphas;
+  if (scaling == QPINV_ALPHA_GIVEN) alphas.assign(alpha, alpha + batch);
+  BKey key;
+  key.count = batch;
+  key.D = (int)D;
+  key.method = method == QPINV_NS ? 0 : method == QPINV_QSAI ? 2 : 3;
+  key.stop = stop;
+  key.max_iter = max_iter;
+  key.tol = tol;
+  key.scaling = scaling == QPINV_ALPHA_GIVEN ? 2 : 0;
+  key.power_steps = c.opt.power_steps;
+  key.seed = c.opt.power_seed;
+  if (!c.batched) c.batched = new BatchedState();
+  std::vector<BInfo> out;
+  // tile configuration: tuned per batch signature (size histogram) when autotuning is on
+  std::vector<int64_t> sig = {batch, D, key.method, stop, max_iter};
+  for (int b = 0; b < batch; ++b) {
+    sig.push_back(A[b].rows);
+    sig.push_back(A[b].cols);
+  }
+  auto it = c.batched_tuned.find(sig);
+  if (it != c.batched_tuned.end()) {
+    key.cfg = it->second;
+  } else if (c.opt.autotune) {
+    double best = 1e300;
+    int best_cfg = 0;
+    for (int cfg = 0; cfg < batched_num_configs(); ++cfg) {
+      key.cfg = cfg;
+      run_batched(*c.batched, key, desc, order_v, alphas, out, s);  // builds the graph (and warms up)
+      const double t1 = now_s();
+      run_batched(*c.batched, key, desc, order_v, alphas, out, s);
+      const double dt = now_s() - t1;
+      if (c.opt.verbose) fprintf(stderr, "[qpinv] batched %s: %.3f ms\n", batched_config_name(cfg), 1e3 * dt);
+      if (dt < best) {
+        best = dt;
+        best_cfg = cfg;
+      }
+    }
+    key.cfg = best_cfg;
+    c.batched_tuned[sig] = best_cfg;
+  } else {
+    key.cfg = 0;
+  }
+  run_batched(*c.batched, key, desc, order_v, alphas, out, s);
+  const double secs = now_s() - t0;
+  int status = QPINV_OK;
+  for (int b = 0; b < batch; ++b) {
+    const BInfo& bi = out[b];
+    if (infos) {
+      qpinv_info& r = infos[b];
+      std::memset(&r, 0, sizeof(r));
+      r.iters = bi.iters;
+      r.iters_f32 = bi.iters;
+      r.returned = bi.returned;
+      r.stop_reason = bi.reason;
+      r.side = desc[b].m > desc[b].n ? QPINV_SIDE_LEFT : QPINV_SIDE_RIGHT;
+      r.alpha_used = bi.alpha;
+      r.mu_used = bi.sigma1_sq > 0 ? bi.alpha * bi.sigma1_sq : 0.0;
+      r.sigma1_sq_est = bi.sigma1_sq;
+      r.final_dx_rel = bi.dx_rel;
+      r.e1_rel = -1.0;
+      r.seconds = secs;
+      r.reserved = bi.status;
+    }
+    if (bi.status == QPINV_ENONFINITE || bi.status == QPINV_EDIVERGED)
+      status = status == QPINV_OK || status == QPINV_ENOTCONVERGED ? bi.status : status;
+    else if (bi.status == QPINV_ENOTCONVERGED && status == QPINV_OK)
+      status = QPINV_ENOTCONVERGED;
+  }
+  return status;
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -37,7 +37,8 @@ struct Options {
   int gemm_timing = 0;
 };
 
-struct MlpState;  // scaling network (mlp.hip)
+struct MlpState;      // scaling network (mlp.hip)
+struct BatchedState;  // batched persistent solver (batched.hip)
 
 struct Ctx {
   int device = 0;
@@ -48,6 +49,8 @@ struct Ctx {
   double* hsc = nullptr;  // pinned host scalars
   std::map<std::tuple<int, int64_t, int64_t, int64_t>, int> tuned;
   MlpState* mlp = nullptr;
+  BatchedState* batched = nullptr;
+  std::map<std::vector<int64_t>, int> batched_tuned;  // batch signature -> tile configuration
   double flops = 0.0;  // running count of algorithmic product flops
   // event pairs around product launches (option gemm_timing)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -84,6 +87,9 @@ void chain(Ctx& c, int method, int order, int side, Prec p, const Mat& A, const 
 
 int solve(Ctx& c, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu, double tol,
           int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info, hipStream_t s);
+
+int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A, qpinv_qmat* X, int scaling,
+                  const double* alpha, double tol, int max_iter, int stop, qpinv_info* infos, hipStream_t s);
 
 void residuals(Ctx& c, const qpinv_qmat* A, const qpinv_qmat* X, double E_abs[4], double E_rel[4], hipStream_t s);
 
