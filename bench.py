@@ -58,6 +58,9 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="use the heuristic tile choice instead of tuning")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 4096^2 mixed-vs-plain precision comparison")
     ap.add_argument("--mixed-steps", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-matrix batched comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-scaling evaluation")
+    ap.add_argument("--learned-count", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -175,6 +178,60 @@ def main() -> int:
         out["mixed_vs_plain"] = {"workload": "4096x4096 quaternion, cond 1e3, geometric spectrum, unit-variance "
                                              "components (FP32 input), guarded stop tol 1e-6",
                                  "input_generation_s": t_g, "results": res}
+
+    if not args.no_batched:
+        # 512 quaternion matrices, rows and cols uniform in [32, 256], planes N(0,1), cond <= 1e3:
+        # one persistent launch (graph replay) vs a loop of single-matrix solves over the same batch
+        t_g = time.time()
+        sizes = qsynth.c4_sizes()
+        As4 = [torch.from_numpy(qsynth.c4_instance(b, sizes).astype(np.float32)).cuda() for b in range(len(sizes))]
+        t_g = time.time() - t_g
+        Xs4 = [torch.empty((4, a.shape[2], a.shape[1]), dtype=torch.float32, device="cuda") for a in As4]
+        q.solve_batched(ctx, As4, "qhpi19", tol=1e-6, stop="guarded", Xs=Xs4)  # tile tuning + graph build
+        torch.cuda.synchronize()
+        reps = 3
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, inf4 = q.solve_batched(ctx, As4, "qhpi19", tol=1e-6, stop="guarded", Xs=Xs4)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t) / reps
+        for a, x in zip(As4[:8], Xs4[:8]):  # warm the single path's shapes a little
+            q.solve(ctx, a, "qhpi19", tol=1e-6, stop="guarded", precision="f32", X=x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a, x in zip(As4, Xs4):
+            q.solve(ctx, a, "qhpi19", tol=1e-6, stop="guarded", precision="f32", X=x)
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t
+        its = [i["iters"] for i in inf4]
+        s_ = [min(a.shape[1], a.shape[2]) for a in As4]
+        o_ = [max(a.shape[1], a.shape[2]) for a in As4]
+        flops = sum(7 * 32.0 * si * si * oi * it for si, oi, it in zip(s_, o_, its))
+        out["batched"] = {"workload": "512 quaternion matrices, rows/cols uniform in [32,256], N(0,1) planes, "
+                                      "cond <= 1e3, QHPI19 FP32, guarded stop tol 1e-6",
+                          "persistent_solves_per_s": len(As4) / t_batch, "batch_ms": 1e3 * t_batch,
+                          "loop_single_solves_per_s": len(As4) / t_loop, "loop_ms": 1e3 * t_loop,
+                          "speedup_vs_loop": t_loop / t_batch, "iters_median": float(np.median(its)),
+                          "gemm_tflops_effective": flops / t_batch / 1e12, "input_generation_s": t_g}
+
+    if not args.no_learned:
+        # learned initial scaling (network trained on the GPU by this library on 20k matrices 64..512):
+        # FP64 QHPI19 to ||AXA - A||_F / ||A||_F <= 1e-10 on held-out 1024 x 768 matrices
+        from paper_2605_01464_amd import learned as L
+
+        meta = L.load(ctx)
+        t_g = time.time()
+        ev = L.build_set(ctx, range(2_000_000, 2_000_000 + args.learned_count), shape=(1024, 768), keep=True)
+        t_g = time.time() - t_g
+        res, _ = L.evaluate(ctx, ev["mats"], ev)
+        res["workload"] = (f"{args.learned_count} held-out 1024x768 quaternion matrices (geometric / clustered / "
+                           "low-rank+noise spectra), QHPI19 FP64, tol 1e-10 on E1_rel")
+        res["gain_iters_vs_classical"] = res["classical"]["mean_iters"] - res["learned"]["mean_iters"]
+        res["headroom_iters_vs_classical"] = res["classical"]["mean_iters"] - res["best"]["mean_iters"]
+        res["train_meta"] = meta
+        res["input_and_feature_s"] = t_g
+        out["learned_scaling"] = res
+        del ev
 
     if not args.no_cpu_baseline:
         # FP64 oracle on the host: one iteration of the same method on the same input (left side),

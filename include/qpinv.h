@@ -200,11 +200,58 @@ int qpinv_qgemm(qpinv_ctx* ctx, int gemm_prec, const qpinv_qmat* A, const qpinv_
  * Errors: EINVAL, EHIP. */
 int qpinv_x0(qpinv_ctx* ctx, const qpinv_qmat* A, double alpha, qpinv_qmat* X, void* hip_stream);
 
-/* Scaling features of A (used by ALPHA_POWER / ALPHA_LEARNED) into host out[6]:
+/* Scaling features of A (used by ALPHA_POWER / ALPHA_LEARNED) into host out[7]:
  *   {sigma1_est^2 (power_steps steps on A^H A from the SplitMix64 start vector, seed power_seed),
- *    ||A||_F, ||A||_1, ||A||_inf, rows, cols}.
+ *    ||A||_F, ||A||_1, ||A||_inf, rows, cols, the estimate of the step before the last}.
  * `power_steps` <= 0 uses the context option.  Errors: EINVAL, ENONFINITE, EHIP. */
-int qpinv_features(qpinv_ctx* ctx, const qpinv_qmat* A, int power_steps, double out[6], void* hip_stream);
+int qpinv_features(qpinv_ctx* ctx, const qpinv_qmat* A, int power_steps, double out[7], void* hip_stream);
+
+/* ---------------------------------------------------------------------------------- learned scaling
+ * A small network predicts mu = alpha * sigma1_est^2 for X_0 = alpha A^H from seven raw features per
+ * matrix, given as rows of 7 doubles (sigma1_est^2, previous estimate, ||A||_F, ||A||_1, ||A||_inf,
+ * rows, cols) -- the order qpinv_features reports them in, with the previous estimate moved second.
+ * ALPHA_LEARNED solves use it once a network is loaded (trained or set); the predicted mu is clamped
+ * into [sigma1_est^2 / min(||A||_F^2, ||A||_1 ||A||_inf), 1.9] (Theorem 1's interval as far as cheap
+ * bounds certify it), and the classical alpha = 1/sigma1_est^2 replaces it when ||I - X_0 A||_2 > 1 or
+ * the iteration diverges.  All arrays below are DEVICE arrays unless marked host. */
+
+/* (Re)initialise the network weights (Xavier-uniform, SplitMix64 stream `seed`) and the optimiser. */
+int qpinv_mlp_init(qpinv_ctx* ctx, uint64_t seed);
+
+/* Standardisation of the network inputs from `count` raw feature rows.  Errors: EINVAL, EHIP. */
+int qpinv_mlp_fit_normalization(qpinv_ctx* ctx, const double* raw, int count, void* hip_stream);
+
+/* One Adam step (lr) on the minibatch rows idx[0..batch) (idx may be NULL: rows 0..batch) of raw
+ * features and targets y = log(mu); batch <= 1024.  *loss (host) receives the minibatch mean squared
+ * error before the step.  Errors: EINVAL, EHIP. */
+int qpinv_mlp_train_step(qpinv_ctx* ctx, const double* raw, const double* target, const int* idx, int batch,
+                         double lr, double* loss, void* hip_stream);
+
+/* Gradient of the minibatch loss with respect to the parameters (FP32, qpinv_mlp_num_params entries)
+ * into grad, without changing the weights; *loss as above.  Errors: EINVAL, EHIP. */
+int qpinv_mlp_gradient(qpinv_ctx* ctx, const double* raw, const double* target, int batch, float* grad, double* loss,
+                       void* hip_stream);
+
+/* mu = exp(network output) for `count` raw rows into mu.  Errors: EINVAL, EHIP. */
+int qpinv_mlp_predict(qpinv_ctx* ctx, const double* raw, int count, double* mu, void* hip_stream);
+
+/* Number of parameters, and get/set of the parameters followed by the standardisation (mean[10],
+ * std[10]) as host floats (n = qpinv_mlp_num_params() + 20).  get returns the required n. */
+int qpinv_mlp_num_params(void);
+int qpinv_mlp_get_params(qpinv_ctx* ctx, float* host, int n);
+int qpinv_mlp_set_params(qpinv_ctx* ctx, const float* host, int n);
+
+/* Training labels from spectra (Theorem 1's proof: X_0 = alpha A^H keeps every iterate V diag U^H, so
+ * each singular value s_i follows rho <- g(rho) from rho = 1 - alpha s_i^2, with g the method's residual
+ * map from its convergence theorem).  For matrix b with singular values spectra[offsets[b] ..
+ * offsets[b+1]) the iteration count J(alpha) to ||AXA - A||_F / ||A||_F <= tol is evaluated on `ngrid`
+ * points mu geometric in [mu_lo, mu_hi] (alpha = mu / s_max^2); the label is the point nearest
+ * mu_target of the longest run of grid points attaining the minimum, reported relative to s1sq_est[b]
+ * as mu_out[b] = alpha* s1sq_est[b]; j_best[b] is that minimum and j_classical[b] the count of
+ * alpha = 1/s1sq_est[b] (max_iter + 1 when not reached; max_iter <= 64).  Errors: EINVAL, EHIP. */
+int qpinv_spectral_labels(qpinv_ctx* ctx, int method, int order, const double* spectra, const int* offsets, int count,
+                          const double* s1sq_est, double tol, int max_iter, int ngrid, double mu_lo, double mu_hi,
+                          double mu_target, double* mu_out, int* j_best, int* j_classical, void* hip_stream);
 
 /* Time every tile configuration of the product for shape (M, N, K) in `gemm_prec` and remember the
  * fastest for later solves on this context.  best_ms (host, may be NULL) receives its time.

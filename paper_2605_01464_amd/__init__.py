@@ -86,6 +86,15 @@ def _load() -> ctypes.CDLL:
         "qpinv_tile_config_name": (ctypes.c_char_p, [I, I]),
         "qpinv_controller_replay": (I, [I, D, I, DP, DP, DP, ctypes.POINTER(ctypes.c_int)]),
         "qpinv_gemm_stats": (I, [P, DP, I]),
+        "qpinv_mlp_init": (I, [P, ctypes.c_uint64]),
+        "qpinv_mlp_fit_normalization": (I, [P, P, I, P]),
+        "qpinv_mlp_train_step": (I, [P, P, P, P, I, D, DP, P]),
+        "qpinv_mlp_gradient": (I, [P, P, P, I, P, DP, P]),
+        "qpinv_mlp_predict": (I, [P, P, I, P, P]),
+        "qpinv_mlp_num_params": (I, []),
+        "qpinv_mlp_get_params": (I, [P, ctypes.POINTER(ctypes.c_float), I]),
+        "qpinv_mlp_set_params": (I, [P, ctypes.POINTER(ctypes.c_float), I]),
+        "qpinv_spectral_labels": (I, [P, I, I, P, P, I, P, D, I, I, D, D, D, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -204,7 +213,7 @@ def qpinv_x0(ctx, A, alpha, X, stream=None) -> int:
 
 
 def qpinv_features(ctx, A, power_steps=0, stream=None):
-    out = (ctypes.c_double * 6)()
+    out = (ctypes.c_double * 7)()
     st = _lib.qpinv_features(ctx, ctypes.byref(qmat(A)), int(power_steps), out, _stream(stream))
     return st, tuple(out)
 
@@ -232,6 +241,60 @@ def qpinv_gemm_stats(ctx, max_rows=32):
     rows = [dict(prec=int(out[5 * i]), cfg=int(out[5 * i + 1]), launches=int(out[5 * i + 2]),
                  flops=out[5 * i + 3], ms=out[5 * i + 4]) for i in range(n)]
     return OK, rows
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def qpinv_mlp_init(ctx, seed: int) -> int:
+    return _lib.qpinv_mlp_init(ctx, ctypes.c_uint64(seed))
+
+
+def qpinv_mlp_fit_normalization(ctx, raw, stream=None) -> int:
+    return _lib.qpinv_mlp_fit_normalization(ctx, _ptr(raw), int(raw.shape[0]), _stream(stream))
+
+
+def qpinv_mlp_train_step(ctx, raw, target, idx, batch, lr, stream=None):
+    loss = ctypes.c_double(0.0)
+    st = _lib.qpinv_mlp_train_step(ctx, _ptr(raw), _ptr(target), _ptr(idx), int(batch), float(lr),
+                                   ctypes.byref(loss), _stream(stream))
+    return st, loss.value
+
+
+def qpinv_mlp_gradient(ctx, raw, target, grad, stream=None):
+    loss = ctypes.c_double(0.0)
+    st = _lib.qpinv_mlp_gradient(ctx, _ptr(raw), _ptr(target), int(raw.shape[0]), _ptr(grad), ctypes.byref(loss),
+                                 _stream(stream))
+    return st, loss.value
+
+
+def qpinv_mlp_predict(ctx, raw, mu, stream=None) -> int:
+    return _lib.qpinv_mlp_predict(ctx, _ptr(raw), int(raw.shape[0]), _ptr(mu), _stream(stream))
+
+
+def qpinv_mlp_num_params() -> int:
+    return _lib.qpinv_mlp_num_params()
+
+
+def qpinv_mlp_get_params(ctx):
+    n = qpinv_mlp_num_params() + 20
+    buf = (ctypes.c_float * n)()
+    st = _lib.qpinv_mlp_get_params(ctx, buf, n)
+    return (st if st < 0 else OK), list(buf)
+
+
+def qpinv_mlp_set_params(ctx, values) -> int:
+    buf = (ctypes.c_float * len(values))(*values)
+    return _lib.qpinv_mlp_set_params(ctx, buf, len(values))
+
+
+def qpinv_spectral_labels(ctx, method, order, spectra, offsets, s1sq_est, tol, max_iter, ngrid, mu_lo, mu_hi,
+                          mu_target, mu_out, j_best, j_classical, stream=None) -> int:
+    return _lib.qpinv_spectral_labels(ctx, method, order, _ptr(spectra), _ptr(offsets), int(s1sq_est.shape[0]),
+                                      _ptr(s1sq_est), float(tol), int(max_iter), int(ngrid), float(mu_lo),
+                                      float(mu_hi), float(mu_target), _ptr(mu_out), _ptr(j_best), _ptr(j_classical),
+                                      _stream(stream))
 
 
 def qpinv_controller_replay(stop, tol, d_abs, x_norm, e1_rel=None):
@@ -357,7 +420,12 @@ def features(ctx: Context, A, power_steps=0, stream=None):
     st, out = qpinv_features(ctx.handle, A, power_steps, stream)
     _err(st, "qpinv_features")
     return {"sigma1_sq": out[0], "fro": out[1], "norm1": out[2], "norminf": out[3], "m": int(out[4]),
-            "n": int(out[5])}
+            "n": int(out[5]), "sigma1_sq_prev": out[6]}
+
+
+def raw_features(f: dict):
+    """The network's raw feature row (s1sq, s1sq_prev, fro, norm1, norminf, m, n) from features()."""
+    return [f["sigma1_sq"], f["sigma1_sq_prev"], f["fro"], f["norm1"], f["norminf"], float(f["m"]), float(f["n"])]
 
 
 def x0(ctx: Context, A, alpha, out_dtype=None, stream=None):

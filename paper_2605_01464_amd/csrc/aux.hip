@@ -237,13 +237,17 @@ __global__ void __launch_bounds__(256) power_init_kernel(double* v, int n, uint6
   if (e < 4 * n) v[e] = (double)(splitmix64((uint64_t)e, seed) >> 11) * 0x1p-52 - 1.0;
 }
 
-// out[0] = sum of squares of x[0..len)
-__global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ x, int64_t len, double* __restrict__ out) {
+// out[0] = sum of squares of x[0..len); if prev != nullptr the old out[0] is moved to prev[0] first
+__global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ x, int64_t len, double* __restrict__ out,
+                                                    double* __restrict__ prev) {
   __shared__ double sh[256];
   double a = 0.0;
   for (int64_t i = threadIdx.x; i < len; i += 256) a += x[i] * x[i];
   a = block_sum256(a, sh);
-  if (threadIdx.x == 0) out[0] = a;
+  if (threadIdx.x == 0) {
+    if (prev) prev[0] = out[0];
+    out[0] = a;
+  }
 }
 
 // w_i = (A v)_i / sqrt(*vn2): one workgroup per row.  v and w are plane-major (4 x len).
@@ -311,13 +315,17 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const double* __restrict
   out[e] = a;
 }
 
+__global__ void copy1_kernel(const double* src, double* dst) {
+  if (threadIdx.x == 0) dst[0] = src[0];
+}
+
 int64_t power_work_doubles(int64_t m, int64_t n) { return 4 * n + 4 * m + (int64_t)col_row_blocks(m) * 4 * n + 8; }
 
 template <class T>
 void power_sigma1_sq(const QView& A, int64_t m, int64_t n, int steps, uint64_t seed, double* lambda, double* work,
                      hipStream_t s) {
   if (m == 0 || n == 0 || steps < 1) {
-    zero_doubles(lambda, 1, s);
+    zero_doubles(lambda, 2, s);
     return;
   }
   double* v = work;
@@ -329,14 +337,15 @@ void power_sigma1_sq(const QView& A, int64_t m, int64_t n, int steps, uint64_t s
   hipLaunchKernelGGL(power_init_kernel, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, s, v, (int)n, (uint64_t)seed);
   QP_HIP(hipGetLastError());
   for (int k = 0; k < steps; ++k) {
-    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(256), 0, s, v, 4 * n, vn2);
+    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(256), 0, s, v, 4 * n, vn2, (double*)nullptr);
     hipLaunchKernelGGL((gemv_n_kernel<T>), dim3((unsigned)m), dim3(256), 0, s, Ap, A.ld, A.ps, (int)m, (int)n, v, vn2, w);
-    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(256), 0, s, w, 4 * m, lambda);
+    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(256), 0, s, w, 4 * m, lambda, k > 0 ? lambda + 1 : (double*)nullptr);
     hipLaunchKernelGGL((gemv_h_kernel<T>), dim3((unsigned)((n + 255) / 256), (unsigned)nrb), dim3(256), 0, s, Ap, A.ld,
                        A.ps, (int)m, (int)n, w, zpart);
     hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, s, zpart, nrb, 4 * n, v);
     QP_HIP(hipGetLastError());
   }
+  if (steps == 1) hipLaunchKernelGGL(copy1_kernel, dim3(1), dim3(64), 0, s, lambda, lambda + 1);
 }
 
 template void power_sigma1_sq<float>(const QView&, int64_t, int64_t, int, uint64_t, double*, double*, hipStream_t);

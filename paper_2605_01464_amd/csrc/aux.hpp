@@ -22,8 +22,8 @@ template <class T>
 void norms(const QView& A, int64_t m, int64_t n, double* out, double* work, hipStream_t s);
 
 // Power iteration on A^H A (k steps) from the SplitMix64 start vector; writes the last Rayleigh
-// quotient ||A v||^2 (v unit) to *lambda (device double).  `work` must hold
-// power_work_doubles(m, n) doubles.
+// quotient ||A v||^2 (v unit) to lambda[0] and the one of the step before to lambda[1] (device
+// doubles; equal when steps == 1).  `work` must hold power_work_doubles(m, n) doubles.
 template <class T>
 void power_sigma1_sq(const QView& A, int64_t m, int64_t n, int steps, uint64_t seed, double* lambda,
                      double* work, hipStream_t s);

@@ -291,13 +291,88 @@ int qpinv_x0(qpinv_ctx* c, const qpinv_qmat* A, double alpha, qpinv_qmat* X, voi
   });
 }
 
-int qpinv_features(qpinv_ctx* c, const qpinv_qmat* A, int power_steps, double out[6], void* hip_stream) {
+int qpinv_features(qpinv_ctx* c, const qpinv_qmat* A, int power_steps, double out[7], void* hip_stream) {
   return guarded([&]() {
     qp::Ctx& cx = ctx_of(c);
     if (!out) throw qp::Error(QPINV_EINVAL, "null output");
     qp::validate(A, "A");
     if (A->rows == 0 || A->cols == 0) throw qp::Error(QPINV_EINVAL, "features of an empty matrix");
     qp::features(cx, qp::from_abi(*A), power_steps, out, stream_of(hip_stream));
+    return QPINV_OK;
+  });
+}
+
+int qpinv_mlp_init(qpinv_ctx* c, uint64_t seed) {
+  return guarded([&]() {
+    qp::mlp_init(ctx_of(c), seed);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_mlp_fit_normalization(qpinv_ctx* c, const double* raw, int count, void* hip_stream) {
+  return guarded([&]() {
+    if (!raw || count < 1) throw qp::Error(QPINV_EINVAL, "need raw features");
+    qp::mlp_fit_normalization(ctx_of(c), raw, count, stream_of(hip_stream));
+    return QPINV_OK;
+  });
+}
+
+int qpinv_mlp_train_step(qpinv_ctx* c, const double* raw, const double* target, const int* idx, int batch, double lr,
+                         double* loss, void* hip_stream) {
+  return guarded([&]() {
+    if (!raw || !target || batch < 1 || batch > 1024 || !(lr > 0.0)) throw qp::Error(QPINV_EINVAL, "bad training step");
+    const double l = qp::mlp_train_step(ctx_of(c), raw, target, idx, batch, lr, nullptr, stream_of(hip_stream));
+    if (loss) *loss = l;
+    return QPINV_OK;
+  });
+}
+
+int qpinv_mlp_gradient(qpinv_ctx* c, const double* raw, const double* target, int batch, float* grad, double* loss,
+                       void* hip_stream) {
+  return guarded([&]() {
+    if (!raw || !target || !grad || batch < 1 || batch > 1024) throw qp::Error(QPINV_EINVAL, "bad gradient request");
+    const double l = qp::mlp_train_step(ctx_of(c), raw, target, nullptr, batch, 1.0, grad, stream_of(hip_stream));
+    if (loss) *loss = l;
+    return QPINV_OK;
+  });
+}
+
+int qpinv_mlp_predict(qpinv_ctx* c, const double* raw, int count, double* mu, void* hip_stream) {
+  return guarded([&]() {
+    if (!raw || !mu || count < 0) throw qp::Error(QPINV_EINVAL, "bad prediction request");
+    qp::mlp_predict(ctx_of(c), raw, count, mu, stream_of(hip_stream));
+    return QPINV_OK;
+  });
+}
+
+int qpinv_mlp_num_params(void) { return qp::mlp_num_params(); }
+
+int qpinv_mlp_get_params(qpinv_ctx* c, float* host, int n) {
+  int need = 0;
+  const int st = guarded([&]() {
+    need = qp::mlp_get(ctx_of(c), host, n);
+    return QPINV_OK;
+  });
+  return st == QPINV_OK ? need : st;
+}
+
+int qpinv_mlp_set_params(qpinv_ctx* c, const float* host, int n) {
+  return guarded([&]() {
+    qp::mlp_set(ctx_of(c), host, n);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_spectral_labels(qpinv_ctx* c, int method, int order, const double* spectra, const int* offsets, int count,
+                          const double* s1sq_est, double tol, int max_iter, int ngrid, double mu_lo, double mu_hi,
+                          double mu_target, double* mu_out, int* j_best, int* j_classical, void* hip_stream) {
+  return guarded([&]() {
+    qp::check_method(method, order);
+    if (count < 0 || (count > 0 && (!spectra || !offsets || !s1sq_est || !mu_out || !j_best || !j_classical)) ||
+        !(tol > 0.0) || max_iter < 1 || max_iter > 64)
+      throw qp::Error(QPINV_EINVAL, "bad label request");
+    qp::spectral_labels(ctx_of(c), method, order, spectra, offsets, count, s1sq_est, tol, max_iter, ngrid, mu_lo, mu_hi,
+                        mu_target, mu_out, j_best, j_classical, stream_of(hip_stream));
     return QPINV_OK;
   });
 }

@@ -13,6 +13,7 @@
 #include "aux.hpp"
 #include "batched.hpp"
 #include "controller.hpp"
+#include "mlp.hpp"
 #include "solver.hpp"
 
 namespace qp {
@@ -223,6 +224,37 @@ void check_method(int method, int& order) {
       break;
     default:
       throw Error(QPINV_EINVAL, "unknown method");
+  }
+}
+
+// Local order p of a method (R_{j+1} ~ R_j^p): NS 2, hyperpower p, QSAI 10, QHPI19 19, and for
+// QRAPID(N) nu_N = 11 a_{N-1} + 7 a_{N-2} + 1 with the Fibonacci numbers a (a_{-1} = 1, a_{-2} = -1).
+static int convergence_order(int method, int order) {
+  switch (method) {
+    case QPINV_NS: return 2;
+    case QPINV_HPI: return order;
+    case QPINV_QSAI: return 10;
+    case QPINV_QHPI19: return 19;
+    default: {
+      auto fib = [](int k) {
+        long a = 0, b = 1;  // a_0, a_1
+        if (k >= 0) {
+          for (int i = 0; i < k; ++i) {
+            const long t = a + b;
+            a = b;
+            b = t;
+          }
+          return a;
+        }
+        for (int i = 0; i < -k; ++i) {
+          const long t = b - a;
+          b = a;
+          a = t;
+        }
+        return a;
+      };
+      return (int)(11 * fib(order - 1) + 7 * fib(order - 2) + 1);
+    }
   }
 }
 
@@ -546,13 +578,14 @@ void norms_host(Ctx& c, const Mat& M, double h[4], hipStream_t s) {
   std::memcpy(h, c.hsc, sizeof(double) * 4);
 }
 
-double power_host(Ctx& c, const Mat& M, int steps, hipStream_t s) {
+double power_host(Ctx& c, const Mat& M, int steps, hipStream_t s, double* prev = nullptr) {
   double* work = static_cast<double*>(c.ws.get("powwork", sizeof(double) * power_work_doubles(M.rows, M.cols)));
   if (M.dtype == QPINV_F32)
     power_sigma1_sq<float>(M.v, M.rows, M.cols, steps, c.opt.power_seed, c.dsc + 16, work, s);
   else
     power_sigma1_sq<double>(M.v, M.rows, M.cols, steps, c.opt.power_seed, c.dsc + 16, work, s);
-  to_host(c, c.dsc + 16, 1, s);
+  to_host(c, c.dsc + 16, 2, s);
+  if (prev) *prev = c.hsc[1];
   return c.hsc[0];
 }
 
@@ -688,10 +721,38 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
 
   // scaling
   double alpha = 0.0;
+  double alpha_classical = 0.0;
+  bool learned = false;
   if (scaling == QPINV_ALPHA_POWER || scaling == QPINV_ALPHA_LEARNED) {
-    inf.sigma1_sq_est = power_host(c, A0, c.opt.power_steps, s);
+    double prev = 0.0;
+    inf.sigma1_sq_est = power_host(c, A0, c.opt.power_steps, s, &prev);
     double mu = am > 0.0 ? am : 1.0;
-    if (scaling == QPINV_ALPHA_LEARNED) inf.fallback_used = 1;  // network inference is wired in by the caller
+    alpha_classical = 1.0 / inf.sigma1_sq_est;
+    if (scaling == QPINV_ALPHA_LEARNED) {
+      if (!mlp_ready(c)) {
+        inf.fallback_used = 1;  // no network loaded: the classical alpha
+      } else {
+        // network input row (s1sq, s1sq_prev, fro, norm1, norminf, m, n) -> mu
+        double* raw = c.dsc + 48;
+        double* hraw = c.hsc + 48;
+        const double row[7] = {inf.sigma1_sq_est, prev, normA, nh[1], nh[2], (double)m, (double)n};
+        std::memcpy(hraw, row, sizeof(row));
+        QP_HIP(hipMemcpyAsync(raw, hraw, sizeof(row), hipMemcpyHostToDevice, s));
+        mlp_predict(c, raw, 1, c.dsc + 56, s);
+        to_host(c, c.dsc + 56, 1, s);
+        double mul = c.hsc[0];
+        // clamp into (0, 2/sigma_1^2) as far as cheap bounds allow: sigma_1 <= U = min(||A||_F,
+        // sqrt(||A||_1 ||A||_inf)) gives mu >= s1sq / U^2; above, mu <= 1.9
+        const double U2 = std::min(nh[0], nh[1] * nh[2]);
+        const double lo = inf.sigma1_sq_est / U2, hi = 1.9;
+        if (!std::isfinite(mul) || mul < lo || mul > hi) {
+          inf.alpha_clamped = 1;
+          mul = std::isfinite(mul) ? std::min(std::max(mul, lo), hi) : 1.0;
+        }
+        mu = mul;
+        learned = true;
+      }
+    }
     alpha = mu / inf.sigma1_sq_est;
     inf.mu_used = mu;
   } else if (scaling == QPINV_ALPHA_FROB) {
@@ -725,6 +786,8 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
   }
 
   StopController ctl(stop, tol);
+  const int p_order = convergence_order(method, order);
+  const double kF32Floor = 1e-6;  // relative error FP32 iterates cannot improve on
   std::vector<double> xnorm_hist(1, 0.0);  // ||X_j||_F by j (X_0 unknown = 0)
   int best_pair[2] = {-1, -1};             // buffer indices of X_{j*-1}, X_{j*}
   int best_j = -1;
@@ -759,8 +822,24 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     Mat R;
     const bool main_phase = p != P_BF16 && !(has_finish && ph == phases.size() - 1);
     const bool keep_R = main_phase && stop == STOP_GUARDED;
-    const bool want_R = (p == P_BF16) || keep_R;
+    // the classical alpha (mu = 1) carries no more risk than the default; only a larger learned mu is checked
+    const bool guard_R = learned && j == 0 && inf.mu_used > 1.0;
+    const bool want_R = (p == P_BF16) || keep_R || guard_R;
     chain(c, method, order, side, p, Adt, S->b[cur], S->b[nxt], red, s, want_R ? &R : nullptr);
+    if (guard_R) {
+      // Theorem 1: alpha is admissible iff every |1 - alpha sigma_i^2| < 1; R_0 = I - X_0 A (or I - A X_0)
+      // has exactly these eigenvalues (and 1 on the null space), so ||R_0||_2 > 1 means divergence
+      const double r0 = std::sqrt(std::max(0.0, power_host(c, R, 3, s)));
+      if (r0 > 1.0 + 1e-3) {
+        learned = false;
+        inf.fallback_used = 1;
+        alpha = alpha_classical;
+        inf.alpha_used = alpha;
+        inf.mu_used = 1.0;
+        x0_into(A_of(dt), alpha, S->b[cur], s);
+        continue;
+      }
+    }
     if (keep_R) {
       // keep R_{j} = residual of the iterate X_j this update started from (slot j % 2)
       const int slot = j % 2;
@@ -787,6 +866,29 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
               inf.final_dx_rel, rnorm);
 
     const bool diverged = !std::isfinite(d_abs) || !std::isfinite(xn) || xn * normA > 1e20;
+    if (diverged && learned) {
+      // the learned alpha failed: start over from the classical alpha
+      learned = false;
+      inf.fallback_used = 1;
+      alpha = alpha_classical;
+      inf.alpha_used = alpha;
+      inf.mu_used = 1.0;
+      dt = store_of(phases[0]);
+      ph = 0;
+      S = &set_of(dt);
+      cur = 0;
+      x0_into(A_of(dt), alpha, S->b[cur], s);
+      j = 0;
+      inf.iters_bf16 = inf.iters_f32 = inf.iters_f64 = 0;
+      ctl = StopController(stop, tol);
+      xnorm_hist.assign(1, 0.0);
+      best_pair[0] = best_pair[1] = -1;
+      best_j = -1;
+      rsave_j[0] = rsave_j[1] = -1;
+      rprev = -1.0;
+      d_prev_finish = -1.0;
+      continue;
+    }
     if (diverged) {
       status = QPINV_EDIVERGED;
       inf.stop_reason = QPINV_REASON_DIVERGED;
@@ -822,7 +924,10 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     if (has_finish && ph == phases.size() - 1) {
       const double d = xn > 0 ? d_abs / xn : 0.0;
       const int fin_it = inf.iters_f64;
-      if (d <= tol) {
+      // in the asymptotic regime the next change is about d^p: once that is below tol the FP64 iterate
+      // just computed is converged and a confirming step is not needed
+      const bool predicted = d <= 0.5 && std::pow(d, (double)p_order) <= tol;
+      if (d <= tol || predicted) {
         inf.stop_reason = QPINV_REASON_TOL;
         returned_buf = nxt;
         returned_j = j;
@@ -849,8 +954,13 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
       e1r = std::sqrt(std::max(0.0, e1_sq(c, p, Adt, S->b[nxt], s))) / normA;
       inf.e1_rel = e1r;
     }
-    const int dec = ctl.update(j, d_abs, xn, e1r);
+    int dec = ctl.update(j, d_abs, xn, e1r);
     int chosen_buf = -1, chosen_j = -1, reason = -1;
+    if (has_finish && (dec == D_CONTINUE || dec == D_NEWMIN)) {
+      // leave the FP32 phase once X_j sits at the FP32 floor: its error is about d^p (asymptotic regime)
+      const double d = xn > 0 ? d_abs / xn : 0.0;
+      if (d <= 0.5 && std::pow(d, (double)p_order) <= kF32Floor) dec = D_TOL;
+    }
     if (dec == D_DIVERGED) {
       status = QPINV_EDIVERGED;
       inf.stop_reason = QPINV_REASON_DIVERGED;
@@ -1103,11 +1213,11 @@ void residuals(Ctx& c, const qpinv_qmat* Aq, const qpinv_qmat* Xq, double E_abs[
   E_rel[3] = nXA > 0 ? E_abs[3] / nXA : 0.0;
 }
 
-void features(Ctx& c, const Mat& A, int steps, double out[6], hipStream_t s) {
+void features(Ctx& c, const Mat& A, int steps, double out[7], hipStream_t s) {
   double nh[4];
   norms_host(c, A, nh, s);
   if (nh[3] > 0) throw Error(QPINV_ENONFINITE, "A holds NaN or Inf");
-  out[0] = power_host(c, A, steps > 0 ? steps : c.opt.power_steps, s);
+  out[0] = power_host(c, A, steps > 0 ? steps : c.opt.power_steps, s, &out[6]);
   out[1] = std::sqrt(nh[0]);
   out[2] = nh[1];
   out[3] = nh[2];

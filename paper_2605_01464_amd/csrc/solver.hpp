@@ -93,7 +93,7 @@ int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A,
 
 void residuals(Ctx& c, const qpinv_qmat* A, const qpinv_qmat* X, double E_abs[4], double E_rel[4], hipStream_t s);
 
-void features(Ctx& c, const Mat& A, int steps, double out[6], hipStream_t s);
+void features(Ctx& c, const Mat& A, int steps, double out[7], hipStream_t s);
 
 // Per kernel (precision, tile configuration): rows of {prec, cfg, launches, flops, milliseconds} of the
 // timed product launches since the last call; returns the row count (at most max_rows) and resets.

@@ -10,21 +10,26 @@ a float64 array of shape (4, m, n), planes in the order (s, x, y, z).
 
 Construction of orthonormal quaternion factors.  The paper's experiments use unseeded Gaussian
 matrices (Section 4).  For matrices with a prescribed spectrum we need quaternion matrices with
-orthonormal columns.  We take a quaternion Gaussian G (m x r) and return its polar factor
-Q = G (G^H G)^{-1/2}, computed in the complex-adjoint form (Section 2: the 2m x 2n complex
-representation is an injective *-homomorphism, so the adjoint of the polar factor is the polar factor
-of the adjoint).  Q spans the same column space as the Q factor of a quaternion QR of G; the two
-differ by an r x r unitary right factor that depends on G, so both are Haar-distributed on the
-quaternion Stiefel manifold and A = U diag(s) V^H has the same distribution either way.
+orthonormal columns.
+  * stiefel(): the polar factor Q = G (G^H G)^{-1/2} of a quaternion Gaussian G (m x r), computed in the
+    complex-adjoint form (Section 2: the 2m x 2n complex representation is an injective
+    *-homomorphism, so the adjoint of the polar factor is the polar factor of the adjoint).  Q spans
+    the same column space as the Q factor of a quaternion QR of G; the two differ by an r x r unitary
+    right factor that depends on G, so both are Haar-distributed on the quaternion Stiefel manifold and
+    A = U diag(s) V^H has the same distribution either way.  O(m r^2); used for the 2048 x 1536 case.
+  * StructuredUnitary: U = C D_1 C D_2 C D_3 (orthonormal DCT-II and diagonals of random unit
+    quaternions), dense and applied in O(n^2 log n); used where an O(n^3) factor is too slow (the
+    4096 x 4096 case and the thousands of learned-scaling matrices).
 """
 from __future__ import annotations
 
 import numpy as np
 
 __all__ = [
-    "gaussian", "stiefel", "from_factors", "geometric", "round_f32",
+    "gaussian", "stiefel", "from_factors", "geometric", "round_f32", "StructuredUnitary",
+    "structured_spectral", "structured_pinv", "mp_quantiles",
     "c1_instance", "c2_instance", "c3_instance", "c4_sizes", "c4_instance",
-    "c5_instance", "small_spectral_instance",
+    "c5_spectrum", "c5_sample", "small_spectral_instance",
 ]
 
 
@@ -65,19 +70,83 @@ def stiefel(seed: int, m: int, r: int) -> np.ndarray:
     return _from_cplx(Qc)
 
 
-def householder_unitary(seed: int, n: int, k: int = 64) -> np.ndarray:
-    """n x n unitary quaternion matrix: the product of k quaternion Householder reflectors
-    H = I - 2 v v^H / (v^H v), v with iid N(0,1) components.  Built in the complex-adjoint form, where a
-    reflector is the rank-2 update I - 2 chi(v) chi(v)^H / ||v||^2 (O(n^2) each), so large factors cost
-    seconds instead of an O(n^3) orthonormalisation.  Used for square matrices with a prescribed spectrum."""
-    rng = np.random.default_rng(seed)
-    Q = np.eye(2 * n, dtype=np.complex128)
-    for _ in range(k):
-        v = rng.standard_normal((4, n, 1))
-        vc = _to_cplx(v)  # 2n x 2
-        nv2 = float(np.sum(v * v))
-        Q -= (2.0 / nv2) * (Q @ vc) @ vc.conj().T
-    return _from_cplx(Q)
+#: threads of the DCTs in StructuredUnitary (-1: all cores; a process pool sets 1 per worker)
+DCT_WORKERS = -1
+
+
+def _unit_quaternions(rng, n: int) -> np.ndarray:
+    """(4, n) random unit quaternions (normalised Gaussian 4-vectors: uniform on the 3-sphere)."""
+    q = rng.standard_normal((4, n))
+    return q / np.sqrt(np.sum(q * q, axis=0, keepdims=True))
+
+
+def _left_diag(q: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """diag(q) M: row i of the quaternion matrix M multiplied on the left by the quaternion q_i."""
+    a = [q[t][:, None] for t in range(4)]
+    b = M
+    return np.stack([a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3],
+                     a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2],
+                     a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1],
+                     a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0]])
+
+
+def _conj(q: np.ndarray) -> np.ndarray:
+    return np.stack([q[0], -q[1], -q[2], -q[3]])
+
+
+class StructuredUnitary:
+    """Dense random unitary U = C D_1 C D_2 C D_3 of order n: C is the orthonormal DCT-II (real, so it acts
+    on each plane), D_i = diag of random unit quaternions.  U and U^H are applied to quaternion matrices in
+    O(n^2 log n) without forming U; for square matrices with a prescribed spectrum at sizes where an
+    O(n^3) orthonormalisation is too slow."""
+
+    def __init__(self, seed: int, n: int, rounds: int = 3):
+        rng = np.random.default_rng(seed)
+        self.n = n
+        self.d = [_unit_quaternions(rng, n) for _ in range(rounds)]
+
+    @staticmethod
+    def _dct(M: np.ndarray, inverse: bool) -> np.ndarray:
+        from scipy.fft import dct, idct
+
+        return (idct if inverse else dct)(M, type=2, norm="ortho", axis=1, workers=DCT_WORKERS)
+
+    def apply(self, M: np.ndarray) -> np.ndarray:
+        """U M (M is n x k)."""
+        for q in reversed(self.d):
+            M = self._dct(_left_diag(q, M), inverse=True)
+        return M
+
+    def apply_h(self, M: np.ndarray) -> np.ndarray:
+        """U^H M."""
+        for q in self.d:
+            M = _left_diag(_conj(q), self._dct(M, inverse=False))
+        return M
+
+
+def _qh(M: np.ndarray) -> np.ndarray:
+    return np.stack([M[0].T, -M[1].T, -M[2].T, -M[3].T])
+
+
+def structured_spectral(seeds, m: int, n: int, s: np.ndarray) -> np.ndarray:
+    """A = U [diag(s) 0; 0 0] V^H with U (m x m), V (n x n) structured random unitaries; len(s) <= min(m, n)."""
+    U = StructuredUnitary(seeds[0], m)
+    V = StructuredUnitary(seeds[1], n)
+    S = np.zeros((4, m, n))
+    r = len(s)
+    S[0, np.arange(r), np.arange(r)] = s
+    # A = U S V^H = U (V S^H)^H
+    return U.apply(_qh(V.apply(_qh(S))))
+
+
+def structured_pinv(seeds, m: int, n: int, s: np.ndarray) -> np.ndarray:
+    """The pseudoinverse V [diag(1/s) 0; 0 0] U^H of structured_spectral(seeds, m, n, s)."""
+    U = StructuredUnitary(seeds[0], m)
+    V = StructuredUnitary(seeds[1], n)
+    S = np.zeros((4, n, m))
+    r = len(s)
+    S[0, np.arange(r), np.arange(r)] = 1.0 / np.asarray(s)
+    return V.apply(_qh(U.apply(_qh(S))))
 
 
 def from_factors(U: np.ndarray, s: np.ndarray, V: np.ndarray) -> np.ndarray:
@@ -128,20 +197,18 @@ def c2_instance(m: int = 2048, n: int = 1536, r: int = 1024, seeds=(100, 101),
     return {"A": round_f32(A64), "A64": A64, "U": U, "s": s, "V": V}
 
 
-def c3_instance(n: int = 4096, seeds=(200, 201), cond: float = 1e3, reflectors: int = 64) -> dict:
+def c3_instance(n: int = 4096, seeds=(200, 201), cond: float = 1e3) -> dict:
     """Square case with condition number `cond`, geometric spectrum, component variance ~1.
 
-    Factors are products of `reflectors` random quaternion Householder reflectors (see
-    householder_unitary).  c = 2n / sqrt(sum s_i^2) makes the mean squared component
-    c^2 sum s^2 / (4 n^2) equal to 1.
+    A = U diag(s) V^H with structured random unitaries (StructuredUnitary); c = 2n / sqrt(sum s_i^2)
+    makes the mean squared component c^2 sum s^2 / (4 n^2) equal to 1.  ``seeds`` name the factors
+    (the pseudoinverse is structured_pinv(seeds, n, n, s)).
     """
-    U = householder_unitary(seeds[0], n, reflectors)
-    V = householder_unitary(seeds[1], n, reflectors)
     s = geometric(n, 1.0, 1.0 / cond)
     c = 2.0 * n / np.sqrt(np.sum(s * s))
     s = c * s
-    A64 = from_factors(U, s, V)
-    return {"A": round_f32(A64), "A64": A64, "U": U, "s": s, "V": V}
+    A64 = structured_spectral(seeds, n, n, s)
+    return {"A": round_f32(A64), "A64": A64, "s": s, "seeds": tuple(seeds)}
 
 
 def c4_sizes(count: int = 512, lo: int = 32, hi: int = 256, seed: int = 300) -> np.ndarray:
@@ -160,42 +227,72 @@ def c4_instance(b: int, sizes: np.ndarray, seed0: int = 300, max_cond: float = 1
         seed += 1000
 
 
-def c5_instance(seed: int, m: int, n: int, family: str) -> dict:
-    """One learned-scaling matrix: spectrum family in {geometric, clustered, lowrank}.
+def mp_quantiles(count: int, m: int, n: int, scale: float) -> np.ndarray:
+    """`count` singular values at the midpoint quantiles of the Marchenko--Pastur law of an m x n matrix
+    whose entries have variance scale^2 (support scale (sqrt M -+ sqrt N), M = max, N = min), descending."""
+    M, N = max(m, n), min(m, n)
+    c = N / M
+    lo, hi = (1 - np.sqrt(c)) ** 2, (1 + np.sqrt(c)) ** 2
+    x = np.linspace(lo, hi, 20001)
+    dens = np.sqrt(np.clip((hi - x) * (x - lo), 0, None)) / x
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (dens[1:] + dens[:-1]) * np.diff(x))])
+    cdf /= cdf[-1]
+    q = (np.arange(count) + 0.5) / count
+    lam = np.interp(q, cdf, x)  # eigenvalues of W W^H / M
+    return np.sort(scale * np.sqrt(M * lam))[::-1]
+
+
+C5_FAMILIES = ("geometric", "clustered", "lowrank")
+
+
+def c5_spectrum(seed: int, m: int, n: int, family: str) -> np.ndarray:
+    """Singular values (descending, length min(m, n)) of one learned-scaling matrix.
 
     geometric: s_i = kappa^(-(i-1)/(r-1)), log10 kappa ~ U[1,4].
     clustered: 2..5 levels 10^-U[0,3] (top level 1); each s_i takes a uniform level, +-1% log-normal jitter.
-    lowrank:   rank k ~ U{2..floor(r/4)} with values 10^-U[0,1] (top 1) plus a Gaussian E whose
-               planes have std 1e-3 / (2 (sqrt m + sqrt n)), so ||E||_2 ~ 1e-3; such instances are
-               returned with ``s = None`` (the spectrum is only known after the noise is added).
+    lowrank:   k ~ U{2..floor(r/4)} values 10^-U[0,1] (top 1) over a noise floor: the singular values of
+               an m x n quaternion Gaussian with component std 1e-3 / (2 (sqrt m + sqrt n)) (so its norm
+               is about 1e-3), taken at their Marchenko--Pastur quantiles.
     """
     rng = np.random.default_rng(seed)
     r = min(m, n)
-    U = stiefel(seed * 2 + 1, m, r)
-    V = stiefel(seed * 2 + 2, n, r)
     if family == "geometric":
         kappa = 10.0 ** rng.uniform(1.0, 4.0)
-        s = geometric(r, 1.0, 1.0 / kappa)
-        return {"A": from_factors(U, s, V), "s": s, "family": family}
+        return geometric(r, 1.0, 1.0 / kappa)
     if family == "clustered":
         c = int(rng.integers(2, 6))
         levels = np.concatenate([[1.0], 10.0 ** (-rng.uniform(0.0, 3.0, size=c - 1))])
         idx = rng.integers(0, c, size=r)
         idx[0] = 0
         s = levels[idx] * np.exp(0.01 * rng.standard_normal(r))
-        s = np.sort(s)[::-1]
-        return {"A": from_factors(U, s, V), "s": s, "family": family}
+        return np.sort(s)[::-1]
     if family == "lowrank":
         k = int(rng.integers(2, max(3, r // 4 + 1)))
         sv = np.sort(10.0 ** (-rng.uniform(0.0, 1.0, size=k)))[::-1]
         sv[0] = 1.0
-        s = np.zeros(r)
-        s[:k] = sv
-        L = from_factors(U, s, V)
         sig_e = 1e-3 / (2.0 * (np.sqrt(m) + np.sqrt(n)))
-        E = sig_e * rng.standard_normal((4, m, n))
-        return {"A": L + E, "s": None, "family": family}
+        noise = mp_quantiles(r - k, m, n, 2.0 * sig_e) if r > k else np.zeros(0)
+        return np.concatenate([sv, noise])
     raise ValueError(f"unknown family {family!r}")
+
+
+def c5_sample(seed: int, size_range=(64, 512), shape=None, max_cond: float = 1e5) -> dict:
+    """One learned-scaling matrix A = U diag(s) V^H (structured random factors): family uniform over
+    C5_FAMILIES, m, n iid uniform in size_range unless `shape` is given, redrawn (seed + 1000) while
+    cond > max_cond.  Returns A (float64 planes), s, family, m, n."""
+    t = 0
+    while True:
+        rng = np.random.default_rng(seed + 1000 * t)
+        family = C5_FAMILIES[int(rng.integers(0, 3))]
+        if shape is None:
+            m, n = (int(v) for v in rng.integers(size_range[0], size_range[1] + 1, size=2))
+        else:
+            m, n = shape
+        s = c5_spectrum(seed * 7 + 1000 * t + 3, m, n, family)
+        if s[-1] > 0 and s[0] / s[-1] <= max_cond:
+            A = structured_spectral((2 * seed + 1 + 1000 * t, 2 * seed + 2 + 1000 * t), m, n, s)
+            return {"A": A, "s": s, "family": family, "m": m, "n": n}
+        t += 1
 
 
 def small_spectral_instance(seed: int, m: int, n: int, s: np.ndarray) -> dict:
