@@ -47,6 +47,33 @@ def qgemm_tflops(q, ctx, n, prec="f32", reps=10):
     return 32.0 * n ** 3 / (ms * 1e-3) / 1e12, ms
 
 
+KERNEL_SOURCES = ("common.hpp", "qgemm.hpp", "qgemm_kern.hpp", "qgemm.hip")
+
+
+def measured_traffic(config_name):
+    """HBM bytes per launch of the product kernel `config_name`, from the FETCH_SIZE / WRITE_SIZE counter
+    summaries under profiles/ (copy-kernel calibrated).  None unless the product kernel sources still hash to
+    the value recorded with the counters, i.e. the kernel has not changed since they were taken."""
+    import glob
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_01464_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))):
+        with open(path) as fh:
+            m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("config") == config_name and rec.get("kernel_sources_sha256") == digest:
+            return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +134,7 @@ def main() -> int:
     dom = max(rows, key=lambda r: r["ms"])
     prec_name = {0: "f64", 1: "f32", 2: "bf16"}[dom["prec"]]
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    dom_name = q.qpinv_tile_config_name(dom["prec"], dom["cfg"])
     gemm_ms = sum(r["ms"] for r in rows)
     info = infos[-1]
 
@@ -127,8 +155,9 @@ def main() -> int:
                                f"{args.method.upper()} FP32, power-iteration alpha, guarded stop tol 1e-6",
                    "m": m, "n": n, "rank": 1024, "method": args.method, "precision": "f32"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec_name], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[prec_name], "traffic": None,
-                     "kernel": f"qgemm_kernel {q.qpinv_tile_config_name(dom['prec'], dom['cfg'])}",
+                     "frac": achieved / PEAK[prec_name], "traffic": measured_traffic(dom_name),
+                     "traffic_unit": "bytes/launch",
+                     "kernel": f"qgemm_kernel {dom_name}",
                      "launches_per_step": dom["launches"] / args.steps,
                      "flops_per_launch": dom["flops"] / max(dom["launches"], 1),
                      "avg_launch_ms": dom["ms"] / max(dom["launches"], 1),

@@ -66,8 +66,11 @@ typedef enum {
                               (option power_steps, default 8); mu = alpha_or_mu if > 0 else 1 */
   QPINV_ALPHA_FROB = 1,    /* alpha = 1 / ||A||_F^2 (Section 4 experimental setup) */
   QPINV_ALPHA_GIVEN = 2,   /* alpha = alpha_or_mu (e.g. 1/sigma_max(A^C)^2 of Algorithms 1-3) */
-  QPINV_ALPHA_LEARNED = 3, /* mu predicted by the scaling network (qpinv_mlp_*), clamped; falls back to
-                              POWER when no network is loaded or the first step does not contract */
+  QPINV_ALPHA_LEARNED = 3, /* mu predicted by the scaling network (qpinv_mlp_*), clamped to
+                              [sigma1_est^2 / min(||A||_F^2, ||A||_1 ||A||_inf), 1.9]; when mu > 1 the
+                              first residual's 2-norm is estimated (3 power steps) and a value above
+                              1 + 1e-3 restarts with mu = 1 (POWER), as does divergence; POWER when
+                              no network is loaded */
   QPINV_X0_GIVEN = 4       /* X holds X_0 on entry (warm start / resume) */
 } qpinv_scaling;
 
@@ -86,9 +89,15 @@ typedef enum {
 typedef enum {
   QPINV_PREC_F64 = 0,          /* every product in FP64 (MFMA f64) */
   QPINV_PREC_F32 = 1,          /* every product in FP32 (MFMA f32, FP32 accumulate) */
-  QPINV_PREC_F32_F64FINISH = 2,/* FP32 until its stop rule fires, then 1-2 FP64 iterations */
-  QPINV_PREC_MIXED = 3         /* BF16 operands (FP32 accumulate) while ||R||_2 is large, then FP32,
-                                  then FP64 finish */
+  QPINV_PREC_F32_F64FINISH = 2,/* FP32 until its stop rule fires or the relative change d satisfies
+                                  d <= 0.5 and d^p <= 1e-6 (the FP32 floor; p = convergence order),
+                                  then FP64 iterations until d <= tol, or d <= 0.5 and d^p <= tol,
+                                  or d rises, or option f64_finish_iters (default 2) FP64 updates */
+  QPINV_PREC_MIXED = 3         /* BF16 operands (FP32 accumulate) first; leave BF16 when ||R||_2
+                                  (power estimate, option mixed_rnorm_steps) or ||R||_2^p drops below
+                                  option mixed_switch (1e-2), or ||R||_2 < 0.9 fails to halve in one
+                                  update, or stops falling, or after max_bf16_iters (8) updates; then
+                                  as F32_F64FINISH */
 } qpinv_precision;
 
 typedef enum { QPINV_GEMM_F64 = 0, QPINV_GEMM_F32 = 1, QPINV_GEMM_BF16 = 2 } qpinv_gemm_prec;
