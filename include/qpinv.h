@@ -136,7 +136,9 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
 
 /* Set a numeric option: side (qpinv_side), power_steps (>= 1), power_seed, autotune (0/1),
  * f64_finish_iters (1..4), mixed_switch (||R||_2 threshold, default 1e-2), mixed_rnorm_steps,
- * max_bf16_iters, gemm_timing (0/1), verbose (0/1).  Errors: EINVAL for an unknown key or out-of-range value. */
+ * max_bf16_iters, gemm_timing (0/1), gemm_cfg_f64 / gemm_cfg_f32 / gemm_cfg_bf16 (tile configuration
+ * index used for every product of that precision, -1 = tuned or heuristic choice), verbose (0/1).
+ * Errors: EINVAL for an unknown key or out-of-range value. */
 int qpinv_set_option(qpinv_ctx* ctx, const char* key, double value);
 
 /* Free the workspace and the context.  NULL is accepted. */

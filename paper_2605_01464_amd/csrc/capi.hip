@@ -80,6 +80,10 @@ void set_option(qp::Ctx& c, const std::string& key, double v) {
   } else if (key == "gemm_timing") {
     need(v == 0 || v == 1);
     c.opt.gemm_timing = (int)v;
+  } else if (key == "gemm_cfg_f64" || key == "gemm_cfg_f32" || key == "gemm_cfg_bf16") {
+    const qp::Prec p = key == "gemm_cfg_f64" ? qp::P_F64 : key == "gemm_cfg_f32" ? qp::P_F32 : qp::P_BF16;
+    need(v == -1 || (v >= 0 && v < (double)qp::tile_configs(p).size() && v == (int)v));
+    c.opt.force_cfg[(int)p] = (int)v;
   } else if (key == "verbose") {
     c.opt.verbose = v != 0;
   } else {

@@ -13,22 +13,81 @@
 // round-robin over the 8 XCDs) take neighbouring tiles, grouped 8 tile-rows at a time, to share
 // that XCD's L2.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "qgemm_kern.hpp"
 
 namespace qp {
 
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH>
+// A workgroup computes tiles blockIdx.x, blockIdx.x + gridDim.x, ... (one tile when the grid covers
+// them all).  With a grid that is a multiple of 8, every tile a workgroup visits maps to the same XCD
+// range, so the XCD-aware order is kept.
+// WALK = false: one tile per workgroup.  WALK = true: tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// (a separate instantiation, so that the loop's live state does not raise the register count, and
+// with it lower the occupancy, of the one-tile form).  With a grid that is a multiple of 8, every tile a
+// workgroup visits maps to the same XCD range, so the XCD-aware order is kept.  ALIGNED and DB as in
+// gemm_tile.
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, bool ALIGNED, bool WALK>
 __global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename MM::T> P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
-  __shared__ typename MM::T smem[C::SMEM];
+  __shared__ typename MM::T smem[DB ? 2 * C::SMEM : C::SMEM];
   __shared__ double red_lds[C::NW][2];
-  int tm, tn;
-  tile_of_block(blockIdx.x, P.tiles_m * P.tiles_n, P.tiles_m, P.tiles_n, tm, tn);
+  const int nt = P.tiles_m * P.tiles_n;
   double s_d = 0.0, s_x = 0.0;
-  gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH>(P, tm, tn, smem, s_d, s_x);
+  if constexpr (WALK) {
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+      int tm, tn;
+      tile_of_block(t, nt, P.tiles_m, P.tiles_n, tm, tn);
+      gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH, ALIGNED, DB>(P, tm, tn, smem, s_d, s_x);
+    }
+  } else {
+    int tm, tn;
+    tile_of_block(blockIdx.x, nt, P.tiles_m, P.tiles_n, tm, tn);
+    gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH, ALIGNED, DB>(P, tm, tn, smem, s_d, s_x);
+  }
   store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
+}
+
+namespace {
+struct DevLimits {
+  int cus = 0;
+  int lds = 0;  // bytes of LDS per compute unit
+};
+
+DevLimits dev_limits() {
+  static std::mutex mu;
+  static std::vector<DevLimits> cache;
+  int dev = 0;
+  QP_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1);
+  DevLimits& d = cache[dev];
+  if (d.cus == 0) {
+    QP_HIP(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    QP_HIP(hipDeviceGetAttribute(&d.lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+  }
+  return d;
+}
+}  // namespace
+
+LaunchShape launch_shape(int64_t tiles, int per_cu, int occ, size_t static_lds) {
+  LaunchShape ls;
+  ls.grid = tiles;
+  if (per_cu <= 0 || tiles == 0) return ls;
+  const DevLimits d = dev_limits();
+  const int c = std::max(1, std::min(per_cu, occ));
+  int64_t cap = (int64_t)d.cus * c;
+  if (cap >= 8) cap &= ~(int64_t)7;
+  if (tiles <= cap) return ls;
+  ls.grid = cap;
+  // reserve LDS so that at most c workgroups fit on a compute unit (kept within the 64 KiB a
+  // workgroup may take without opting in)
+  if (d.lds > 0) {
+    const size_t target = (size_t)((double)d.lds / (c + 0.5));
+    if (target > static_lds) ls.dyn_lds = std::min<size_t>(target, 65536) - static_lds;
+  }
+  return ls;
 }
 
 // Deterministic sum of `count` (d, x) pairs: one workgroup, fixed strided order, fixed tree.
@@ -64,20 +123,61 @@ void reduce_pairs(const double* partial, int64_t count, double* red, hipStream_t
 // ------------------------------------------------------------------------------------------------
 // configuration table and dispatch
 // ------------------------------------------------------------------------------------------------
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH>
-static void launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
+// Resident workgroups per compute unit and static LDS bytes of a kernel (queried once).
+struct KernelLimits {
+  int occ = 1;
+  size_t lds = 0;
+};
+
+template <class K>
+static KernelLimits kernel_limits(K kern, int threads) {
+  KernelLimits k;
+  int occ = 0;
+  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, 0));
+  hipFuncAttributes fa{};
+  QP_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)));
+  k.occ = std::max(occ, 1);
+  k.lds = fa.sharedSizeBytes;
+  return k;
+}
+
+// Launches the configuration; returns the number of workgroups (partial sums) launched.  PER_CU as
+// TileConfig::per_cu; the aligned form is used whenever the shape and the views allow it.
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, int PER_CU>
+static int64_t launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   GemmParams<typename MM::T> P = P0;
   P.tiles_m = (P.M + BM - 1) / BM;
   P.tiles_n = (P.N + BN - 1) / BN;
-  const int nb = P.tiles_m * P.tiles_n;
-  if (nb == 0) return;
-  hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH>), dim3(nb), dim3(C::NT), 0, s, P);
+  const int64_t nt = (int64_t)P.tiles_m * P.tiles_n;
+  if (nt == 0) return 0;
+  const bool aligned = P.vec && P.M % BM == 0 && P.N % BN == 0 && P.K % BK == 0;
+  if constexpr (PER_CU > 0) {
+    auto walk = qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, true>;
+    static const KernelLimits kl = kernel_limits(walk, C::NT);
+    const LaunchShape ls = launch_shape(nt, PER_CU, kl.occ, kl.lds);
+    if (ls.grid < nt) {
+      if (aligned)
+        hipLaunchKernelGGL(walk, dim3((unsigned)ls.grid), dim3(C::NT), ls.dyn_lds, s, P);
+      else
+        hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, true>), dim3((unsigned)ls.grid),
+                           dim3(C::NT), ls.dyn_lds, s, P);
+      QP_HIP(hipGetLastError());
+      return ls.grid;
+    }
+  }
+  if (aligned)
+    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, false>), dim3((unsigned)nt), dim3(C::NT),
+                       0, s, P);
+  else
+    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, false>), dim3((unsigned)nt), dim3(C::NT),
+                       0, s, P);
   QP_HIP(hipGetLastError());
+  return nt;
 }
 
-using F32Launch = void (*)(const GemmParams<float>&, hipStream_t);
-using F64Launch = void (*)(const GemmParams<double>&, hipStream_t);
+using F32Launch = int64_t (*)(const GemmParams<float>&, hipStream_t);
+using F64Launch = int64_t (*)(const GemmParams<double>&, hipStream_t);
 
 struct F32Entry {
   TileConfig cfg;
@@ -89,22 +189,29 @@ struct F64Entry {
 };
 
 // FP32 configurations accumulate in two levels (flush every 128 k); FP64 needs no flush.
+// "_db": double-buffered LDS staging; "_cuC": C workgroups per compute unit walking the tiles.
 static const std::vector<F32Entry>& f32_table() {
   static const std::vector<F32Entry> t = {
-      {{0, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 64, 16, 2, 2, 128>},
-      {{1, 32, 32, 16, 256, "f32_32x32x16_w2x2_mfma16"}, launch_cfg<MM16F, 32, 32, 16, 2, 2, 128>},
-      {{2, 128, 64, 16, 256, "f32_128x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 128, 64, 16, 2, 2, 128>},
-      {{3, 64, 128, 16, 256, "f32_64x128x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 128, 16, 2, 2, 128>},
-      {{4, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma16"}, launch_cfg<MM16F, 64, 64, 16, 2, 2, 128>},
+      {{0, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 64, 16, 2, 2, 128, false, 0>},
+      {{1, 32, 32, 16, 256, "f32_32x32x16_w2x2_mfma16"}, launch_cfg<MM16F, 32, 32, 16, 2, 2, 128, false, 0>},
+      {{2, 128, 64, 16, 256, "f32_128x64x16_w2x2_mfma32"}, launch_cfg<MM32F, 128, 64, 16, 2, 2, 128, false, 0>},
+      {{3, 64, 128, 16, 256, "f32_64x128x16_w2x2_mfma32"}, launch_cfg<MM32F, 64, 128, 16, 2, 2, 128, false, 0>},
+      {{4, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma16"}, launch_cfg<MM16F, 64, 64, 16, 2, 2, 128, false, 0>},
+      {{5, 64, 64, 16, 256, "f32_64x64x16_w2x2_mfma32_db"}, launch_cfg<MM32F, 64, 64, 16, 2, 2, 128, true, 0>},
+      {{6, 32, 32, 16, 256, "f32_32x32x16_w2x2_mfma16_db"}, launch_cfg<MM16F, 32, 32, 16, 2, 2, 128, true, 0>},
+      {{7, 64, 64, 16, 1024, "f32_64x64x16_w4x4_mfma16_db"}, launch_cfg<MM16F, 64, 64, 16, 4, 4, 128, true, 0>},
+      {{8, 32, 32, 16, 256, "f32_32x32x16_w2x2_mfma16_db_cu3", 3}, launch_cfg<MM16F, 32, 32, 16, 2, 2, 128, true, 3>},
   };
   return t;
 }
 
 static const std::vector<F64Entry>& f64_table() {
   static const std::vector<F64Entry> t = {
-      {{0, 64, 64, 8, 256, "f64_64x64x8_w2x2_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 2, 2, 0>},
-      {{1, 32, 32, 16, 256, "f64_32x32x16_w2x2_mfma16"}, launch_cfg<MM16D, 32, 32, 16, 2, 2, 0>},
-      {{2, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 4, 4, 0>},
+      {{0, 64, 64, 8, 256, "f64_64x64x8_w2x2_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 2, 2, 0, false, 0>},
+      {{1, 32, 32, 16, 256, "f64_32x32x16_w2x2_mfma16"}, launch_cfg<MM16D, 32, 32, 16, 2, 2, 0, false, 0>},
+      {{2, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 4, 4, 0, false, 0>},
+      {{3, 32, 32, 16, 256, "f64_32x32x16_w2x2_mfma16_db"}, launch_cfg<MM16D, 32, 32, 16, 2, 2, 0, true, 0>},
+      {{4, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16_db"}, launch_cfg<MM16D, 64, 64, 8, 4, 4, 0, true, 0>},
   };
   return t;
 }
@@ -130,14 +237,14 @@ int64_t qgemm_blocks(Prec p, int cfg, int64_t M, int64_t N) {
   return blocks_for(t.at(cfg), M, N);
 }
 
+// Measured on MI355X: the 64 x 64 double-buffered tiles win once there are >= 4 of them per compute unit,
+// the 32 x 32 ones below that (fewer tiles leave compute units idle in the last wave).
 int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
   (void)K;
-  if (p == P_F64) {
-    return blocks_for(tile_configs(p)[0], M, N) >= 256 ? 0 : 1;
-  }
-  const auto& t = tile_configs(p);
-  if (p == P_BF16) return blocks_for(t[0], M, N) >= 256 ? 0 : 1;
-  return blocks_for(t[0], M, N) >= 512 ? 0 : 1;
+  const int64_t b64 = ((M + 63) / 64) * ((N + 63) / 64);
+  if (p == P_F64) return b64 >= 1024 ? 4 : 1;
+  if (p == P_BF16) return b64 >= 256 ? 0 : 1;
+  return b64 >= 1024 ? 5 : 6;
 }
 
 template <class T>
@@ -175,7 +282,7 @@ static GemmParams<T> make_params(const QView& A, const QView& B, int64_t M, int6
   return P;
 }
 
-void bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s);  // qgemm_bf16.hip
+int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s);  // qgemm_bf16.hip
 int64_t bf16_blocks(int cfg, int64_t M, int64_t N);
 
 void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t K, const Epilogue& epi,
@@ -186,17 +293,19 @@ void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t
   if (cfg < 0) cfg = default_config(p, M, N, K);
   const auto& cfgs = tile_configs(p);
   if (cfg >= (int)cfgs.size()) throw Error(-1, "qgemm: bad tile config");
+  // an upper bound of the workgroups launched (a per-CU configuration launches at most this many)
   const int64_t nb = p == P_BF16 ? bf16_blocks(cfg, M, N) : blocks_for(cfgs[cfg], M, N);
   if (epi.reduce && nb > scratch.capacity / 2) throw Error(-1, "qgemm: reduction scratch too small");
   double* partial = epi.reduce ? scratch.partial : nullptr;
+  int64_t launched = 0;
   if (p == P_F64) {
-    f64_table()[cfg].fn(make_params<double>(A, B, M, N, K, epi, partial), stream);
+    launched = f64_table()[cfg].fn(make_params<double>(A, B, M, N, K, epi, partial), stream);
   } else if (p == P_F32) {
-    f32_table()[cfg].fn(make_params<float>(A, B, M, N, K, epi, partial), stream);
+    launched = f32_table()[cfg].fn(make_params<float>(A, B, M, N, K, epi, partial), stream);
   } else {
-    bf16_launch(make_params<float>(A, B, M, N, K, epi, partial), cfg, stream);
+    launched = bf16_launch(make_params<float>(A, B, M, N, K, epi, partial), cfg, stream);
   }
-  if (epi.reduce) reduce_pairs(partial, nb, red, stream);
+  if (epi.reduce) reduce_pairs(partial, launched, red, stream);
 }
 
 }  // namespace qp

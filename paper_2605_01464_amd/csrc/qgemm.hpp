@@ -42,7 +42,21 @@ struct TileConfig {
   int id;
   int bm, bn, bk, threads;
   const char* name;
+  int per_cu = 0;  // 0: one workgroup per output tile.  c > 0: c workgroups per compute unit (LDS
+                   // reservation caps residency at c) each walking an equal share of the tiles, so
+                   // tile counts that are a multiple of c x CUs finish without a partial last wave
 };
+
+// Launch geometry of a configuration on the current device: workgroups launched and the dynamic LDS
+// reservation that caps residency.
+struct LaunchShape {
+  int64_t grid = 0;
+  size_t dyn_lds = 0;
+};
+
+// Workgroups and dynamic LDS for `tiles` output tiles of a kernel with `static_lds` bytes of LDS,
+// `occ` resident workgroups per compute unit, `per_cu` as in TileConfig.
+LaunchShape launch_shape(int64_t tiles, int per_cu, int occ, size_t static_lds);
 
 // Tile configurations available for a compute precision (F32/BF16 take float storage,
 // F64 takes double storage).

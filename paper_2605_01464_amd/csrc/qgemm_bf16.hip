@@ -6,6 +6,7 @@
 // and B tiles transposed as [plane][col][k], both k-contiguous, so that every lane reads its eight
 // consecutive k of a fragment with one 16-byte LDS load.  Lane layout (64 lanes, verified):
 //   A frag: row l%16, k = 8(l/16) .. 8(l/16)+7;  B frag: col l%16, same k;  D reg r: row 4(l/16)+r, col l%16.
+#include <utility>
 #include <vector>
 
 #include "qgemm_kern.hpp"
@@ -40,17 +41,14 @@ struct Bf16Cfg {
   static_assert(NW * BLK * BLK * 4 <= (int)LDS, "epilogue staging fits");
 };
 
+// One BM x BN output tile (all four planes) with the epilogue; adds the reduction terms to s_d, s_x.
 template <int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(64 * WM * WN) qgemm_bf16_kernel(GemmParams<float> P) {
+__device__ __forceinline__ void bf16_tile(const GemmParams<float>& P, int tm, int tn, __bf16* smem, double& s_d,
+                                          double& s_x) {
   using C = Bf16Cfg<BM, BN, WM, WN>;
   constexpr int BK = C::BK, LDK = C::LDK;
-  __shared__ __attribute__((aligned(16))) __bf16 smem[4 * (BM + BN) * LDK];
   __bf16* const As = smem;                 // [4][BM][LDK]
   __bf16* const Bs = smem + 4 * BM * LDK;  // [4][BN][LDK]
-  __shared__ double red_lds[C::NW][2];
-
-  int tm, tn;
-  tile_of_block(blockIdx.x, P.tiles_m * P.tiles_n, P.tiles_m, P.tiles_n, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w % WM, wn = w / WM;
@@ -173,7 +171,6 @@ __global__ void __launch_bounds__(64 * WM * WN) qgemm_bf16_kernel(GemmParams<flo
   }
 
   // epilogue through a per-wave FP32 slab (static accumulator indices, row-contiguous output pass)
-  double s_d = 0.0, s_x = 0.0;
   float* const slab = reinterpret_cast<float*>(smem) + w * 16 * 16;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
@@ -188,24 +185,54 @@ __global__ void __launch_bounds__(64 * WM * WN) qgemm_bf16_kernel(GemmParams<flo
         const int rb0 = m0 + wm * C::WTM + i * 16, cb0 = n0 + wn * C::WTN + j * 16;
         for (int e = lane; e < 256; e += 64) epilogue_plane(P, p, rb0 + e / 16, cb0 + e % 16, slab[e], s_d, s_x);
       }
-  store_partials<C::NW>(P.partial, s_d, s_x, red_lds, lane, w, tid);
+  __syncthreads();  // LDS is reused by the workgroup's next tile
+}
+
+// Tiles blockIdx.x, blockIdx.x + gridDim.x, ... (one tile when the grid covers them all).
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) qgemm_bf16_kernel(GemmParams<float> P) {
+  using C = Bf16Cfg<BM, BN, WM, WN>;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[4 * (BM + BN) * C::LDK];
+  __shared__ double red_lds[C::NW][2];
+  const int nt = P.tiles_m * P.tiles_n;
+  double s_d = 0.0, s_x = 0.0;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int tm, tn;
+    tile_of_block(t, nt, P.tiles_m, P.tiles_n, tm, tn);
+    bf16_tile<BM, BN, WM, WN>(P, tm, tn, smem, s_d, s_x);
+  }
+  store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
 }
 
 template <int BM, int BN, int WM, int WN>
-static void launch_bf16(const GemmParams<float>& P0, hipStream_t s) {
+static int64_t launch_bf16(const GemmParams<float>& P0, int per_cu, hipStream_t s) {
   using C = Bf16Cfg<BM, BN, WM, WN>;
   GemmParams<float> P = P0;
   P.tiles_m = (P.M + BM - 1) / BM;
   P.tiles_n = (P.N + BN - 1) / BN;
-  const int nb = P.tiles_m * P.tiles_n;
-  if (nb == 0) return;
-  hipLaunchKernelGGL((qgemm_bf16_kernel<BM, BN, WM, WN>), dim3(nb), dim3(C::NT), 0, s, P);
+  const int64_t nt = (int64_t)P.tiles_m * P.tiles_n;
+  if (nt == 0) return 0;
+  auto kern = qgemm_bf16_kernel<BM, BN, WM, WN>;
+  LaunchShape ls;
+  ls.grid = nt;
+  if (per_cu > 0) {
+    static const std::pair<int, size_t> kl = [&] {
+      int occ = 0;
+      QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, C::NT, 0));
+      hipFuncAttributes fa{};
+      QP_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)));
+      return std::make_pair(std::max(occ, 1), (size_t)fa.sharedSizeBytes);
+    }();
+    ls = launch_shape(nt, per_cu, kl.first, kl.second);
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)ls.grid), dim3(C::NT), ls.dyn_lds, s, P);
   QP_HIP(hipGetLastError());
+  return ls.grid;
 }
 
 struct Bf16Entry {
   TileConfig cfg;
-  void (*fn)(const GemmParams<float>&, hipStream_t);
+  int64_t (*fn)(const GemmParams<float>&, int, hipStream_t);
 };
 
 static const std::vector<Bf16Entry>& bf16_table() {
@@ -214,6 +241,8 @@ static const std::vector<Bf16Entry>& bf16_table() {
       {{1, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32"}, launch_bf16<32, 32, 2, 2>},
       {{2, 128, 64, 32, 256, "bf16_128x64x32_w2x2_mfma16x16x32"}, launch_bf16<128, 64, 2, 2>},
       {{3, 64, 128, 32, 256, "bf16_64x128x32_w2x2_mfma16x16x32"}, launch_bf16<64, 128, 2, 2>},
+      {{4, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32_cu3", 3}, launch_bf16<32, 32, 2, 2>},
+      {{5, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_cu2", 2}, launch_bf16<64, 64, 2, 2>},
   };
   return t;
 }
@@ -225,7 +254,10 @@ const std::vector<TileConfig>& bf16_configs() {
   return v;
 }
 
-void bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s) { bf16_table().at(cfg).fn(P, s); }
+int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s) {
+  const auto& e = bf16_table().at(cfg);
+  return e.fn(P, e.cfg.per_cu, s);
+}
 
 int64_t bf16_blocks(int cfg, int64_t M, int64_t N) {
   const auto& c = bf16_table().at(cfg).cfg;

@@ -183,15 +183,20 @@ struct GemmCfg {
   static constexpr int NB = (BCH + NT - 1) / NT;
   static_assert(TM >= 1 && TN >= 1 && WTM % MM::BLK == 0 && WTN % MM::BLK == 0, "wave tile");
   static_assert(BK % MM::KS == 0 && BK % VA == 0 && BN % VA == 0, "k tile");
-  static constexpr int SMEM = 4 * BK * (LDA + LDB);  // elements of T
+  static constexpr int SMEM = 4 * BK * (LDA + LDB);  // elements of T (one staging buffer)
   static constexpr size_t LDS_BYTES = sizeof(T) * SMEM;
   static_assert(LDS_BYTES <= 65536, "LDS budget");
 };
 
 // One BM x BN output tile (all four planes) of C = A B with the epilogue; the epilogue's reduction
-// terms are added to the caller's s_d, s_x.  `smem` holds C::SMEM elements.  Used by the standalone
-// product kernel (one tile per workgroup) and by the batched solver (a workgroup walks all tiles).
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH>
+// terms are added to the caller's s_d, s_x.  Used by the standalone product kernel and by the batched
+// solver (a workgroup walks all tiles).
+//   ALIGNED: the caller guarantees 16-byte vector loads and M % BM = N % BN = K % BK = 0, so the loads
+//            carry no bounds checks or scalar fallbacks.
+//   DB:      two LDS staging buffers (`smem` holds 2 C::SMEM elements): the next K step is written to
+//            one while the MFMAs read the other, one barrier per K step; otherwise one buffer
+//            (C::SMEM elements) and two barriers per K step.
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool ALIGNED = false, bool DB = false>
 __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, int tm, int tn, typename MM::T* smem,
                                           double& s_d, double& s_x) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
@@ -201,8 +206,6 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
   constexpr int VA = C::VA;
   static_assert(FLUSH == 0 || FLUSH % BK == 0, "flush interval is a whole number of K tiles");
 
-  T* const As = smem;
-  T* const Bs = smem + 4 * BK * C::LDA;
   static_assert(C::NW * MM::BLK * MM::BLK <= C::SMEM, "epilogue staging fits in LDS");
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
@@ -253,8 +256,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
   T rb[4][C::NB][VA];
 
   auto load = [&](int k0) {
-    const bool fullA = P.vec && (m0 + BM <= P.M) && (k0 + BK <= P.K);
-    const bool fullB = P.vec && (n0 + BN <= P.N) && (k0 + BK <= P.K);
+    const bool fullA = ALIGNED || (P.vec && (m0 + BM <= P.M) && (k0 + BK <= P.K));
+    const bool fullB = ALIGNED || (P.vec && (n0 + BN <= P.N) && (k0 + BK <= P.K));
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const T* Aq = P.A + q * P.psa;
@@ -298,7 +301,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
     }
   };
 
-  auto store = [&]() {
+  auto store = [&](T* As, T* Bs) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
@@ -326,12 +329,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
   };
 
   const int fr = MM::fr(lane), fk = MM::fk(lane);
-  if (P.K > 0) load(0);
-  for (int k0 = 0; k0 < P.K; k0 += BK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + BK < P.K) load(k0 + BK);
+  auto compute = [&](const T* As, const T* Bs) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += MM::KS) {
       T a[C::TM][4], b[C::TN][4];
@@ -354,8 +352,45 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
           for (int p = 0; p < 4; ++p) acc[p][i][j] = t4[p];
         }
     }
-    if constexpr (FLUSH > 0) {
-      if ((k0 + BK) % FLUSH == 0) flush();
+  };
+  constexpr int BOFF = 4 * BK * C::LDA;  // B staging follows A staging in a buffer
+  if constexpr (!DB) {
+    if (P.K > 0) load(0);
+    for (int k0 = 0; k0 < P.K; k0 += BK) {
+      __syncthreads();
+      store(smem, smem + BOFF);
+      __syncthreads();
+      if (k0 + BK < P.K) load(k0 + BK);
+      compute(smem, smem + BOFF);
+      if constexpr (FLUSH > 0) {
+        if ((k0 + BK) % FLUSH == 0) flush();
+      }
+    }
+  } else {
+    // buffer b holds K step s with s % 2 == b.  Step s reads buffer s % 2 while step s + 1 is written
+    // to the other one (whose last reader was step s - 1, behind the previous barrier) and step s + 2
+    // is fetched into registers.
+    __syncthreads();  // the caller may have used the LDS just before (previous tile's epilogue)
+    if (P.K > 0) {
+      load(0);
+      store(smem, smem + BOFF);
+      if (BK < P.K) load(BK);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < P.K; k0 += BK) {
+      T* const Ac = smem + cur * C::SMEM;
+      compute(Ac, Ac + BOFF);
+      if (k0 + BK < P.K) {
+        T* const An = smem + (cur ^ 1) * C::SMEM;
+        store(An, An + BOFF);
+        if (k0 + 2 * BK < P.K) load(k0 + 2 * BK);
+      }
+      if constexpr (FLUSH > 0) {
+        if ((k0 + BK) % FLUSH == 0) flush();
+      }
+      __syncthreads();
+      cur ^= 1;
     }
   }
   flush();

@@ -105,6 +105,7 @@ Ctx::~Ctx() {
 }
 
 int Ctx::config_for(Prec p, int64_t M, int64_t N, int64_t K, hipStream_t s) {
+  if (opt.force_cfg[(int)p] >= 0) return opt.force_cfg[(int)p];
   auto key = std::make_tuple((int)p, M, N, K);
   auto it = tuned.find(key);
   if (it != tuned.end()) return it->second;

@@ -35,6 +35,7 @@ struct Options {
   int max_bf16_iters = 8;
   int verbose = 0;
   int gemm_timing = 0;
+  int force_cfg[3] = {-1, -1, -1};  // per product precision: tile configuration for every product, -1 = choose
 };
 
 struct MlpState;      // scaling network (mlp.hip)
