@@ -28,8 +28,8 @@ namespace qp {
 // with it lower the occupancy, of the one-tile form).  With a grid that is a multiple of 8, every tile a
 // workgroup visits maps to the same XCD range, so the XCD-aware order is kept.  ALIGNED and DB as in
 // gemm_tile.
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, bool ALIGNED, bool WALK>
-__global__ void __launch_bounds__(64 * WM * WN) qgemm_kernel(GemmParams<typename MM::T> P) {
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, bool ALIGNED, bool WALK, int MINW>
+__global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_kernel(GemmParams<typename MM::T> P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   __shared__ typename MM::T smem[DB ? 2 * C::SMEM : C::SMEM];
   __shared__ double red_lds[C::NW][2];
@@ -143,7 +143,8 @@ static KernelLimits kernel_limits(K kern, int threads) {
 
 // Launches the configuration; returns the number of workgroups (partial sums) launched.  PER_CU as
 // TileConfig::per_cu; the aligned form is used whenever the shape and the views allow it.
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, int PER_CU>
+// MINW: waves per SIMD the register allocation must leave room for (launch bound).
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, int PER_CU, int MINW = 1>
 static int64_t launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   GemmParams<typename MM::T> P = P0;
@@ -153,24 +154,24 @@ static int64_t launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
   if (nt == 0) return 0;
   const bool aligned = P.vec && P.M % BM == 0 && P.N % BN == 0 && P.K % BK == 0;
   if constexpr (PER_CU > 0) {
-    auto walk = qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, true>;
+    auto walk = qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, true, MINW>;
     static const KernelLimits kl = kernel_limits(walk, C::NT);
     const LaunchShape ls = launch_shape(nt, PER_CU, kl.occ, kl.lds);
     if (ls.grid < nt) {
       if (aligned)
         hipLaunchKernelGGL(walk, dim3((unsigned)ls.grid), dim3(C::NT), ls.dyn_lds, s, P);
       else
-        hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, true>), dim3((unsigned)ls.grid),
+        hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, true, MINW>), dim3((unsigned)ls.grid),
                            dim3(C::NT), ls.dyn_lds, s, P);
       QP_HIP(hipGetLastError());
       return ls.grid;
     }
   }
   if (aligned)
-    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, false>), dim3((unsigned)nt), dim3(C::NT),
+    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, false, MINW>), dim3((unsigned)nt), dim3(C::NT),
                        0, s, P);
   else
-    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, false>), dim3((unsigned)nt), dim3(C::NT),
+    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, false, MINW>), dim3((unsigned)nt), dim3(C::NT),
                        0, s, P);
   QP_HIP(hipGetLastError());
   return nt;

@@ -848,8 +848,8 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
       QP_HIP(hipMemcpyAsync(rsave[slot].v.p, R.v.p, 4 * R.v.ps * esize(R.dtype), hipMemcpyDeviceToDevice, s));
       rsave_j[slot] = j;
     }
-    double rnorm = -1.0;
-    if (want_R) rnorm = std::sqrt(std::max(0.0, power_host(c, R, c.opt.mixed_rnorm_steps, s)));
+    double rnorm = -1.0;  // ||R_j||_2 estimate: only the BF16 phase's switch rule uses it
+    if (p == P_BF16) rnorm = std::sqrt(std::max(0.0, power_host(c, R, c.opt.mixed_rnorm_steps, s)));
     to_host(c, red, 2, s);
     const double d_abs = std::sqrt(std::max(0.0, c.hsc[0]));
     const double xn = std::sqrt(std::max(0.0, c.hsc[1]));

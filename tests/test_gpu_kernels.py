@@ -11,7 +11,9 @@ pytestmark = pytest.mark.gpu
 U32 = 2.0 ** -24
 U64 = 2.0 ** -53
 
-SHAPES = [(1, 1, 1), (7, 5, 3), (33, 65, 17), (100, 37, 129), (128, 128, 128), (130, 250, 70), (257, 129, 300)]
+# (384, 384, 192) is a whole number of tiles of every configuration (the aligned, unchecked load path)
+SHAPES = [(1, 1, 1), (7, 5, 3), (33, 65, 17), (100, 37, 129), (128, 128, 128), (130, 250, 70), (257, 129, 300),
+          (384, 384, 192)]
 
 
 def gemm_bound(A, B, C0, alpha, beta, gamma, u):
