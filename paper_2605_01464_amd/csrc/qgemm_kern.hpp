@@ -173,17 +173,21 @@ struct GemmCfg {
   static constexpr int NW = WM * WN, NT = 64 * NW;
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int TM = WTM / MM::BLK, TN = WTN / MM::BLK;
-  static constexpr int PADA = (sizeof(T) == 4) ? 4 : 2;
   static constexpr int PADB = (sizeof(T) == 4) ? 4 : 2;
-  static constexpr int LDA = BM + PADA, LDB = BN + PADB;
+  static constexpr int LDB = BN + PADB;
   static constexpr int VA = V16<T>::n;
+  // A staging: [plane][k chunk of VA][row, BM + 2 rows of padding][VA]; the padding puts the four
+  // chunks a group of lanes writes (consecutive k chunks of two rows) and reads on distinct banks.
+  static constexpr int LDAC = BM + 2;
+  static constexpr int KB = VA * MM::KS;  // k covered by one 16-byte fragment read (VA MFMAs)
+  static constexpr int AELEMS = 4 * (BK / VA) * LDAC * VA;
   static constexpr int ACH = BM * BK / VA;  // 16-byte chunks per plane of an A tile
   static constexpr int BCH = BK * BN / VA;
   static constexpr int NA = (ACH + NT - 1) / NT;
   static constexpr int NB = (BCH + NT - 1) / NT;
   static_assert(TM >= 1 && TN >= 1 && WTM % MM::BLK == 0 && WTN % MM::BLK == 0, "wave tile");
-  static_assert(BK % MM::KS == 0 && BK % VA == 0 && BN % VA == 0, "k tile");
-  static constexpr int SMEM = 4 * BK * (LDA + LDB);  // elements of T (one staging buffer)
+  static_assert(BK % KB == 0 && BN % VA == 0, "k tile");
+  static constexpr int SMEM = AELEMS + 4 * BK * LDB;  // elements of T (one staging buffer)
   static constexpr size_t LDS_BYTES = sizeof(T) * SMEM;
   static_assert(LDS_BYTES <= 65536, "LDS budget");
 };
@@ -309,8 +313,11 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
         const int c = tid + t * C::NT;
         if (C::ACH % C::NT == 0 || c < C::ACH) {
           const int i = c / (BK / VA), kc = (c % (BK / VA)) * VA;
+          VT v;
+          T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
-          for (int e = 0; e < VA; ++e) As[(q * BK + kc + e) * C::LDA + i] = ra[q][t][e];
+          for (int e = 0; e < VA; ++e) pv[e] = ra[q][t][e];
+          *reinterpret_cast<VT*>(&As[((q * (BK / VA) + kc / VA) * C::LDAC + i) * VA]) = v;
         }
       }
 #pragma unroll
@@ -328,32 +335,47 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
     }
   };
 
+  // MFMA k-group g = fk(lane) of a block of KB k takes the VA consecutive k of chunk g from one 16-byte
+  // LDS read; the e-th of the block's VA MFMAs uses element e of every lane (k = VA g + e), so the VA
+  // MFMAs together sum the block's KB products (in a different order than k = 0, 1, ...).
   const int fr = MM::fr(lane), fk = MM::fk(lane);
   auto compute = [&](const T* As, const T* Bs) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += MM::KS) {
-      T a[C::TM][4], b[C::TN][4];
+    for (int kb = 0; kb < BK / C::KB; ++kb) {
+      VT av[C::TM][4];
+      T b[C::TN][4][VA];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
 #pragma unroll
         for (int i = 0; i < C::TM; ++i)
-          a[i][q] = As[(q * BK + kk + fk) * C::LDA + wm * C::WTM + i * MM::BLK + fr];
+          av[i][q] = *reinterpret_cast<const VT*>(
+              &As[((q * (BK / VA) + kb * MM::KS + fk) * C::LDAC + wm * C::WTM + i * MM::BLK + fr) * VA]);
 #pragma unroll
         for (int j = 0; j < C::TN; ++j)
-          b[j][q] = Bs[(q * BK + kk + fk) * C::LDB + wn * C::WTN + j * MM::BLK + fr];
+#pragma unroll
+          for (int e = 0; e < VA; ++e)
+            b[j][q][e] = Bs[(q * BK + kb * C::KB + VA * fk + e) * C::LDB + wn * C::WTN + j * MM::BLK + fr];
       }
 #pragma unroll
-      for (int i = 0; i < C::TM; ++i)
+      for (int e = 0; e < VA; ++e)
 #pragma unroll
-        for (int j = 0; j < C::TN; ++j) {
-          Acc t4[4] = {acc[0][i][j], acc[1][i][j], acc[2][i][j], acc[3][i][j]};
-          quat_mma<MM>(t4, a[i], b[j]);
+        for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-          for (int p = 0; p < 4; ++p) acc[p][i][j] = t4[p];
-        }
+          for (int j = 0; j < C::TN; ++j) {
+            T a4[4], b4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              a4[q] = reinterpret_cast<const T*>(&av[i][q])[e];
+              b4[q] = b[j][q][e];
+            }
+            Acc t4[4] = {acc[0][i][j], acc[1][i][j], acc[2][i][j], acc[3][i][j]};
+            quat_mma<MM>(t4, a4, b4);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) acc[p][i][j] = t4[p];
+          }
     }
   };
-  constexpr int BOFF = 4 * BK * C::LDA;  // B staging follows A staging in a buffer
+  constexpr int BOFF = C::AELEMS;  // B staging follows A staging in a buffer
   if constexpr (!DB) {
     if (P.K > 0) load(0);
     for (int k0 = 0; k0 < P.K; k0 += BK) {
