@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -26,25 +28,49 @@ PEAK = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}  # TFLOP/s, dense MFMA, MI355
 METRIC = "pinv solves/s + quaternion GEMM TFLOP/s at rel-err<=1e-6; mixed/learned vs plain"
 
 
-def qgemm_tflops(q, ctx, n, prec="f32", reps=10):
+def hamilton_rows(A, B):
+    """Rows of the quaternion product A B in FP64 (A: 4 x r x K planes, B: 4 x K x N); a direct transcription
+    of the Hamilton product used only to report the products' sampled error."""
+    a, b = [A[i].astype(np.float64) for i in range(4)], [B[i].astype(np.float64) for i in range(4)]
+    return np.stack([a[0] @ b[0] - a[1] @ b[1] - a[2] @ b[2] - a[3] @ b[3],
+                     a[0] @ b[1] + a[1] @ b[0] + a[2] @ b[3] - a[3] @ b[2],
+                     a[0] @ b[2] - a[1] @ b[3] + a[2] @ b[0] + a[3] @ b[1],
+                     a[0] @ b[3] + a[1] @ b[2] - a[2] @ b[1] + a[3] @ b[0]])
+
+
+def qgemm_rate(q, ctx, M, N, K, prec="f32", reps=20, check_rows=16):
+    """Median TFLOP/s over `reps` timed launches of C = A B (planes N(0,1), seed 400, tuned tiles) and the
+    relative Frobenius error of `check_rows` sampled rows against the FP64 product of the same inputs."""
     import torch
 
-    dt = torch.float32 if prec != "f64" else torch.float64
+    dt = torch.float64 if prec == "f64" else torch.float32
     g = torch.Generator(device="cuda").manual_seed(400)
-    A = torch.randn((4, n, n), device="cuda", dtype=dt, generator=g)
-    B = torch.randn((4, n, n), device="cuda", dtype=dt, generator=g)
-    C = torch.empty((4, n, n), device="cuda", dtype=dt)
+    A = torch.randn((4, M, K), device="cuda", dtype=dt, generator=g)
+    B = torch.randn((4, K, N), device="cuda", dtype=dt, generator=g)
+    C = torch.empty((4, M, N), device="cuda", dtype=dt)
+    ctx.set("autotune", 1)
     q.qgemm(ctx, A, B, C, gemm_prec=prec)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(s)
         q.qgemm(ctx, A, B, C, gemm_prec=prec)
-    e1.record(s)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return 32.0 * n ** 3 / (ms * 1e-3) / 1e12, ms
+        e1.record(s)
+    torch.cuda.synchronize()
+    ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+    rows = np.random.default_rng(7).choice(M, min(check_rows, M), replace=False)
+    Ah, Bh = A[:, rows, :].double().cpu().numpy(), B.double().cpu().numpy()
+    if prec == "bf16":  # the kernel multiplies the BF16-rounded operands
+        Ah = A[:, rows, :].bfloat16().double().cpu().numpy()
+        Bh = B.bfloat16().double().cpu().numpy()
+    ref = hamilton_rows(Ah, Bh)
+    got = C[:, rows, :].double().cpu().numpy()
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    del A, B, C
+    torch.cuda.empty_cache()
+    return {"tflops": 32.0 * M * N * K / (ms * 1e-3) / 1e12, "ms_median": ms, "reps": reps,
+            "frac_peak": 32.0 * M * N * K / (ms * 1e-3) / 1e12 / PEAK[prec], "rel_err_sampled_rows": err}
 
 
 KERNEL_SOURCES = ("common.hpp", "qgemm.hpp", "qgemm_kern.hpp", "qgemm.hip")
@@ -88,12 +114,13 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-matrix batched comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-scaling evaluation")
     ap.add_argument("--learned-count", type=int, default=256)
+    ap.add_argument("--no-methods", action="store_true", help="skip the other methods on the 2048x1536 input")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64x48 FP64 latency section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         return 2
 
-    import numpy as np
     import torch
 
     import paper_2605_01464_amd as q
@@ -172,10 +199,66 @@ def main() -> int:
     }
 
     if not args.no_gemm:
+        # standalone quaternion products: square sizes and the solver's own shapes, per precision
         out["qgemm_square"] = {}
-        for nn in (2048, 4096):
-            tf, ms = qgemm_tflops(q, ctx, nn)
-            out["qgemm_square"][f"f32_n{nn}"] = {"tflops": tf, "ms": ms, "frac_peak": tf / PEAK["f32"]}
+        for nn in (1024, 2048, 4096, 8192):
+            out["qgemm_square"][f"f32_n{nn}"] = qgemm_rate(q, ctx, nn, nn, nn, reps=10 if nn == 8192 else 20)
+        for prec in ("f64", "bf16"):
+            out["qgemm_square"][f"{prec}_n4096"] = qgemm_rate(q, ctx, 4096, 4096, 4096, prec=prec, reps=10)
+        out["qgemm_solver_shapes"] = {
+            f"f32_{M_}x{N_}x{K_}": qgemm_rate(q, ctx, M_, N_, K_)
+            for M_, N_, K_ in ((1536, 1536, 2048), (1536, 1536, 1536), (1536, 2048, 1536))}
+        ctx.set("autotune", 0 if args.no_autotune else 1)
+
+    if not args.no_methods:
+        # the same 2048 x 1536 workload with the other methods (FP32, guarded stop), and the factorized
+        # order-19 update against the plain hyperpower polynomial of order 19 at equal update counts
+        res = {}
+        for meth in ("ns", "qsai", "qrapid", "qhpi19"):
+            kw = dict(method=meth, scaling="power", tol=1e-6, max_iter=200, stop="guarded", precision="f32", X=X)
+            q.solve(ctx, A, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, inf_m = q.solve(ctx, A, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            res[meth] = {"pinv_per_s": 1.0 / dt, "ms": 1e3 * dt, "iters": inf_m["iters"], "returned": inf_m["returned"],
+                         "reason": inf_m["reason"], "gemm_tflop": inf_m["gemm_flops"] / 1e12}
+        fixed = {}
+        for key_, meth, order_ in (("qhpi19", "qhpi19", 19), ("hpi19", "hpi", 19)):
+            kw = dict(method=meth, order=order_, scaling="power", tol=0.0, max_iter=4, stop="dx_abs",
+                      precision="f32", X=X, check=False)
+            q.solve(ctx, A, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, inf_m = q.solve(ctx, A, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            fixed[key_] = {"ms_per_4_updates": 1e3 * dt, "gemm_tflop": inf_m["gemm_flops"] / 1e12}
+        fixed["time_ratio_unfactorized_over_factorized"] = (fixed["hpi19"]["ms_per_4_updates"] /
+                                                            fixed["qhpi19"]["ms_per_4_updates"])
+        out["methods_2048x1536"] = {"guarded_tol_1e-6": res, "order19_factorized_vs_horner_4_updates": fixed}
+
+    if not args.no_small:
+        # 64 x 48 FP64 (planes N(0,1), seeds 0..9): latency of one solve to ||AXA - A||_F / ||A||_F <= 1e-12
+        res = {}
+        smalls = [torch.from_numpy(qsynth.c1_instance(seed)).cuda() for seed in range(10)]
+        for meth in ("ns", "qsai", "qhpi19", "qrapid"):
+            kw = dict(method=meth, scaling="power", tol=1e-12, max_iter=200, stop="e1_rel", precision="f64")
+            for a in smalls:
+                q.solve(ctx, a, **kw)
+            torch.cuda.synchronize()
+            times, its = [], []
+            for rep in range(5):
+                for a in smalls:
+                    t = time.perf_counter()
+                    _, inf_s = q.solve(ctx, a, **kw)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t)
+                    its.append(inf_s["iters"])
+            res[meth] = {"us_median": 1e6 * float(np.median(times)), "pinv_per_s": 1.0 / float(np.median(times)),
+                         "iters_mean": float(np.mean(its))}
+        out["small_fp64_64x48"] = res
 
     mixed_inst = None
     if not args.no_mixed:

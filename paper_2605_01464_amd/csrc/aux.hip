@@ -114,6 +114,26 @@ void zero_doubles(double* p, int64_t count, hipStream_t s) {
   QP_HIP(hipGetLastError());
 }
 
+// Values in [-1, 1) from a multiplicative hash of the index (timing inputs: MFMA power and thus clocks
+// depend on the operand bits, so tiles are timed on dense data rather than zeros).
+template <class T>
+__global__ void __launch_bounds__(256) fill_kernel(T* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
+    const uint32_t h = (uint32_t)(i * 2654435761ull) ^ (uint32_t)(i >> 17);
+    p[i] = (T)((double)(h >> 8) * 0x1p-23 - 1.0);
+  }
+}
+
+template <class T>
+void fill_pattern(T* p, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  const unsigned blocks = (unsigned)std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks), dim3(256), 0, s, p, count);
+  QP_HIP(hipGetLastError());
+}
+template void fill_pattern<float>(float*, int64_t, hipStream_t);
+template void fill_pattern<double>(double*, int64_t, hipStream_t);
+
 // ------------------------------------------------------------------------------------------------
 // norms: row pass (one workgroup per row), column pass (column strips x row blocks), finalize
 // ------------------------------------------------------------------------------------------------

@@ -38,5 +38,7 @@ int64_t hermdiff_blocks(int64_t n);
 
 // Write `count` zeros to device doubles (a kernel, so it is safe inside captured graphs).
 void zero_doubles(double* p, int64_t count, hipStream_t s);
+template <class T>
+void fill_pattern(T* p, int64_t count, hipStream_t s);  // deterministic values in [-1, 1)
 
 }  // namespace qp
