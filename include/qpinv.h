@@ -137,7 +137,8 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
 /* Set a numeric option: side (qpinv_side), power_steps (>= 1), power_seed, autotune (0/1),
  * f64_finish_iters (1..4), mixed_switch (||R||_2 threshold, default 1e-2), mixed_rnorm_steps,
  * max_bf16_iters, gemm_timing (0/1), gemm_cfg_f64 / gemm_cfg_f32 / gemm_cfg_bf16 (tile configuration
- * index used for every product of that precision, -1 = tuned or heuristic choice), verbose (0/1).
+ * index used for every product of that precision, -1 = tuned or heuristic choice), batched_cfg
+ * (configuration of qpinv_solve_batched, -1 = tuned or default), verbose (0/1).
  * Errors: EINVAL for an unknown key or out-of-range value. */
 int qpinv_set_option(qpinv_ctx* ctx, const char* key, double value);
 
@@ -168,9 +169,14 @@ int qpinv_solve(qpinv_ctx* ctx, int method, int order, const qpinv_qmat* A, int 
                 void* hip_stream);
 
 /* Many independent solves in ONE persistent kernel launch (replayed from a captured hipGraph when the
- * batch signature repeats).  Each workgroup takes matrices from a device queue, largest work first,
- * and runs the whole method on each (power-iteration or given alpha, X_0 = alpha A^H, the product chain,
- * the stop rule) on the residual side of the smaller dimension.
+ * batch signature repeats): power-iteration or given alpha, X_0 = alpha A^H, the product chain and the
+ * stop rule per matrix, on the residual side of the smaller dimension.  Two kernel forms, chosen by the
+ * autotuner (option autotune = 1) or option batched_cfg:
+ *   queue:              each workgroup takes matrices from a device queue (largest work first) and
+ *                       runs a whole solve on its own (no waits between workgroups);
+ *   phase-synchronous:  all matrices advance one product at a time; every product's output tiles over
+ *                       all active matrices are spread over all workgroups, which meet at a bounded
+ *                       grid barrier (batch <= 2048; an expired wait returns ETIMEOUT).
  *   method       NS, QSAI or QHPI19 (order as for qpinv_solve).
  *   batch        number of matrices; A and X are HOST arrays of `batch` descriptors of DEVICE data.
  *   A[b]         m_b x n_b, FP32, 1 <= m_b, n_b <= 512;  X[b]: n_b x m_b, FP32 (output).
@@ -179,7 +185,7 @@ int qpinv_solve(qpinv_ctx* ctx, int method, int order, const qpinv_qmat* A, int 
  *   infos        host array of `batch` (may be NULL); infos[b].reserved holds that solve's status.
  * The tile configuration is timed on the batch when option autotune = 1 (once per batch signature).
  * Return: OK; ENOTCONVERGED / EDIVERGED / ENONFINITE if any solve ended that way (see infos);
- *         EINVAL; EHIP; ENOMEM.  The call waits for the batch to finish. */
+ *         EINVAL; EHIP; ENOMEM; ETIMEOUT.  The call waits for the batch to finish. */
 int qpinv_solve_batched(qpinv_ctx* ctx, int method, int order, int batch, const qpinv_qmat* A, qpinv_qmat* X,
                         int scaling, const double* alpha, double tol, int max_iter, int stop, qpinv_info* infos,
                         void* hip_stream);
@@ -273,6 +279,11 @@ int qpinv_autotune(qpinv_ctx* ctx, int gemm_prec, int64_t M, int64_t N, int64_t 
 /* Number of tile configurations for a product precision, and the name of one (static storage). */
 int qpinv_num_tile_configs(int gemm_prec);
 const char* qpinv_tile_config_name(int gemm_prec, int cfg);
+
+/* Configurations of qpinv_solve_batched (option batched_cfg): count and static name ("" if out of
+ * range).  Names starting with "batched_sync" are phase-synchronous, the others queue kernels. */
+int qpinv_num_batched_configs(void);
+const char* qpinv_batched_config_name(int cfg);
 
 /* Same as qpinv_qgemm with an explicit tile configuration (for measurement). */
 int qpinv_qgemm_cfg(qpinv_ctx* ctx, int gemm_prec, int cfg, const qpinv_qmat* A, const qpinv_qmat* B,

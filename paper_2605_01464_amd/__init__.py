@@ -84,6 +84,8 @@ def _load() -> ctypes.CDLL:
         "qpinv_autotune": (I, [P, I, I64, I64, I64, DP, P]),
         "qpinv_num_tile_configs": (I, [I]),
         "qpinv_tile_config_name": (ctypes.c_char_p, [I, I]),
+        "qpinv_num_batched_configs": (I, []),
+        "qpinv_batched_config_name": (ctypes.c_char_p, [I]),
         "qpinv_controller_replay": (I, [I, D, I, DP, DP, DP, ctypes.POINTER(ctypes.c_int)]),
         "qpinv_gemm_stats": (I, [P, DP, I]),
         "qpinv_mlp_init": (I, [P, ctypes.c_uint64]),
@@ -230,6 +232,14 @@ def qpinv_num_tile_configs(gemm_prec) -> int:
 
 def qpinv_tile_config_name(gemm_prec, cfg) -> str:
     return _lib.qpinv_tile_config_name(gemm_prec, cfg).decode()
+
+
+def qpinv_num_batched_configs() -> int:
+    return _lib.qpinv_num_batched_configs()
+
+
+def qpinv_batched_config_name(cfg) -> str:
+    return _lib.qpinv_batched_config_name(cfg).decode()
 
 
 def qpinv_gemm_stats(ctx, max_rows=32):

@@ -163,10 +163,148 @@ __device__ __attribute__((noinline)) void wg_gemm(const DM& A, const DM& B, cons
   __syncthreads();
 }
 
+// Per-matrix set-up by one workgroup: finiteness and ||A||_F, the scaling (power iteration on A^H A
+// from the SplitMix64 start vector, or the given alpha) and X_0 = alpha A^H into X0.  `dw` holds
+// 4 (Dv + Dv) doubles with Dv >= max(m, n).  Returns false (info.status = ENONFINITE) for a non-finite A.
+__device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsigned long long seed, double alpha_given, const DM& A,
+                             const DM& X0, double* dw, int Dv, double* sh, float* lds, BInfo& info, double& normA,
+                             double& alpha) {
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int lane = tid & 63, nw = nthr >> 6;
+  const int m = A.rows, n = A.cols;
+  double fro2 = 0.0, nf = 0.0;
+  for (int e = tid; e < m * n; e += nthr) {
+    const int i = e / n, j = e - i * n;
+    for (int p = 0; p < 4; ++p) {
+      const double v = A.p[p * A.ps + (int64_t)i * A.ld + j];
+      if (!__builtin_isfinite(v)) nf += 1.0;
+      fro2 += v * v;
+    }
+  }
+  fro2 = wg_sum(fro2, sh);
+  nf = wg_sum(nf, sh);
+  if (nf > 0.0) {
+    info.status = -2;
+    return false;
+  }
+  normA = sqrt(fro2);
+  if (scaling == 2) {
+    alpha = alpha_given;
+  } else {
+    double* v = dw;            // 4n
+    double* wv = dw + 4 * Dv;  // 4m
+    for (int e = tid; e < 4 * n; e += nthr) v[e] = (double)(bsplitmix64((uint64_t)e, seed) >> 11) * 0x1p-52 - 1.0;
+    __syncthreads();
+    double lam = 0.0;
+    for (int k = 0; k < power_steps; ++k) {
+      double nv = 0.0;
+      for (int e = tid; e < 4 * n; e += nthr) nv += v[e] * v[e];
+      nv = wg_sum(nv, sh);
+      const double inv = 1.0 / sqrt(nv);
+      // w = A v: one wave per row, lanes along the row (coalesced), fixed-order wave reduction
+#pragma unroll 2
+      for (int i = tid >> 6; i < m; i += nw) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int j = lane; j < n; j += 64) {
+          const int64_t o = (int64_t)i * A.ld + j;
+          const double as = A.p[o], ax = A.p[A.ps + o], ay = A.p[2 * A.ps + o], az = A.p[3 * A.ps + o];
+          const double vs = v[j], vx = v[n + j], vy = v[2 * n + j], vz = v[3 * n + j];
+          s0 += as * vs - ax * vx - ay * vy - az * vz;
+          s1 += as * vx + ax * vs + ay * vz - az * vy;
+          s2 += as * vy - ax * vz + ay * vs + az * vx;
+          s3 += as * vz + ax * vy - ay * vx + az * vs;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          s0 += __shfl_xor(s0, off, 64);
+          s1 += __shfl_xor(s1, off, 64);
+          s2 += __shfl_xor(s2, off, 64);
+          s3 += __shfl_xor(s3, off, 64);
+        }
+        if (lane == 0) {
+          wv[i] = s0 * inv;
+          wv[m + i] = s1 * inv;
+          wv[2 * m + i] = s2 * inv;
+          wv[3 * m + i] = s3 * inv;
+        }
+      }
+      __syncthreads();
+      double l2 = 0.0;
+      for (int e = tid; e < 4 * m; e += nthr) l2 += wv[e] * wv[e];
+      lam = wg_sum(l2, sh);
+      // v = A^H w: lanes along 64 columns (coalesced), the waves split the rows; the waves' partial
+      // sums are added in wave order through LDS
+      double* red = reinterpret_cast<double*>(lds);  // [waves][64][4]
+      for (int j0 = 0; j0 < n; j0 += 64) {
+        const int j = j0 + lane;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (j < n) {
+#pragma unroll 4
+          for (int i = tid >> 6; i < m; i += nw) {
+            const int64_t o = (int64_t)i * A.ld + j;
+            const double as = A.p[o], ax = A.p[A.ps + o], ay = A.p[2 * A.ps + o], az = A.p[3 * A.ps + o];
+            const double ws = wv[i], wx = wv[m + i], wy = wv[2 * m + i], wz = wv[3 * m + i];
+            s0 += as * ws + ax * wx + ay * wy + az * wz;
+            s1 += as * wx - ax * ws - ay * wz + az * wy;
+            s2 += as * wy + ax * wz - ay * ws - az * wx;
+            s3 += as * wz - ax * wy + ay * wx - az * ws;
+          }
+        }
+        double* r = red + (int64_t)(tid >> 6) * 256 + lane * 4;
+        r[0] = s0;
+        r[1] = s1;
+        r[2] = s2;
+        r[3] = s3;
+        __syncthreads();
+        if (tid < 64 && j < n) {
+          double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+          for (int q = 0; q < nw; ++q) {
+            const double* rq = red + q * 256 + lane * 4;
+            t0 += rq[0];
+            t1 += rq[1];
+            t2 += rq[2];
+            t3 += rq[3];
+          }
+          v[j] = t0;
+          v[n + j] = t1;
+          v[2 * n + j] = t2;
+          v[3 * n + j] = t3;
+        }
+        __syncthreads();
+      }
+    }
+    info.sigma1_sq = lam;
+    alpha = 1.0 / lam;
+  }
+  info.alpha = alpha;
+  // X_0 = alpha A^H, transposed through 32 x 32 LDS tiles (coalesced reads and writes)
+  float* tile = lds;  // [32][33]
+  const int tr = tid >> 5, tc = tid & 31, rstep = nthr >> 5;
+  for (int ib = 0; ib < m; ib += 32)
+    for (int jb = 0; jb < n; jb += 32)
+      for (int p = 0; p < 4; ++p) {
+        const double sc = p == 0 ? alpha : -alpha;
+        for (int r = tr; r < 32; r += rstep) {
+          const int i = ib + r, j = jb + tc;
+          tile[r * 33 + tc] = (i < m && j < n) ? A.p[p * A.ps + (int64_t)i * A.ld + j] : 0.f;
+        }
+        __syncthreads();
+        for (int r = tr; r < 32; r += rstep) {
+          const int j = jb + r, i = ib + tc;
+          if (j < n && i < m) X0.p[p * X0.ps + (int64_t)j * X0.ld + i] = (float)(sc * (double)tile[tc * 33 + r]);
+        }
+        __syncthreads();
+      }
+  __threadfence_block();
+  __syncthreads();
+  return true;
+}
+
 template <class MM, int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) batched_kernel(BParams P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
-  __shared__ float smem[C::SMEM];
+  __shared__ __attribute__((aligned(16))) float smem[C::SMEM];
   __shared__ double sh[16];
   __shared__ int s_next;
   const int tid = threadIdx.x;
@@ -211,92 +349,13 @@ __global__ void __launch_bounds__(64 * WM * WN) batched_kernel(BParams P) {
     info.dx_rel = 0.0;
     info.sigma1_sq = 0.0;
 
-    // ---------------------------------------------------------------- norm and finiteness of A
-    double fro2 = 0.0, nf = 0.0;
-    for (int e = tid; e < m * n; e += nthr) {
-      const int i = e / n, j = e - i * n;
-      for (int p = 0; p < 4; ++p) {
-        const double v = A.p[p * A.ps + (int64_t)i * A.ld + j];
-        if (!__builtin_isfinite(v)) nf += 1.0;
-        fro2 += v * v;
-      }
-    }
-    fro2 = wg_sum(fro2, sh);
-    nf = wg_sum(nf, sh);
-    if (nf > 0.0) {
-      info.status = -2;
+    DM X[4] = {buf(BX, n, m), buf(BX + 1, n, m), buf(BX + 2, n, m), buf(BX + 3, n, m)};
+    double normA = 0.0, alpha = 0.0;
+    if (!setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, X[0], dw, D, sh, smem,
+                      info, normA, alpha)) {
       if (tid == 0) P.info[b] = info;
       continue;
     }
-    const double normA = sqrt(fro2);
-
-    // ---------------------------------------------------------------- scaling
-    double alpha;
-    if (P.scaling == 2) {
-      alpha = P.alpha[b];
-    } else {
-      double* v = dw;          // 4n
-      double* wv = dw + 4 * D;  // 4m
-      for (int e = tid; e < 4 * n; e += nthr) v[e] = (double)(bsplitmix64((uint64_t)e, P.seed) >> 11) * 0x1p-52 - 1.0;
-      __syncthreads();
-      double lam = 0.0;
-      for (int k = 0; k < P.power_steps; ++k) {
-        double nv = 0.0;
-        for (int e = tid; e < 4 * n; e += nthr) nv += v[e] * v[e];
-        nv = wg_sum(nv, sh);
-        const double inv = 1.0 / sqrt(nv);
-        for (int i = tid; i < m; i += nthr) {
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-          for (int j = 0; j < n; ++j) {
-            const int64_t o = (int64_t)i * A.ld + j;
-            const double as = A.p[o], ax = A.p[A.ps + o], ay = A.p[2 * A.ps + o], az = A.p[3 * A.ps + o];
-            const double vs = v[j], vx = v[n + j], vy = v[2 * n + j], vz = v[3 * n + j];
-            s0 += as * vs - ax * vx - ay * vy - az * vz;
-            s1 += as * vx + ax * vs + ay * vz - az * vy;
-            s2 += as * vy - ax * vz + ay * vs + az * vx;
-            s3 += as * vz + ax * vy - ay * vx + az * vs;
-          }
-          wv[i] = s0 * inv;
-          wv[m + i] = s1 * inv;
-          wv[2 * m + i] = s2 * inv;
-          wv[3 * m + i] = s3 * inv;
-        }
-        __syncthreads();
-        double l2 = 0.0;
-        for (int e = tid; e < 4 * m; e += nthr) l2 += wv[e] * wv[e];
-        lam = wg_sum(l2, sh);
-        for (int j = tid; j < n; j += nthr) {
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-          for (int i = 0; i < m; ++i) {
-            const int64_t o = (int64_t)i * A.ld + j;
-            const double as = A.p[o], ax = A.p[A.ps + o], ay = A.p[2 * A.ps + o], az = A.p[3 * A.ps + o];
-            const double ws = wv[i], wx = wv[m + i], wy = wv[2 * m + i], wz = wv[3 * m + i];
-            s0 += as * ws + ax * wx + ay * wy + az * wz;
-            s1 += as * wx - ax * ws - ay * wz + az * wy;
-            s2 += as * wy + ax * wz - ay * ws - az * wx;
-            s3 += as * wz - ax * wy + ay * wx - az * ws;
-          }
-          v[j] = s0;
-          v[n + j] = s1;
-          v[2 * n + j] = s2;
-          v[3 * n + j] = s3;
-        }
-        __syncthreads();
-      }
-      info.sigma1_sq = lam;
-      alpha = 1.0 / lam;
-    }
-    info.alpha = alpha;
-
-    // ---------------------------------------------------------------- X_0 = alpha A^H
-    DM X[4] = {buf(BX, n, m), buf(BX + 1, n, m), buf(BX + 2, n, m), buf(BX + 3, n, m)};
-    for (int e = tid; e < m * n; e += nthr) {
-      const int i = e / n, j = e - i * n;
-      for (int p = 0; p < 4; ++p)
-        X[0].p[p * PS + (int64_t)j * D + i] = (float)((p == 0 ? alpha : -alpha) * (double)A.p[p * A.ps + (int64_t)i * A.ld + j]);
-    }
-    __threadfence_block();
-    __syncthreads();
 
     // ---------------------------------------------------------------- iterations
     StopController ctl(P.stop, P.tol);
@@ -511,13 +570,685 @@ __global__ void __launch_bounds__(64 * WM * WN) batched_kernel(BParams P) {
 }
 
 // ------------------------------------------------------------------------------------------------
+// Phase-synchronous form: all matrices advance one product of the method at a time.  Each phase's
+// work items are the output tiles of that product over every still-active matrix; the workgroups
+// (all resident: the grid is at most the occupancy times the compute units) take items i, i + G, ...,
+// then meet at a grid barrier.  After the update phase a controller phase (one workgroup per active
+// matrix) sums the update's per-tile change norms in tile order, applies the stop rule and either
+// retires the matrix (copying its chosen iterate out) or moves it to the next update.  A large matrix
+// is thus spread over many compute units instead of one, and small ones fill the gaps.
+//
+// The grid barrier is a counter and a generation word in device memory; arrival releases this
+// workgroup's writes at device scope and leaving acquires the others'.  Every wait is bounded: a
+// workgroup that waits too long raises the flag, and every workgroup leaves at the next barrier it
+// sees the flag at, so the grid always drains.
+// ------------------------------------------------------------------------------------------------
+struct LState {
+  int active, status, reason, returned;
+  int pending;   // 1: the two candidate products of the rise rule are due (phases 1 and 2)
+  int copy_buf;  // >= 0: copy this iterate to the caller's X in phase 1 of the next pass, then retire
+  int j;  // updates done; the current iterate is X_j
+  int cur, best0, best1, best_j;
+  int rsj0, rsj1;  // iterates whose residuals the R buffers 0 and 1 hold
+  double alpha, normA, sigma1_sq, xn_prev, xn_a, xn_b, dx_rel;
+  StopController ctl;
+};
+
+struct SParams {
+  const BDesc* desc;
+  BInfo* info;
+  LState* st;
+  int count;
+  float* pool;
+  double* partial;
+  double* dwork;
+  unsigned int* bar;  // [0] arrivals, [1] generation, [2] timeout flag
+  const double* alpha;
+  int method, stop, max_iter;
+  double tol;
+  int scaling, power_steps;
+  unsigned long long seed;
+  Coef k;
+  unsigned long long* trace;  // optional: workgroup 0 stamps wall_clock64() after every grid barrier
+  int trace_cap;
+};
+
+constexpr int SYNC_MAX = 2048;
+constexpr int kTraceCap = 4096;  // barrier time stamps kept per launch      // matrices per launch (the per-phase tile prefix lives in LDS)
+constexpr long long SPIN_MAX = 1ll << 22;  // barrier polls before the wait is abandoned
+
+// Grid barrier; returns false once any workgroup has abandoned a wait.
+__device__ bool grid_sync(unsigned int* bar, unsigned int nblocks) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();
+    const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == nblocks) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > SPIN_MAX) {
+          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();
+    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ok = 0;
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Views of matrix b's work buffers: 10 of s x s (chain 0..7, residuals 8..9) and 5 of n x m (iterates
+// 0..3, candidate product 4).
+struct MBufs {
+  float* base;
+  int64_t lds, pss, ldw, psw;
+  int s, m, n;
+  __device__ DM sq(int k) const {
+    DM v;
+    v.p = base + (int64_t)k * 4 * pss;
+    v.ld = lds;
+    v.ps = pss;
+    v.rows = v.cols = s;
+    return v;
+  }
+  __device__ DM xw(int k) const {
+    DM v;
+    v.p = base + 10 * 4 * pss + (int64_t)k * 4 * psw;
+    v.ld = ldw;
+    v.ps = psw;
+    v.rows = n;
+    v.cols = m;
+    return v;
+  }
+};
+
+__device__ __forceinline__ MBufs mbufs(const SParams& P, const BDesc& d) {
+  MBufs B;
+  B.base = P.pool + d.off;
+  B.lds = d.lds;
+  B.pss = d.pss;
+  B.ldw = d.ldw;
+  B.psw = d.psw;
+  B.m = d.m;
+  B.n = d.n;
+  B.s = d.m > d.n ? d.n : d.m;
+  return B;
+}
+
+__device__ __forceinline__ int num_phases(int method) { return method == 0 ? 2 : method == 2 ? 6 : 7; }
+
+// The product of phase `ph` (1-based; the last one is the update) of matrix b with iterate X_cur into
+// X_nxt: operands, output shape and epilogue.
+__device__ __forceinline__ void phase_product(const SParams& P, const MBufs& B, const LState& S, int nxt, int ph, DM& Aop, DM& Bop,
+                              DEpi& e) {
+  const bool left = B.m > B.n;
+  const DM Xc = B.xw(S.cur), Xn = B.xw(nxt);
+  const DM R = B.sq(8 + (S.j & 1));
+  const int np = num_phases(P.method);
+  e = DEpi();
+  if (ph == np) {  // update: T X (left) or X T (right), change norms against X_cur
+    const DM T = P.method == 0 ? B.sq(1) : P.method == 2 ? B.sq(2) : B.sq(5);
+    e = epi_out(Xn);
+    e.nin = 1;
+    e.in[0] = Xc;
+    e.ref = 0;
+    e.reduce = 1;
+    Aop = left ? T : Xc;
+    Bop = left ? Xc : T;
+    return;
+  }
+  if (ph == 1) {  // side product: X A (left) or A X (right); the caller fills the A view
+    Aop = Xc;  // placeholder, replaced by the caller
+    Bop = Xc;
+    if (P.method == 0) {  // T = 2I - prod, R = I - prod
+      e = epi_out(B.sq(1), -1.f, 2.f);
+      e.nout = 2;
+      e.out[1] = R;
+      e.a[1] = -1.f;
+      e.g[1] = 1.f;
+    } else if (P.method == 2) {  // R and Sp = 2I - prod
+      e = epi_out(R, -1.f, 1.f);
+      e.nout = 2;
+      e.out[1] = B.sq(1);
+      e.a[1] = -1.f;
+      e.g[1] = 2.f;
+    } else {
+      e = epi_out(R, -1.f, 1.f);
+    }
+    return;
+  }
+  if (P.method == 2) {  // QSAI: R2 = R R; P1, P2 from R2 R2; Q = P1 P2; T = Sp Q
+    if (ph == 2) {
+      Aop = R;
+      Bop = R;
+      e = epi_out(B.sq(2));
+    } else if (ph == 3) {
+      Aop = B.sq(2);
+      Bop = B.sq(2);
+      e.nout = 2;
+      e.out[0] = B.sq(3);
+      e.out[1] = B.sq(4);
+      e.nin = 1;
+      e.in[0] = B.sq(2);
+      e.b[0][0] = P.k.beta1;
+      e.b[1][0] = P.k.beta2;
+      e.g[0] = e.g[1] = 1.f;
+    } else if (ph == 4) {
+      Aop = B.sq(3);
+      Bop = B.sq(4);
+      e = epi_out(B.sq(5));
+    } else {  // ph == 5
+      Aop = B.sq(1);
+      Bop = B.sq(5);
+      e = epi_out(B.sq(2));
+    }
+    return;
+  }
+  // QHPI19 (Algorithm 3): R2 (+ S = R + R2); R4 (+ P1, P2); V, W from P1 P2; G = V W + ...; T = I + S G
+  const DM R2 = B.sq(0), R4 = B.sq(2), Sm = B.sq(3), P1 = B.sq(4), P2 = B.sq(5), V = B.sq(6), W = B.sq(7);
+  if (ph == 2) {
+    Aop = R;
+    Bop = R;
+    e = epi_out(R2);
+    e.nout = 2;
+    e.out[1] = Sm;
+    e.nin = 1;
+    e.in[0] = R;
+    e.b[1][0] = 1.f;
+  } else if (ph == 3) {
+    Aop = R2;
+    Bop = R2;
+    e = epi_out(R4);
+    e.nout = 3;
+    e.out[1] = P1;
+    e.out[2] = P2;
+    e.nin = 1;
+    e.in[0] = R2;
+    e.b[1][0] = P.k.d1;
+    e.b[2][0] = P.k.d2;
+    e.g[1] = e.g[2] = 1.f;
+  } else if (ph == 4) {
+    Aop = P1;
+    Bop = P2;
+    e.nout = 2;
+    e.out[0] = V;
+    e.out[1] = W;
+    e.nin = 2;
+    e.in[0] = R2;
+    e.in[1] = R4;
+    e.b[0][0] = P.k.d3;
+    e.b[1][0] = P.k.e1;
+    e.b[1][1] = P.k.e2;
+  } else if (ph == 5) {
+    Aop = V;
+    Bop = W;
+    e = epi_out(P1);
+    e.nin = 2;
+    e.in[0] = R2;
+    e.in[1] = R4;
+    e.b[0][0] = P.k.c1;
+    e.b[0][1] = P.k.c2;
+  } else {  // ph == 6
+    Aop = Sm;
+    Bop = P1;
+    e = epi_out(P2, 1.f, 1.f);
+  }
+}
+
+// Workgroup-uniform values built from loaded data move to scalar registers (every lane holds the
+// same value), which keeps the per-item product parameters out of the vector register budget.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+template <class T>
+__device__ __forceinline__ T* uni(T* p) {
+  return reinterpret_cast<T*>(uni((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+__device__ __forceinline__ void make_uniform(GemmParams<float>& G) {
+  G.A = uni(G.A);
+  G.lda = uni(G.lda);
+  G.psa = uni(G.psa);
+  G.B = uni(G.B);
+  G.ldb = uni(G.ldb);
+  G.psb = uni(G.psb);
+  G.M = uni(G.M);
+  G.N = uni(G.N);
+  G.K = uni(G.K);
+  G.tiles_m = uni(G.tiles_m);
+  G.tiles_n = uni(G.tiles_n);
+  G.vec = uni(G.vec);
+  G.nout = uni(G.nout);
+  G.nin = uni(G.nin);
+  G.ref = uni(G.ref);
+  G.reduce = uni(G.reduce);
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    G.out[t] = uni(G.out[t]);
+    G.ldo[t] = uni(G.ldo[t]);
+    G.pso[t] = uni(G.pso[t]);
+    G.in[t] = uni(G.in[t]);
+    G.ldi[t] = uni(G.ldi[t]);
+    G.psi[t] = uni(G.psi[t]);
+    G.ca[t] = uni(G.ca[t]);
+    G.cg[t] = uni(G.cg[t]);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) G.cb[t][u] = uni(G.cb[t][u]);
+  }
+}
+
+// GemmParams of C = Aop Bop with epilogue e (FP32 storage).
+__device__ __forceinline__ GemmParams<float> gemm_params(const DM& Aop, const DM& Bop, const DEpi& e, int BM, int BN) {
+  GemmParams<float> G;
+  G.A = Aop.p;
+  G.lda = Aop.ld;
+  G.psa = Aop.ps;
+  G.B = Bop.p;
+  G.ldb = Bop.ld;
+  G.psb = Bop.ps;
+  G.M = Aop.rows;
+  G.N = Bop.cols;
+  G.K = Aop.cols;
+  G.tiles_m = (G.M + BM - 1) / BM;
+  G.tiles_n = (G.N + BN - 1) / BN;
+  G.vec = ((Aop.ld | Aop.ps | Bop.ld | Bop.ps) & 3) == 0;
+  G.nout = e.nout;
+  G.nin = e.nin;
+  G.ref = e.ref;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    G.out[t] = e.out[t].p;
+    G.ldo[t] = e.out[t].ld;
+    G.pso[t] = e.out[t].ps;
+    G.in[t] = e.in[t].p;
+    G.ldi[t] = e.in[t].ld;
+    G.psi[t] = e.in[t].ps;
+    G.ca[t] = e.a[t];
+    G.cg[t] = e.g[t];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) G.cb[t][u] = e.b[t][u];
+  }
+  G.partial = nullptr;
+  G.reduce = e.reduce;
+  return G;
+}
+
+template <int BM, int BN>
+__device__ __forceinline__ int tiles_of(int rows, int cols) {
+  return ((rows + BM - 1) / BM) * ((cols + BN - 1) / BN);
+}
+
+// next free iterate buffer: not the current one and not the pair kept around the smallest change
+__device__ __forceinline__ int next_buf(const LState& S) {
+  int nxt = 0;
+  while (nxt == S.cur || nxt == S.best0 || nxt == S.best1) ++nxt;
+  return nxt;
+}
+
+template <class MM, int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P) {
+  using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
+  __shared__ __attribute__((aligned(16))) float smem[C::SMEM];
+  __shared__ double sh[16];
+  __shared__ int pref[SYNC_MAX + 1];
+  __shared__ int s_mn[SYNC_MAX];  // m | n << 16 per matrix
+  __shared__ int s_total;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const unsigned int G = gridDim.x;
+  const int np = num_phases(P.method);
+  unsigned long long* const trace = (blockIdx.x == 0 && tid == 0) ? P.trace : nullptr;
+  const int trace_cap = P.trace_cap;
+  int nstamp = 0;
+#define QP_STAMP()                                            \
+  do {                                                        \
+    if (trace && nstamp < trace_cap) trace[nstamp] = wall_clock64(); \
+    ++nstamp;                                                 \
+  } while (0)
+  QP_STAMP();
+
+  for (int b = tid; b < P.count; b += nthr) s_mn[b] = P.desc[b].m | (P.desc[b].n << 16);
+
+  // ---------------------------------------------------------------- set-up: one workgroup per matrix
+  for (int b = blockIdx.x; b < P.count; b += G) {
+    const BDesc d = P.desc[b];
+    const MBufs B = mbufs(P, d);
+    DM A;
+    A.p = const_cast<float*>(d.A);
+    A.ld = d.lda;
+    A.ps = d.psa;
+    A.rows = d.m;
+    A.cols = d.n;
+    BInfo info;
+    info.iters = 0;
+    info.returned = 0;
+    info.reason = 0;
+    info.status = 0;
+    info.alpha = 0.0;
+    info.dx_rel = 0.0;
+    info.sigma1_sq = 0.0;
+    double normA = 0.0, alpha = 0.0;
+    const int Dv = d.m > d.n ? d.m : d.n;
+    const bool ok = setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, B.xw(0),
+                                 P.dwork + d.doff, Dv, sh, smem, info, normA, alpha);
+    if (tid == 0) {
+      LState S;
+      S.active = ok ? 1 : 0;
+      S.pending = 0;
+      S.copy_buf = -1;
+      S.status = info.status;
+      S.reason = 0;
+      S.returned = 0;
+      S.j = 0;
+      S.cur = 0;
+      S.best0 = S.best1 = S.best_j = -1;
+      S.rsj0 = S.rsj1 = -1;
+      S.alpha = alpha;
+      S.normA = normA;
+      S.sigma1_sq = info.sigma1_sq;
+      S.xn_prev = S.xn_a = S.xn_b = 0.0;
+      S.dx_rel = 0.0;
+      S.ctl = StopController(P.stop, P.tol);
+      P.st[b] = S;
+      if (!ok) P.info[b] = info;
+    }
+    __syncthreads();
+  }
+  if (!grid_sync(P.bar, G)) return;
+  QP_STAMP();
+
+  // ---------------------------------------------------------------- updates
+  // max_iter updates, plus one pass for the rise rule's candidate products
+  for (int it = 0; it <= P.max_iter + 1; ++it) {
+    for (int ph = 1; ph <= np + 1; ++ph) {
+      // tile counts of this phase over the active matrices (phase np + 1: one item per active matrix)
+      const int per = (P.count + nthr - 1) / nthr;
+      int loc = 0;
+      for (int q = 0; q < per; ++q) {
+        const int b = tid * per + q;
+        int c = 0;
+        if (b < P.count && P.st[b].active) {
+          const int mb = s_mn[b] & 0xffff, nb = s_mn[b] >> 16;
+          const int sd = mb > nb ? nb : mb;
+          if (P.st[b].copy_buf >= 0)  // the result copy, then the controller
+            c = ph > np ? 1 : ph == 1 ? tiles_of<BM, BN>(nb, mb) : 0;
+          else if (P.st[b].pending)  // the rise rule's two candidate products, then the controller
+            c = ph > np ? 1 : ph <= 2 ? tiles_of<BM, BN>(nb, mb) : 0;
+          else
+            c = ph > np ? 1 : ph == np ? tiles_of<BM, BN>(nb, mb) : tiles_of<BM, BN>(sd, sd);
+        }
+        if (b < P.count) pref[b + 1] = c;
+        loc += c;
+      }
+      // exclusive scan: per-thread totals through the workgroup, then each thread's run
+      __syncthreads();
+      if (tid == 0) pref[0] = 0;
+      {
+        __shared__ int part[1024];
+        part[tid] = loc;
+        __syncthreads();
+        if (tid == 0) {
+          int acc = 0;
+          for (int t = 0; t < nthr; ++t) {
+            const int v = part[t];
+            part[t] = acc;
+            acc += v;
+          }
+          s_total = acc;
+        }
+        __syncthreads();
+        int run = part[tid];
+        for (int q = 0; q < per; ++q) {
+          const int b = tid * per + q;
+          if (b < P.count) {
+            const int c = pref[b + 1];
+            pref[b + 1] = run + c;
+            run += c;
+          }
+        }
+      }
+      __syncthreads();
+      const int total = s_total;
+      if (ph == 1 && total == 0) return;  // nothing active: every workgroup sees the same states
+      for (int item = blockIdx.x; item < total; item += G) {
+        // matrix of this item: last b with pref[b] <= item
+        int lo = 0, hi = P.count;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (pref[mid] <= item) lo = mid; else hi = mid;
+        }
+        const int b = lo;
+        const int t = item - pref[b];
+        const BDesc d = P.desc[b];
+        const MBufs B = mbufs(P, d);
+        LState S = P.st[b];
+        if (ph <= np && S.copy_buf >= 0) {
+          // tile t of the chosen iterate to the caller's X
+          const DM Xr = B.xw(S.copy_buf);
+          const int tn = (d.m + BN - 1) / BN;
+          const int r0 = (t / tn) * BM, c0 = (t % tn) * BN;
+          for (int e = tid; e < BM * BN; e += nthr) {
+            const int i = r0 + e / BN, c = c0 + e % BN;
+            if (i < d.n && c < d.m)
+#pragma unroll
+              for (int p = 0; p < 4; ++p)
+                d.X[p * d.psx + (int64_t)i * d.ldx + c] = Xr.p[p * Xr.ps + (int64_t)i * Xr.ld + c];
+          }
+          continue;
+        }
+        if (ph <= np && S.pending) {
+          // candidate product ph of the rise rule: R_k X_k (left) or X_k R_k (right), k = best_j - 1, best_j
+          const bool left = d.m > d.n;
+          const int kc = ph == 1 ? S.best_j - 1 : S.best_j;
+          const DM Rr = B.sq(8 + (kc & 1));
+          const DM Xr = B.xw(ph == 1 ? S.best0 : S.best1);
+          DEpi eo = epi_out(B.xw(4));
+          eo.reduce = 1;
+          GemmParams<float> Gp = left ? gemm_params(Rr, Xr, eo, BM, BN) : gemm_params(Xr, Rr, eo, BM, BN);
+          make_uniform(Gp);
+          double a0 = 0.0, a1 = 0.0;
+          gemm_tile<MM, BM, BN, BK, WM, WN, 128>(Gp, t / Gp.tiles_n, t % Gp.tiles_n, smem, a0, a1);
+          a0 = wg_sum(a0, sh);
+          if (tid == 0) P.partial[d.poff + 2 * ((ph - 1) * tiles_of<BM, BN>(d.n, d.m) + t)] = a0;
+          __syncthreads();
+          continue;
+        }
+        if (ph <= np) {
+          DM Aop, Bop;
+          DEpi e;
+          const int nxt = next_buf(S);
+          phase_product(P, B, S, nxt, ph, Aop, Bop, e);
+          if (ph == np) {  // the new iterate also goes to the caller's X (the result unless the rise rule picks)
+            e.nout = 2;
+            e.out[1].p = d.X;
+            e.out[1].ld = d.ldx;
+            e.out[1].ps = d.psx;
+            e.a[1] = 1.f;
+          }
+          if (ph == 1) {
+            DM A;
+            A.p = const_cast<float*>(d.A);
+            A.ld = d.lda;
+            A.ps = d.psa;
+            A.rows = d.m;
+            A.cols = d.n;
+            const DM Xc = B.xw(S.cur);
+            const bool left = d.m > d.n;
+            Aop = left ? Xc : A;
+            Bop = left ? A : Xc;
+          }
+          GemmParams<float> Gp = gemm_params(Aop, Bop, e, BM, BN);
+          make_uniform(Gp);
+          double a0 = 0.0, a1 = 0.0;
+          gemm_tile<MM, BM, BN, BK, WM, WN, 128>(Gp, t / Gp.tiles_n, t % Gp.tiles_n, smem, a0, a1);
+          if (ph == np) {
+            a0 = wg_sum(a0, sh);
+            a1 = wg_sum(a1, sh);
+            if (tid == 0) {
+              P.partial[d.poff + 2 * t] = a0;
+              P.partial[d.poff + 2 * t + 1] = a1;
+            }
+          }
+          __syncthreads();
+          continue;
+        }
+        // ---------------------------------------------------------------- controller of matrix b
+        const int nxt = next_buf(S);
+        const int ntile = tiles_of<BM, BN>(d.n, d.m);
+        if (S.copy_buf >= 0) {  // the copy ran in phase 1 of this pass
+          S.copy_buf = -1;
+          S.active = 0;
+          if (tid == 0) {
+            BInfo info;
+            info.iters = S.j;
+            info.returned = S.returned;
+            info.reason = S.reason;
+            info.status = S.status;
+            info.alpha = S.alpha;
+            info.dx_rel = S.dx_rel;
+            info.sigma1_sq = S.sigma1_sq;
+            P.info[b] = info;
+            P.st[b] = S;
+          }
+          __syncthreads();
+          continue;
+        }
+        if (S.pending) {
+          // finish the rise rule: the better of X_{best_j - 1}, X_{best_j} by ||XAX - X||_F / ||X||_F
+          double qa = 0.0, qb = 0.0;
+          for (int q = tid; q < ntile; q += nthr) {
+            qa += P.partial[d.poff + 2 * q];
+            qb += P.partial[d.poff + 2 * (ntile + q)];
+          }
+          qa = wg_sum(qa, sh);
+          qb = wg_sum(qb, sh);
+          const double ea = sqrt(qa) / fmax(S.xn_a, 1e-300), eb = sqrt(qb) / fmax(S.xn_b, 1e-300);
+          const int ka = S.best_j - 1;
+          const int done_buf = (ka >= 1 && ea < eb) ? S.best0 : S.best1;
+          S.returned = (ka >= 1 && ea < eb) ? ka : S.best_j;
+          S.pending = 0;
+          S.copy_buf = done_buf;  // an older iterate: copied in the next pass
+          if (tid == 0) P.st[b] = S;
+          __syncthreads();
+          continue;
+        }
+        double sd0 = 0.0, sx0 = 0.0;
+        for (int q = tid; q < ntile; q += nthr) {
+          sd0 += P.partial[d.poff + 2 * q];
+          sx0 += P.partial[d.poff + 2 * q + 1];
+        }
+        const double sdv = wg_sum(sd0, sh), sxv = wg_sum(sx0, sh);
+        const double d_abs = sqrt(fmax(sdv, 0.0)), xn = sqrt(fmax(sxv, 0.0));
+        const int j = S.j + 1;  // index of the new iterate X_j = buffer nxt
+        if (S.j & 1)  // this update's residual belongs to X_{j-1}
+          S.rsj1 = S.j;
+        else
+          S.rsj0 = S.j;
+        S.dx_rel = xn > 0.0 ? d_abs / xn : 0.0;
+        int done_buf = -1;
+        if (!__builtin_isfinite(d_abs) || !__builtin_isfinite(xn) || xn * S.normA > 1e20) {
+          S.reason = 3;
+          S.status = -3;
+          S.returned = __builtin_isfinite(xn) ? j : j - 1;
+          done_buf = __builtin_isfinite(xn) ? nxt : S.cur;
+        } else {
+          const int dec = S.ctl.update(j, d_abs, xn, -1.0);
+          if (dec == D_TOL) {
+            S.reason = 0;
+            S.returned = j;
+            done_buf = nxt;
+          } else if (dec == D_RISE) {
+            S.reason = 1;
+            const int ka = S.best_j - 1, kb = S.best_j;
+            const int ra = (ka & 1) ? S.rsj1 : S.rsj0, rb = (kb & 1) ? S.rsj1 : S.rsj0;
+            if (ka >= 0 && ra == ka && rb == kb) {
+              S.pending = 1;  // the candidate products run in the next pass over the phases
+            } else {
+              S.returned = kb;
+              done_buf = S.best1;
+            }
+          } else if (dec == D_DIVERGED) {
+            S.reason = 3;
+            S.status = -3;
+            S.returned = j - 1;
+            done_buf = S.cur;
+          } else {
+            if (dec == D_NEWMIN) {
+              S.best0 = S.cur;
+              S.best1 = nxt;
+              S.best_j = j;
+              S.xn_a = S.xn_prev;
+              S.xn_b = xn;
+            }
+            S.xn_prev = xn;
+            S.cur = nxt;
+            if (j >= P.max_iter) {
+              S.reason = 2;
+              S.status = -4;
+              S.returned = j;
+              done_buf = nxt;
+            }
+          }
+        }
+        S.j = j;
+        if (done_buf >= 0 && done_buf != nxt) {  // not the iterate the update wrote to the caller's X
+          S.copy_buf = done_buf;
+          done_buf = -1;
+        }
+        if (done_buf >= 0) {
+          S.active = 0;
+          if (tid == 0) {
+            BInfo info;
+            info.iters = j;
+            info.returned = S.returned;
+            info.reason = S.reason;
+            info.status = S.status;
+            info.alpha = S.alpha;
+            info.dx_rel = S.dx_rel;
+            info.sigma1_sq = S.sigma1_sq;
+            P.info[b] = info;
+          }
+        }
+        if (tid == 0) P.st[b] = S;
+        __syncthreads();
+      }
+      if (!grid_sync(P.bar, G)) return;
+      QP_STAMP();
+    }
+  }
+#undef QP_STAMP
+}
+
+// ------------------------------------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------------------------------------
 using BatchedLaunch = void (*)(const BParams&, int grid, hipStream_t);
+using SyncLaunch = void (*)(const SParams&, int grid, hipStream_t);
 
 template <class MM, int BM, int BN, int BK, int WM, int WN>
 static void launch_batched(const BParams& P, int grid, hipStream_t s) {
   hipLaunchKernelGGL((batched_kernel<MM, BM, BN, BK, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, s, P);
+  QP_HIP(hipGetLastError());
+}
+
+template <class MM, int BM, int BN, int BK, int WM, int WN>
+static void launch_sync(const SParams& P, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((batched_sync_kernel<MM, BM, BN, BK, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, s, P);
   QP_HIP(hipGetLastError());
 }
 
@@ -528,26 +1259,79 @@ static int occupancy_of() {
   return std::max(nb, 1);
 }
 
+template <class MM, int BM, int BN, int BK, int WM, int WN>
+static int occupancy_sync() {
+  int nb = 0;
+  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_sync_kernel<MM, BM, BN, BK, WM, WN>, 64 * WM * WN,
+                                                      0));
+  return std::max(nb, 1);
+}
+
+// Queue kernels (one workgroup per matrix) and phase-synchronous kernels (all workgroups per product).
 struct BatchedEntry {
   const char* name;
   BatchedLaunch fn;
+  SyncLaunch sfn;
   int (*occ)();
+  int bm, bn;
 };
 
 static const std::vector<BatchedEntry>& batched_table() {
   static const std::vector<BatchedEntry> t = {
-      {"batched_f32_32x32x16_mfma16", launch_batched<MM16F, 32, 32, 16, 2, 2>, occupancy_of<MM16F, 32, 32, 16, 2, 2>},
-      {"batched_f32_64x64x16_mfma32", launch_batched<MM32F, 64, 64, 16, 2, 2>, occupancy_of<MM32F, 64, 64, 16, 2, 2>},
-      {"batched_f32_64x64x16_mfma16", launch_batched<MM16F, 64, 64, 16, 2, 2>, occupancy_of<MM16F, 64, 64, 16, 2, 2>},
+      {"batched_f32_32x32x16_mfma16", launch_batched<MM16F, 32, 32, 16, 2, 2>, nullptr,
+       occupancy_of<MM16F, 32, 32, 16, 2, 2>, 32, 32},
+      {"batched_f32_64x64x16_mfma32", launch_batched<MM32F, 64, 64, 16, 2, 2>, nullptr,
+       occupancy_of<MM32F, 64, 64, 16, 2, 2>, 64, 64},
+      {"batched_f32_64x64x16_mfma16", launch_batched<MM16F, 64, 64, 16, 2, 2>, nullptr,
+       occupancy_of<MM16F, 64, 64, 16, 2, 2>, 64, 64},
+      {"batched_sync_f32_32x32x16_mfma16", nullptr, launch_sync<MM16F, 32, 32, 16, 2, 2>,
+       occupancy_sync<MM16F, 32, 32, 16, 2, 2>, 32, 32},
+      {"batched_sync_f32_64x64x16_mfma32", nullptr, launch_sync<MM32F, 64, 64, 16, 2, 2>,
+       occupancy_sync<MM32F, 64, 64, 16, 2, 2>, 64, 64},
   };
   return t;
 }
 
 int batched_num_configs() { return (int)batched_table().size(); }
 const char* batched_config_name(int cfg) { return batched_table().at(cfg).name; }
+bool batched_is_sync(int cfg) { return batched_table().at(cfg).sfn != nullptr; }
+
+void batched_layout(std::vector<BDesc>& desc, int cfg, int64_t& pool, int64_t& part, int64_t& dwork) {
+  const auto& ent = batched_table().at(cfg);
+  auto up4 = [](int64_t x) { return (x + 3) / 4 * 4; };
+  pool = part = dwork = 0;
+  for (auto& d : desc) {
+    const int64_t s = std::min(d.m, d.n);
+    d.lds = up4(s);
+    d.pss = s * d.lds;
+    d.ldw = up4(d.m);
+    d.psw = (int64_t)d.n * d.ldw;
+    d.off = pool;
+    pool += 4 * (10 * d.pss + 5 * d.psw);
+    d.poff = part;
+    part += 4 * (int64_t)((d.n + ent.bm - 1) / ent.bm) * ((d.m + ent.bn - 1) / ent.bn);  // 2 products x 2
+    d.doff = dwork;
+    dwork += 8 * (int64_t)std::max(d.m, d.n) + 8;
+  }
+}
 
 __global__ void zero_int_kernel(int* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// timeout flag, barrier words and a status sentinel for every matrix (overwritten when it retires)
+__global__ void sync_reset_kernel(unsigned int* bar, BInfo* info, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 4) bar[i] = 0u;
+  for (int b = i; b < count; b += gridDim.x * blockDim.x) {
+    info[b].iters = 0;
+    info[b].returned = 0;
+    info[b].reason = 0;
+    info[b].status = -7;
+    info[b].alpha = 0.0;
+    info[b].dx_rel = 0.0;
+    info[b].sigma1_sq = 0.0;
+  }
 }
 
 BatchedState::~BatchedState() {
@@ -560,6 +1344,7 @@ BatchedState::~BatchedState() {
   if (h_info) (void)hipHostFree(h_info);
   if (h_order) (void)hipHostFree(h_order);
   if (h_alpha) (void)hipHostFree(h_alpha);
+  if (h_trace) (void)hipHostFree(h_trace);
   for (void* p : dev) (void)hipFree(p);
 }
 
@@ -571,6 +1356,74 @@ static void* dev_alloc(BatchedState& st, size_t bytes) {
   }
   st.dev.push_back(p);
   return p;
+}
+
+// (Re)build the device buffers and the captured graph of a phase-synchronous configuration.
+static void build_sync(BatchedState& st, const BKey& key, int64_t pool_cap, int64_t part_cap, int64_t dw_cap) {
+  st.~BatchedState();
+  new (&st) BatchedState();
+  st.key = key;
+  st.pool_cap = pool_cap;
+  st.part_cap = part_cap;
+  st.dw_cap = dw_cap;
+  const int count = key.count;
+  const auto& ent = batched_table().at(key.cfg);
+  int dev = 0, cus = 0;
+  QP_HIP(hipGetDevice(&dev));
+  QP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // every workgroup must be resident for the grid barrier: at most the occupancy per compute unit
+  st.grid = std::max(1, cus * std::min(ent.occ(), 2));
+  QP_HIP(hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking));
+  QP_HIP(hipEventCreateWithFlags(&st.ev0, hipEventDisableTiming));
+  QP_HIP(hipEventCreateWithFlags(&st.ev1, hipEventDisableTiming));
+  QP_HIP(hipHostMalloc(reinterpret_cast<void**>(&st.h_desc), sizeof(BDesc) * count, hipHostMallocDefault));
+  QP_HIP(hipHostMalloc(reinterpret_cast<void**>(&st.h_info), sizeof(BInfo) * count, hipHostMallocDefault));
+  QP_HIP(hipHostMalloc(reinterpret_cast<void**>(&st.h_order), sizeof(int) * 4, hipHostMallocDefault));
+  QP_HIP(hipHostMalloc(reinterpret_cast<void**>(&st.h_alpha), sizeof(double) * count, hipHostMallocDefault));
+  BDesc* d_desc = static_cast<BDesc*>(dev_alloc(st, sizeof(BDesc) * count));
+  BInfo* d_info = static_cast<BInfo*>(dev_alloc(st, sizeof(BInfo) * count));
+  LState* d_st = static_cast<LState*>(dev_alloc(st, sizeof(LState) * count));
+  unsigned int* d_bar = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * 4));
+  double* d_alpha = static_cast<double*>(dev_alloc(st, sizeof(double) * count));
+  float* pool = static_cast<float*>(dev_alloc(st, sizeof(float) * (size_t)pool_cap));
+  double* partial = static_cast<double*>(dev_alloc(st, sizeof(double) * (size_t)part_cap));
+  double* dwork = static_cast<double*>(dev_alloc(st, sizeof(double) * (size_t)dw_cap));
+  unsigned long long* trace = static_cast<unsigned long long*>(dev_alloc(st, sizeof(unsigned long long) * kTraceCap));
+  QP_HIP(hipHostMalloc(reinterpret_cast<void**>(&st.h_trace), sizeof(unsigned long long) * kTraceCap,
+                       hipHostMallocDefault));
+
+  SParams P;
+  P.desc = d_desc;
+  P.info = d_info;
+  P.st = d_st;
+  P.count = count;
+  P.pool = pool;
+  P.partial = partial;
+  P.dwork = dwork;
+  P.bar = d_bar;
+  P.alpha = d_alpha;
+  P.method = key.method;
+  P.stop = key.stop;
+  P.max_iter = key.max_iter;
+  P.tol = key.tol;
+  P.scaling = key.scaling;
+  P.power_steps = key.power_steps;
+  P.seed = key.seed;
+  P.k = make_coef();
+  P.trace = trace;
+  P.trace_cap = kTraceCap;
+
+  hipStream_t s = st.stream;
+  QP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  QP_HIP(hipMemcpyAsync(d_desc, st.h_desc, sizeof(BDesc) * count, hipMemcpyHostToDevice, s));
+  QP_HIP(hipMemcpyAsync(d_alpha, st.h_alpha, sizeof(double) * count, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(sync_reset_kernel, dim3((count + 255) / 256 + 1), dim3(256), 0, s, d_bar, d_info, count);
+  ent.sfn(P, st.grid, s);
+  QP_HIP(hipMemcpyAsync(st.h_info, d_info, sizeof(BInfo) * count, hipMemcpyDeviceToHost, s));
+  QP_HIP(hipMemcpyAsync(st.h_order, d_bar, sizeof(unsigned int) * 4, hipMemcpyDeviceToHost, s));
+  QP_HIP(hipMemcpyAsync(st.h_trace, trace, sizeof(unsigned long long) * kTraceCap, hipMemcpyDeviceToHost, s));
+  QP_HIP(hipStreamEndCapture(s, &st.graph));
+  QP_HIP(hipGraphInstantiate(&st.exec, st.graph, nullptr, nullptr, 0));
 }
 
 // (Re)build device buffers and the captured graph for a batch signature.
@@ -632,12 +1485,22 @@ static void build(BatchedState& st, const BKey& key, hipStream_t) {
   QP_HIP(hipGraphInstantiate(&st.exec, st.graph, nullptr, nullptr, 0));
 }
 
-void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& desc, const std::vector<int>& order,
-                 const std::vector<double>& alphas, std::vector<BInfo>& infos, hipStream_t caller) {
-  if (!st.exec || !(st.key == key)) build(st, key, caller);
+void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& desc_in, const std::vector<int>& order,
+                 const std::vector<double>& alphas, std::vector<BInfo>& infos, hipStream_t caller, bool verbose) {
   const int count = key.count;
+  const bool sync = batched_is_sync(key.cfg);
+  std::vector<BDesc> desc = desc_in;
+  if (sync) {
+    if (count > SYNC_MAX) throw Error(-1, "phase-synchronous batched solves take at most 2048 matrices");
+    int64_t pool = 0, part = 0, dw = 0;
+    batched_layout(desc, key.cfg, pool, part, dw);
+    if (!st.exec || !(st.key == key) || pool > st.pool_cap || part > st.part_cap || dw > st.dw_cap)
+      build_sync(st, key, pool + pool / 4 + 64, part + part / 4 + 64, dw + dw / 4 + 64);
+  } else if (!st.exec || !(st.key == key) || st.pool_cap != 0) {
+    build(st, key, caller);
+  }
   std::memcpy(st.h_desc, desc.data(), sizeof(BDesc) * count);
-  std::memcpy(st.h_order, order.data(), sizeof(int) * count);
+  if (!sync) std::memcpy(st.h_order, order.data(), sizeof(int) * count);
   for (int b = 0; b < count; ++b) st.h_alpha[b] = b < (int)alphas.size() ? alphas[b] : 0.0;
   // order the graph after the caller's stream, and the caller after the graph
   QP_HIP(hipEventRecord(st.ev0, caller));
@@ -647,6 +1510,23 @@ void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& de
   QP_HIP(hipStreamWaitEvent(caller, st.ev1, 0));
   QP_HIP(hipStreamSynchronize(st.stream));
   infos.assign(st.h_info, st.h_info + count);
+  if (sync && verbose) {
+    // phase durations from the barrier stamps (100 MHz wall clock): per update, the np product phases
+    // and the controller phase
+    const unsigned long long* t = st.h_trace;
+    const int np = key.method == 0 ? 2 : key.method == 2 ? 6 : 7;
+    fprintf(stderr, "[qpinv] batched set-up %.1f us\n", (double)(t[1] - t[0]) * 1e-2);
+    int k = 2;
+    while (k < kTraceCap && t[k] > t[k - 1] && t[k] - t[k - 1] < 100000000ull) {
+      if ((k - 2) % (np + 1) == 0) fprintf(stderr, "[qpinv] batched update %d:", (k - 2) / (np + 1) + 1);
+      fprintf(stderr, " %.1f", (double)(t[k] - t[k - 1]) * 1e-2);
+      if ((k - 2) % (np + 1) == np) fprintf(stderr, " us\n");
+      ++k;
+    }
+    fprintf(stderr, "\n");
+  }
+  if (sync && reinterpret_cast<const unsigned int*>(st.h_order)[2] != 0u)
+    throw Error(-7, "batched solve: a grid barrier wait expired (workgroups not co-resident?)");
 }
 
 }  // namespace qp

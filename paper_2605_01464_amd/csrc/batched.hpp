@@ -7,13 +7,17 @@
 
 namespace qp {
 
-// One matrix of a batch (device pointers, FP32 storage).  X_b is n x m.
+// One matrix of a batch (device pointers, FP32 storage).  X_b is n x m.  The phase-synchronous kernel
+// also reads the matrix's workspace offsets (elements into its float pool, double partial-sum array and
+// double vector scratch) and the row strides of its s x s and n x m work buffers.
 struct BDesc {
   const float* A;
   int64_t lda, psa;
   float* X;
   int64_t ldx, psx;
   int m, n;
+  int64_t off = 0, poff = 0, doff = 0;
+  int64_t lds = 0, pss = 0, ldw = 0, psw = 0;
 };
 
 // Per-matrix outcome written by the kernel.
@@ -45,14 +49,23 @@ struct BatchedState {
   BInfo* h_info = nullptr;
   int* h_order = nullptr;
   double* h_alpha = nullptr;
+  unsigned long long* h_trace = nullptr;
   int grid = 0;
   std::vector<void*> dev;
+  // phase-synchronous configurations: capacities the captured graph was built for
+  int64_t pool_cap = 0, part_cap = 0, dw_cap = 0;
   ~BatchedState();
 };
 
+// Phase-synchronous configurations keep every matrix's work buffers in one pool: fill the offsets and
+// strides of `desc` and return the pool, partial-sum and vector scratch sizes (elements).
+void batched_layout(std::vector<BDesc>& desc, int cfg, int64_t& pool, int64_t& part, int64_t& dwork);
+bool batched_is_sync(int cfg);
+
 // Upload the batch, replay (or build) the graph and wait for it; infos receives the outcomes.
 void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& desc, const std::vector<int>& order,
-                 const std::vector<double>& alphas, std::vector<BInfo>& infos, hipStream_t caller);
+                 const std::vector<double>& alphas, std::vector<BInfo>& infos, hipStream_t caller,
+                 bool verbose = false);
 
 int batched_num_configs();
 const char* batched_config_name(int cfg);

@@ -4,6 +4,7 @@
 
 #include "../../include/qpinv.h"
 #include "aux.hpp"
+#include "batched.hpp"
 #include "controller.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
@@ -84,6 +85,9 @@ void set_option(qp::Ctx& c, const std::string& key, double v) {
     const qp::Prec p = key == "gemm_cfg_f64" ? qp::P_F64 : key == "gemm_cfg_f32" ? qp::P_F32 : qp::P_BF16;
     need(v == -1 || (v >= 0 && v < (double)qp::tile_configs(p).size() && v == (int)v));
     c.opt.force_cfg[(int)p] = (int)v;
+  } else if (key == "batched_cfg") {
+    need(v == -1 || (v >= 0 && v < (double)qp::batched_num_configs() && v == (int)v));
+    c.opt.batched_cfg = (int)v;
   } else if (key == "verbose") {
     c.opt.verbose = v != 0;
   } else {
@@ -402,6 +406,13 @@ const char* qpinv_tile_config_name(int gemm_prec, int cfg) {
   const auto& t = qp::tile_configs((qp::Prec)gemm_prec);
   if (cfg < 0 || cfg >= (int)t.size()) return "";
   return t[cfg].name;
+}
+
+int qpinv_num_batched_configs(void) { return qp::batched_num_configs(); }
+
+const char* qpinv_batched_config_name(int cfg) {
+  if (cfg < 0 || cfg >= qp::batched_num_configs()) return "";
+  return qp::batched_config_name(cfg);
 }
 
 int qpinv_gemm_stats(qpinv_ctx* c, double* out, int max_rows) {

@@ -27,10 +27,11 @@ struct StopController {
   double best_d = __builtin_huge_val();
   int best_j = -1;
 
+  QP_HD StopController() : rule(STOP_GUARDED), tol(0.0) {}
   QP_HD StopController(int r, double t) : rule(r), tol(t) {}
 
   // j = index of the new iterate X_j (1-based update count).
-  QP_HD int update(int j, double d_abs, double x_norm, double e1_rel) {
+  QP_HD __attribute__((always_inline)) int update(int j, double d_abs, double x_norm, double e1_rel) {
     if (!__builtin_isfinite(d_abs) || !__builtin_isfinite(x_norm)) return D_DIVERGED;
     switch (rule) {
       case STOP_DX_ABS:

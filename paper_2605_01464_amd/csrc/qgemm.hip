@@ -31,7 +31,7 @@ namespace qp {
 template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, bool ALIGNED, bool WALK, int MINW>
 __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_kernel(GemmParams<typename MM::T> P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
-  __shared__ typename MM::T smem[DB ? 2 * C::SMEM : C::SMEM];
+  __shared__ __attribute__((aligned(16))) typename MM::T smem[DB ? 2 * C::SMEM : C::SMEM];
   __shared__ double red_lds[C::NW][2];
   const int nt = P.tiles_m * P.tiles_n;
   double s_d = 0.0, s_x = 0.0;

@@ -183,7 +183,17 @@ __device__ __forceinline__ void bf16_tile(const GemmParams<float>& P, int tm, in
         for (int r = 0; r < 4; ++r) slab[(((lane >> 4) << 2) + r) * 16 + (lane & 15)] = acc[p][i][j][r];
         __syncthreads();
         const int rb0 = m0 + wm * C::WTM + i * 16, cb0 = n0 + wn * C::WTN + j * 16;
-        for (int e = lane; e < 256; e += 64) epilogue_plane(P, p, rb0 + e / 16, cb0 + e % 16, slab[e], s_d, s_x);
+        float inv[4][3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int e = lane + 64 * k;
+          epilogue_inputs(P, p, rb0 + e / 16, cb0 + e % 16, inv[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int e = lane + 64 * k;
+          epilogue_apply(P, p, rb0 + e / 16, cb0 + e % 16, slab[e], inv[k], s_d, s_x);
+        }
       }
   __syncthreads();  // LDS is reused by the workgroup's next tile
 }

@@ -116,14 +116,20 @@ __device__ __forceinline__ void tile_of_block(int bid, int nb, int tiles_m, int 
 }
 
 
-// out_t = a_t v + sum_u b_tu in_u + g_t I for plane p at one element, plus the reduction terms.
+// The epilogue inputs in_u of plane p at one element (0 outside the output or beyond nin).
 template <class T>
-__device__ __forceinline__ void epilogue_plane(const GemmParams<T>& P, int p, int row, int col, T v, double& s_d,
-                                               double& s_x) {
-  if (row >= P.M || col >= P.N) return;
-  T inv[3];
+__device__ __forceinline__ void epilogue_inputs(const GemmParams<T>& P, int p, int row, int col, T (&inv)[3]) {
+  const bool ok = row < P.M && col < P.N;
 #pragma unroll
-  for (int u = 0; u < 3; ++u) inv[u] = (u < P.nin) ? P.in[u][p * P.psi[u] + (int64_t)row * P.ldi[u] + col] : T(0);
+  for (int u = 0; u < 3; ++u) inv[u] = (ok && u < P.nin) ? P.in[u][p * P.psi[u] + (int64_t)row * P.ldi[u] + col] : T(0);
+}
+
+// out_t = a_t v + sum_u b_tu in_u + g_t I for plane p at one element, plus the reduction terms; inv
+// holds the element's inputs (epilogue_inputs).
+template <class T>
+__device__ __forceinline__ void epilogue_apply(const GemmParams<T>& P, int p, int row, int col, T v, const T (&inv)[3],
+                                               double& s_d, double& s_x) {
+  if (row >= P.M || col >= P.N) return;
   const T eye = (p == 0 && row == col) ? T(1) : T(0);
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
@@ -439,8 +445,22 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
         }
         __syncthreads();
         const int rb = m0 + wm * C::WTM + i * MM::BLK, cb = n0 + wn * C::WTN + j * MM::BLK;
-        for (int e = lane; e < MM::BLK * MM::BLK; e += 64)
-          epilogue_plane(P, p, rb + e / MM::BLK, cb + e % MM::BLK, slab[e], s_d, s_x);
+        // the input loads of 4 of this lane's elements at a time first (one memory latency per group),
+        // then their outputs
+        constexpr int NE = MM::BLK * MM::BLK / 64, NG = NE < 4 ? NE : 4;
+        for (int k0 = 0; k0 < NE; k0 += NG) {
+          T inv[NG][3];
+#pragma unroll
+          for (int k = 0; k < NG; ++k) {
+            const int e = lane + 64 * (k0 + k);
+            epilogue_inputs(P, p, rb + e / MM::BLK, cb + e % MM::BLK, inv[k]);
+          }
+#pragma unroll
+          for (int k = 0; k < NG; ++k) {
+            const int e = lane + 64 * (k0 + k);
+            epilogue_apply(P, p, rb + e / MM::BLK, cb + e % MM::BLK, slab[e], inv[k], s_d, s_x);
+          }
+        }
       }
   __syncthreads();  // the LDS slabs / tiles are reused by whatever runs next in this workgroup
 }

@@ -1099,13 +1099,18 @@ int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A,
     sig.push_back(A[b].rows);
     sig.push_back(A[b].cols);
   }
+  auto usable = [&](int cfg) { return !batched_is_sync(cfg) || batch <= 2048; };
   auto it = c.batched_tuned.find(sig);
-  if (it != c.batched_tuned.end()) {
+  if (c.opt.batched_cfg >= 0) {
+    if (!usable(c.opt.batched_cfg)) throw Error(QPINV_EINVAL, "batched configuration takes at most 2048 matrices");
+    key.cfg = c.opt.batched_cfg;
+  } else if (it != c.batched_tuned.end()) {
     key.cfg = it->second;
   } else if (c.opt.autotune) {
     double best = 1e300;
     int best_cfg = 0;
     for (int cfg = 0; cfg < batched_num_configs(); ++cfg) {
+      if (!usable(cfg)) continue;
       key.cfg = cfg;
       run_batched(*c.batched, key, desc, order_v, alphas, out, s);  // builds the graph (and warms up)
       const double t1 = now_s();
@@ -1122,7 +1127,7 @@ int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A,
   } else {
     key.cfg = 0;
   }
-  run_batched(*c.batched, key, desc, order_v, alphas, out, s);
+  run_batched(*c.batched, key, desc, order_v, alphas, out, s, c.opt.verbose != 0);
   const double secs = now_s() - t0;
   int status = QPINV_OK;
   for (int b = 0; b < batch; ++b) {

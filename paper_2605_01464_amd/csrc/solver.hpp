@@ -36,6 +36,7 @@ struct Options {
   int verbose = 0;
   int gemm_timing = 0;
   int force_cfg[3] = {-1, -1, -1};  // per product precision: tile configuration for every product, -1 = choose
+  int batched_cfg = -1;             // batched kernel configuration, -1 = tuned or default
 };
 
 struct MlpState;      // scaling network (mlp.hip)

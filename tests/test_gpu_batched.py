@@ -9,6 +9,21 @@ from oracle import methods as M
 
 pytestmark = pytest.mark.gpu
 
+# kernel forms: the queue kernel (one workgroup per matrix) and the phase-synchronous kernel (all
+# workgroups per product), with the same 32 x 32 tile routine
+FORMS = {"queue": 0, "sync": 3}
+
+
+@pytest.fixture(autouse=True, params=sorted(FORMS))
+def batched_form(request, qctx):
+    import paper_2605_01464_amd as q
+
+    cfg = FORMS[request.param]
+    assert q.qpinv_batched_config_name(cfg).startswith("batched_sync" if request.param == "sync" else "batched_f32")
+    qctx.set("batched_cfg", cfg)
+    yield request.param
+    qctx.set("batched_cfg", -1)
+
 
 @pytest.fixture(scope="module")
 def small_batch():
@@ -113,3 +128,22 @@ def test_batched_full_workload_sampled(qctx):
     assert all(inf["status"] == q.OK for inf in infos)
     errs = [rel_fro(to_np(Xs[b]), Q.pinv_svd(A)) for b, A in mats.items()]
     assert max(errs) <= 1e-4, (max(errs), float(np.median(errs)))
+
+
+def test_sync_equals_queue_bitwise(qctx, small_batch, batched_form):
+    """Both kernel forms run the same tile routine on the same operands: at a fixed number of updates the
+    iterates agree bit for bit."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    if batched_form != "sync":
+        pytest.skip("compares the two forms once")
+    As = [to_dev(A, "f32") for A in small_batch]
+    alphas = [M.alpha_sigma(A) for A in small_batch]
+    kw = dict(scaling="given", alphas=alphas, tol=0.0, max_iter=4, stop="dx_rel", check=False)
+    Xs_sync, _ = q.solve_batched(qctx, As, "qhpi19", **kw)
+    qctx.set("batched_cfg", FORMS["queue"])
+    Xs_queue, _ = q.solve_batched(qctx, As, "qhpi19", **kw)
+    for a, b in zip(Xs_sync, Xs_queue):
+        assert torch.equal(a, b)
