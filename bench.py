@@ -214,8 +214,9 @@ def main() -> int:
         # the same 2048 x 1536 workload with the other methods (FP32, guarded stop), and the factorized
         # order-19 update against the plain hyperpower polynomial of order 19 at equal update counts
         res = {}
+        Xm = torch.empty_like(X)  # the headline solve's result in X stays untouched
         for meth in ("ns", "qsai", "qrapid", "qhpi19"):
-            kw = dict(method=meth, scaling="power", tol=1e-6, max_iter=200, stop="guarded", precision="f32", X=X)
+            kw = dict(method=meth, scaling="power", tol=1e-6, max_iter=200, stop="guarded", precision="f32", X=Xm)
             q.solve(ctx, A, **kw)
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -227,7 +228,7 @@ def main() -> int:
         fixed = {}
         for key_, meth, order_ in (("qhpi19", "qhpi19", 19), ("hpi19", "hpi", 19)):
             kw = dict(method=meth, order=order_, scaling="power", tol=0.0, max_iter=4, stop="dx_abs",
-                      precision="f32", X=X, check=False)
+                      precision="f32", X=Xm, check=False)
             q.solve(ctx, A, **kw)
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -299,15 +300,28 @@ def main() -> int:
         As4 = [torch.from_numpy(qsynth.c4_instance(b, sizes).astype(np.float32)).cuda() for b in range(len(sizes))]
         t_g = time.time() - t_g
         Xs4 = [torch.empty((4, a.shape[2], a.shape[1]), dtype=torch.float32, device="cuda") for a in As4]
-        q.solve_batched(ctx, As4, "qhpi19", tol=1e-6, stop="guarded", Xs=Xs4)  # tile tuning + graph build
-        torch.cuda.synchronize()
         reps = 3
+        per_cfg = {}
+        for cfg in range(q.qpinv_num_batched_configs()):  # every kernel form and tile shape
+            ctx.set("batched_cfg", cfg)
+            q.solve_batched(ctx, As4, "qhpi19", tol=1e-6, stop="guarded", Xs=Xs4)  # graph build
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                q.solve_batched(ctx, As4, "qhpi19", tol=1e-6, stop="guarded", Xs=Xs4)
+            torch.cuda.synchronize()
+            per_cfg[q.qpinv_batched_config_name(cfg)] = len(As4) * reps / (time.perf_counter() - t)
+        ctx.set("batched_cfg", -1)
+        q.solve_batched(ctx, As4, "qhpi19", tol=1e-6, stop="guarded", Xs=Xs4)  # autotuned choice + graph build
+        torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(reps):
             _, inf4 = q.solve_batched(ctx, As4, "qhpi19", tol=1e-6, stop="guarded", Xs=Xs4)
         torch.cuda.synchronize()
         t_batch = (time.perf_counter() - t) / reps
-        for a, x in zip(As4[:8], Xs4[:8]):  # warm the single path's shapes a little
+        # the loop uses the heuristic tile choice (tuning each of the 512 shapes would be timed otherwise)
+        ctx.set("autotune", 0)
+        for a, x in zip(As4[:8], Xs4[:8]):  # warm-up
             q.solve(ctx, a, "qhpi19", tol=1e-6, stop="guarded", precision="f32", X=x)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -315,6 +329,7 @@ def main() -> int:
             q.solve(ctx, a, "qhpi19", tol=1e-6, stop="guarded", precision="f32", X=x)
         torch.cuda.synchronize()
         t_loop = time.perf_counter() - t
+        ctx.set("autotune", 0 if args.no_autotune else 1)
         its = [i["iters"] for i in inf4]
         s_ = [min(a.shape[1], a.shape[2]) for a in As4]
         o_ = [max(a.shape[1], a.shape[2]) for a in As4]
@@ -324,7 +339,8 @@ def main() -> int:
                           "persistent_solves_per_s": len(As4) / t_batch, "batch_ms": 1e3 * t_batch,
                           "loop_single_solves_per_s": len(As4) / t_loop, "loop_ms": 1e3 * t_loop,
                           "speedup_vs_loop": t_loop / t_batch, "iters_median": float(np.median(its)),
-                          "gemm_tflops_effective": flops / t_batch / 1e12, "input_generation_s": t_g}
+                          "gemm_tflops_effective": flops / t_batch / 1e12, "input_generation_s": t_g,
+                          "solves_per_s_by_config": per_cfg}
 
     if not args.no_learned:
         # learned initial scaling (network trained on the GPU by this library on 20k matrices 64..512):

@@ -114,6 +114,47 @@ void zero_doubles(double* p, int64_t count, hipStream_t s) {
   QP_HIP(hipGetLastError());
 }
 
+__global__ void __launch_bounds__(256) add_delta_kernel(const double* __restrict__ Xc, int64_t ldc, int64_t psc,
+                                                        const float* __restrict__ D, int64_t ldd, int64_t psd,
+                                                        double* __restrict__ Xn, int64_t ldn, int64_t psn, int rows,
+                                                        int cols, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int64_t total = (int64_t)rows * cols;
+  double sd = 0.0, sx = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / cols, j = e - i * cols;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const double xc = Xc[p * psc + i * ldc + j];
+      const double xn = xc + (double)D[p * psd + i * ldd + j];
+      Xn[p * psn + i * ldn + j] = xn;
+      const double dd = xn - xc;
+      sd += dd * dd;
+      sx += xn * xn;
+    }
+  }
+  const double a = block_sum256(sd, sh);
+  const double b = block_sum256(sx, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
+int64_t add_delta_blocks(int64_t rows, int64_t cols) {
+  return std::max<int64_t>(1, std::min<int64_t>((rows * cols + 255) / 256, 1024));
+}
+
+void add_delta(const QView& Xc, const QView& D, const QView& Xn, int64_t rows, int64_t cols, double* out,
+               double* work, hipStream_t s) {
+  const int64_t nb = add_delta_blocks(rows, cols);
+  hipLaunchKernelGGL(add_delta_kernel, dim3((unsigned)nb), dim3(256), 0, s, static_cast<const double*>(Xc.p), Xc.ld,
+                     Xc.ps, static_cast<const float*>(D.p), D.ld, D.ps, static_cast<double*>(Xn.p), Xn.ld, Xn.ps,
+                     (int)rows, (int)cols, work);
+  QP_HIP(hipGetLastError());
+  reduce_pairs(work, nb, out, s);
+}
+
 // Values in [-1, 1) from a multiplicative hash of the index (timing inputs: MFMA power and thus clocks
 // depend on the operand bits, so tiles are timed on dense data rather than zeros).
 template <class T>

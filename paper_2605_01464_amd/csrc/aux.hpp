@@ -36,6 +36,13 @@ template <class T>
 void herm_diff(const QView& M, int64_t n, double* out, double* work, hipStream_t s);
 int64_t hermdiff_blocks(int64_t n);
 
+// Xn = Xc + D (FP64 iterates, FP32 correction D), rows x cols, and the change norms
+// out[0] = sum |Xn - Xc|^2, out[1] = sum |Xn|^2 (device doubles, fixed summation order).
+// `work` must hold 2 * add_delta_blocks(rows, cols) doubles.
+void add_delta(const QView& Xc, const QView& D, const QView& Xn, int64_t rows, int64_t cols, double* out,
+               double* work, hipStream_t s);
+int64_t add_delta_blocks(int64_t rows, int64_t cols);
+
 // Write `count` zeros to device doubles (a kernel, so it is safe inside captured graphs).
 void zero_doubles(double* p, int64_t count, hipStream_t s);
 template <class T>

@@ -557,6 +557,151 @@ void convert_mat(const Mat& src, const Mat& dst, hipStream_t s) {
     convert<double, double>(src.v, dst.v, src.rows, src.cols, s);
 }
 
+// One update of the FP64 finish evaluated in mixed precision (NS, HPI, QSAI, QHPI19: X+ = T(R) X with
+// T = I + T'): the residual R = I - X A (left) or I - A X (right) is an FP64 product of the FP64
+// iterate, and X+ = X + T' X is summed in FP64; T' (a polynomial in R without the identity term) and
+// the correction T' X are FP32 products.  Near convergence R and T' are small, so the FP32 rounding of
+// the correction is relative to |T' X|, far below |X| u_64-level effects of the FP64 residual.
+void chain_refined(Ctx& c, int method, int order, int side, const Mat& A64, const Mat& Xc, const Mat& Xn,
+                   double* red, hipStream_t s) {
+  const int64_t m = A64.rows, n = A64.cols;
+  const bool left = side == QPINV_SIDE_LEFT;
+  const int64_t sd = left ? n : m;
+  auto sq = [&](int k) { return ws_mat(c, "rf" + std::to_string(k), sd, sd, QPINV_F32); };
+  Mat R64 = ws_mat(c, "rfR64", sd, sd, QPINV_F64), S64 = ws_mat(c, "rfS64", sd, sd, QPINV_F64);
+  {  // R = I - prod and (for HPI) S = I + R = 2I - prod, in FP64
+    Epilogue e = epi1(R64, -1.0, 1.0);
+    if (method == QPINV_HPI) {
+      e.nout = 2;
+      e.out[1] = S64.v;
+      e.a[1] = -1.0;
+      e.g[1] = 2.0;
+    }
+    if (left)
+      gemm(c, P_F64, Xc, A64, e, s);
+    else
+      gemm(c, P_F64, A64, Xc, e, s);
+  }
+  Mat R = sq(0);
+  convert_mat(R64, R, s);
+  Mat X32 = ws_mat(c, "rfX", n, m, QPINV_F32);
+  convert_mat(Xc, X32, s);
+  Mat Tp;  // T - I
+  switch (method) {
+    case QPINV_NS:  // T = I + R
+      Tp = R;
+      break;
+    case QPINV_HPI: {  // S = I + R; S <- I + R S (p - 3 times); T - I = R S
+      Mat cur = sq(1), nxt = sq(2);
+      convert_mat(S64, cur, s);
+      if (order == 2) {
+        Tp = R;
+        break;
+      }
+      for (int k = 0; k < order - 3; ++k) {
+        gemm(c, P_F32, R, cur, epi1(nxt, 1.0, 1.0), s);
+        std::swap(cur, nxt);
+      }
+      Tp = nxt;
+      gemm(c, P_F32, R, cur, epi1(Tp), s);
+      break;
+    }
+    case QPINV_QSAI: {
+      // P1 = I + a, P2 = I + b with a = b1 R^2 + R^4, b = b2 R^2 + R^4; Q = P1 P2 = I + Q',
+      // Q' = a b + a + b; T = (I + R) Q, T - I = R Q' + R + Q'
+      Mat R2 = sq(1), Pa = sq(2), Pb = sq(3), Qp = sq(4);
+      Tp = sq(5);
+      gemm(c, P_F32, R, R, epi1(R2), s);
+      Epilogue e4;
+      e4.nout = 2;
+      e4.out[0] = Pa.v;
+      e4.out[1] = Pb.v;
+      e4.a[0] = e4.a[1] = 1.0;
+      e4.nin = 1;
+      e4.in[0] = R2.v;
+      e4.b[0][0] = kBeta1;
+      e4.b[1][0] = kBeta2;
+      gemm(c, P_F32, R2, R2, e4, s);
+      Epilogue eq = epi1(Qp);
+      eq.nin = 2;
+      eq.in[0] = Pa.v;
+      eq.in[1] = Pb.v;
+      eq.b[0][0] = 1.0;
+      eq.b[0][1] = 1.0;
+      gemm(c, P_F32, Pa, Pb, eq, s);
+      Epilogue et = epi1(Tp);
+      et.nin = 2;
+      et.in[0] = R.v;
+      et.in[1] = Qp.v;
+      et.b[0][0] = 1.0;
+      et.b[0][1] = 1.0;
+      gemm(c, P_F32, R, Qp, et, s);
+      break;
+    }
+    default: {  // QHPI19: the chain of Algorithm 3 from R; T - I = (R + R^2) Gamma
+      Mat R2 = sq(1), R4 = sq(2), Sm = sq(3), P1 = sq(4), P2 = sq(5), V = sq(6), W = sq(7);
+      {
+        Epilogue e = epi1(R2);
+        e.nout = 2;
+        e.out[1] = Sm.v;
+        e.a[1] = 1.0;
+        e.nin = 1;
+        e.in[0] = R.v;
+        e.b[1][0] = 1.0;
+        gemm(c, P_F32, R, R, e, s);
+      }
+      {
+        Epilogue e = epi1(R4);
+        e.nout = 3;
+        e.out[1] = P1.v;
+        e.out[2] = P2.v;
+        e.a[1] = e.a[2] = 1.0;
+        e.nin = 1;
+        e.in[0] = R2.v;
+        e.b[1][0] = kD1;
+        e.b[2][0] = kD2;
+        e.g[1] = e.g[2] = 1.0;
+        gemm(c, P_F32, R2, R2, e, s);
+      }
+      {
+        Epilogue e;
+        e.nout = 2;
+        e.out[0] = V.v;
+        e.out[1] = W.v;
+        e.a[0] = e.a[1] = 1.0;
+        e.nin = 2;
+        e.in[0] = R2.v;
+        e.in[1] = R4.v;
+        e.b[0][0] = kD3;
+        e.b[1][0] = kE1;
+        e.b[1][1] = kE2;
+        gemm(c, P_F32, P1, P2, e, s);
+      }
+      Mat G = P1;
+      {
+        Epilogue e = epi1(G);
+        e.nin = 2;
+        e.in[0] = R2.v;
+        e.in[1] = R4.v;
+        e.b[0][0] = kC1;
+        e.b[0][1] = kC2;
+        gemm(c, P_F32, V, W, e, s);
+      }
+      Tp = P2;
+      gemm(c, P_F32, Sm, G, epi1(Tp), s);
+      break;
+    }
+  }
+  Mat D = ws_mat(c, "rfD", n, m, QPINV_F32);
+  if (left)
+    gemm(c, P_F32, Tp, X32, epi1(D), s);
+  else
+    gemm(c, P_F32, X32, Tp, epi1(D), s);
+  if (add_delta_blocks(n, m) * 2 > c.scratch.capacity) throw Error(QPINV_EINVAL, "refined finish: scratch too small");
+  add_delta(Xc.v, D.v, Xn.v, n, m, red, c.scratch.partial, s);
+}
+
+
 void x0_into(const Mat& A, double alpha, const Mat& X, hipStream_t s) {
   if (A.dtype == QPINV_F32 && X.dtype == QPINV_F32)
     x0_scaled_adjoint<float, float>(A.v, A.rows, A.cols, alpha, X.v, s);
@@ -826,7 +971,11 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     // the classical alpha (mu = 1) carries no more risk than the default; only a larger learned mu is checked
     const bool guard_R = learned && j == 0 && inf.mu_used > 1.0;
     const bool want_R = (p == P_BF16) || keep_R || guard_R;
-    chain(c, method, order, side, p, Adt, S->b[cur], S->b[nxt], red, s, want_R ? &R : nullptr);
+    const bool refined = has_finish && ph == phases.size() - 1 && c.opt.f64_refined && method != QPINV_QRAPID;
+    if (refined)
+      chain_refined(c, method, order, side, Adt, S->b[cur], S->b[nxt], red, s);
+    else
+      chain(c, method, order, side, p, Adt, S->b[cur], S->b[nxt], red, s, want_R ? &R : nullptr);
     if (guard_R) {
       // Theorem 1: alpha is admissible iff every |1 - alpha sigma_i^2| < 1; R_0 = I - X_0 A (or I - A X_0)
       // has exactly these eigenvalues (and 1 on the null space), so ||R_0||_2 > 1 means divergence

@@ -32,6 +32,28 @@ def test_ladder_reaches_1e6_vs_oracle(qctx, sq512, method, order, precision):
     assert info["iters_f32"] >= 1
 
 
+@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("qsai", 10), ("ns", 2), ("hpi", 5)])
+@pytest.mark.parametrize("refined", [1, 0])
+def test_f64_finish_forms_vs_oracle(qctx, sq512, method, order, refined):
+    """The FP64 finish with every product in FP64 (refined = 0) and with FP64 residual and update sum
+    around FP32 polynomial products (refined = 1) both reach the FP64 pseudoinverse to 1e-10."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    A = sq512["A"]
+    ref = Q.pinv_svd(A)
+    qctx.set("f64_refined", refined)
+    try:
+        X, info = q.solve(qctx, to_dev(A, "f32"), method, order, scaling="power", tol=1e-6, stop="guarded",
+                          precision="f32_f64finish", out_dtype=torch.float64, max_iter=200)
+    finally:
+        qctx.set("f64_refined", 1)
+    err = rel_fro(to_np(X), ref)
+    assert err <= 1e-10, (method, refined, err, info)
+    assert 1 <= info["iters_f64"] <= 2
+
+
 def test_plain_f32_floor_vs_oracle(qctx, sq512):
     """Plain FP32 stops at its rounding floor (about kappa * u32 * growth), above 1e-6."""
     import paper_2605_01464_amd as q
