@@ -135,9 +135,11 @@ typedef struct qpinv_ctx qpinv_ctx;
 int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
 
 /* Set a numeric option: side (qpinv_side), power_steps (>= 1), power_seed, autotune (0/1),
- * f64_finish_iters (1..4), f64_refined (0/1, default 1: FP64 finish updates of NS, HPI, QSAI and
- * QHPI19 form the residual R and the sum X + (T - I) X in FP64 and the polynomial T - I of R and its
- * product with X in FP32; 0: every finish product in FP64), mixed_switch (||R||_2 threshold, default 1e-2), mixed_rnorm_steps,
+ * f64_finish_iters (1..4), f64_refined (0/1, default 0 = every finish product in FP64; 1: FP64
+ * finish updates of NS, HPI, QSAI and QHPI19 form the residual R and the sum X + (T - I) X in FP64
+ * and the polynomial T - I of R and its product with X in FP32 -- faster, but the correction then
+ * carries FP32 rounding relative to |(T - I) X|, about u32 |R_f32 floor| |X|), mixed_switch (||R||_2
+ * threshold, default 1e-2), mixed_rnorm_steps,
  * max_bf16_iters, gemm_timing (0/1), gemm_cfg_f64 / gemm_cfg_f32 / gemm_cfg_bf16 (tile configuration
  * index used for every product of that precision, -1 = tuned or heuristic choice), batched_cfg
  * (configuration of qpinv_solve_batched, -1 = tuned or default), verbose (0/1).

@@ -33,25 +33,30 @@ def test_ladder_reaches_1e6_vs_oracle(qctx, sq512, method, order, precision):
 
 
 @pytest.mark.parametrize("method,order", [("qhpi19", 19), ("qsai", 10), ("ns", 2), ("hpi", 5)])
-@pytest.mark.parametrize("refined", [1, 0])
-def test_f64_finish_forms_vs_oracle(qctx, sq512, method, order, refined):
-    """The FP64 finish with every product in FP64 (refined = 0) and with FP64 residual and update sum
-    around FP32 polynomial products (refined = 1) both reach the FP64 pseudoinverse to 1e-10."""
+def test_f64_finish_forms_vs_oracle(qctx, sq512, method, order):
+    """The FP64 finish with every product in FP64 (f64_refined = 0) and with FP64 residual and update
+    sum around FP32 polynomial products (f64_refined = 1): the same updates, both past the 1e-6 target,
+    and the mixed form no less accurate than the all-FP64 one (within 2x or 1e-10)."""
     import torch
 
     import paper_2605_01464_amd as q
 
     A = sq512["A"]
     ref = Q.pinv_svd(A)
-    qctx.set("f64_refined", refined)
+    out = {}
     try:
-        X, info = q.solve(qctx, to_dev(A, "f32"), method, order, scaling="power", tol=1e-6, stop="guarded",
-                          precision="f32_f64finish", out_dtype=torch.float64, max_iter=200)
+        for refined in (0, 1):
+            qctx.set("f64_refined", refined)
+            X, info = q.solve(qctx, to_dev(A, "f32"), method, order, scaling="power", tol=1e-6, stop="guarded",
+                              precision="f32_f64finish", out_dtype=torch.float64, max_iter=200)
+            out[refined] = (rel_fro(to_np(X), ref), info)
     finally:
-        qctx.set("f64_refined", 1)
-    err = rel_fro(to_np(X), ref)
-    assert err <= 1e-10, (method, refined, err, info)
-    assert 1 <= info["iters_f64"] <= 2
+        qctx.set("f64_refined", 0)
+    (e0, i0), (e1, i1) = out[0], out[1]
+    assert (i0["iters_f32"], i0["iters_f64"]) == (i1["iters_f32"], i1["iters_f64"]), (i0, i1)
+    assert 1 <= i1["iters_f64"] <= 2
+    assert e0 <= 1e-6 and e1 <= 1e-6, (e0, e1)
+    assert e1 <= max(2.0 * e0, 1e-10), (method, e0, e1)
 
 
 def test_plain_f32_floor_vs_oracle(qctx, sq512):
