@@ -613,8 +613,8 @@ struct SParams {
   int trace_cap;
 };
 
-constexpr int SYNC_MAX = 2048;
-constexpr int kTraceCap = 4096;  // barrier time stamps kept per launch      // matrices per launch (the per-phase tile prefix lives in LDS)
+constexpr int SYNC_MAX = 2048;   // matrices per launch (the per-phase tile prefix lives in LDS)
+constexpr int kTraceCap = 4096;  // time stamps kept per launch: barriers from 0, per-matrix set-up from the middle
 constexpr long long SPIN_MAX = 1ll << 22;  // barrier polls before the wait is abandoned
 
 // Grid barrier; returns false once any workgroup has abandoned a wait.
@@ -944,8 +944,10 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P
     info.sigma1_sq = 0.0;
     double normA = 0.0, alpha = 0.0;
     const int Dv = d.m > d.n ? d.m : d.n;
+    const unsigned long long t_set = wall_clock64();
     const bool ok = setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, B.xw(0),
                                  P.dwork + d.doff, Dv, sh, smem, info, normA, alpha);
+    if (P.trace && tid == 0 && kTraceCap / 2 + b < kTraceCap) P.trace[kTraceCap / 2 + b] = wall_clock64() - t_set;
     if (tid == 0) {
       LState S;
       S.active = ok ? 1 : 0;
@@ -1516,6 +1518,20 @@ void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& de
     const unsigned long long* t = st.h_trace;
     const int np = key.method == 0 ? 2 : key.method == 2 ? 6 : 7;
     fprintf(stderr, "[qpinv] batched set-up %.1f us\n", (double)(t[1] - t[0]) * 1e-2);
+    {  // per-matrix set-up durations (stamped by the workgroup that did it)
+      double mx = 0.0, sum = 0.0;
+      int arg = 0;
+      for (int b = 0; b < count && kTraceCap / 2 + b < kTraceCap; ++b) {
+        const double v = (double)t[kTraceCap / 2 + b] * 1e-2;
+        sum += v;
+        if (v > mx) {
+          mx = v;
+          arg = b;
+        }
+      }
+      fprintf(stderr, "[qpinv] batched per-matrix set-up: mean %.1f us, max %.1f us (matrix %d, %d x %d)\n",
+              sum / std::max(count, 1), mx, arg, desc[arg].m, desc[arg].n);
+    }
     int k = 2;
     while (k < kTraceCap && t[k] > t[k - 1] && t[k] - t[k - 1] < 100000000ull) {
       if ((k - 2) % (np + 1) == 0) fprintf(stderr, "[qpinv] batched update %d:", (k - 2) / (np + 1) + 1);
