@@ -12,7 +12,9 @@
  *   - A quaternion matrix A = A_s + A_x i + A_y j + A_z k (Section 2) is described by qpinv_qmat:
  *     four real planes in ONE device allocation, plane p (p = 0..3 for s, x, y, z) starting at
  *     data + p * plane_stride elements, each plane row-major with row stride `ld` elements.
- *     Requirements: rows >= 0, cols >= 0, ld >= cols, plane_stride >= rows * ld.
+ *     Requirements: rows >= 0, cols >= 0, ld >= cols, plane_stride >= rows * ld.  The whole
+ *     rows x ld extent of every plane must be readable: kernels may load a row up to ld (16-byte
+ *     loads from a clamped chunk) and discard the elements beyond cols, whatever they hold.
  *   - All matrix pointers are DEVICE pointers owned by the caller; the library never frees or
  *     retains them beyond the call.  The library owns its workspace (grown on demand, freed by
  *     qpinv_finalize).

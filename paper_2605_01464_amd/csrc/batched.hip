@@ -163,23 +163,169 @@ __device__ __attribute__((noinline)) void wg_gemm(const DM& A, const DM& B, cons
   __syncthreads();
 }
 
+// Loads issued together per lane in the power iteration's row pass (fixed count, addresses clamped
+// into A): a chunk of kSetupRows rows x 64 kSetupGroups columns then costs one memory latency.
+constexpr int kSetupGroups = 2;
+constexpr int kSetupRows = 4;
+
+// sum over the 64 lanes of a wave, fixed order (every lane gets the total)
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Power iteration on A^H A with v (4 n doubles) and w (4 m doubles) in LDS, so that every load in
+// flight is one of A's.  w = A v / ||v||: a wave takes kSetupRows rows at a time, lanes along them.
+// v = A^H w: a wave takes 64 columns, lanes along them, and runs down all rows 8 at a time (no
+// reduction across waves).  Returns ||w||^2 of the last step.
+__device__ __forceinline__ double power_lds(const DM& A, int steps, unsigned long long seed, double* vs, double* ws,
+                                            double* sh) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  const int m = A.rows, n = A.cols;
+  constexpr int RR = kSetupRows, CG = kSetupGroups, RC = 8;
+  for (int e = tid; e < 4 * n; e += nthr) vs[e] = (double)(bsplitmix64((uint64_t)e, seed) >> 11) * 0x1p-52 - 1.0;
+  __syncthreads();
+  double lam = 0.0;
+  for (int step = 0; step < steps; ++step) {
+    double nv = 0.0;
+    for (int e = tid; e < 4 * n; e += nthr) nv += vs[e] * vs[e];
+    nv = wg_sum(nv, sh);
+    const double inv = 1.0 / sqrt(nv);
+    for (int i0 = RR * wave; i0 < m; i0 += RR * nw) {
+      double acc[RR][4];
+#pragma unroll
+      for (int r = 0; r < RR; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+      for (int j0 = 0; j0 < n; j0 += 64 * CG) {
+        float a[RR][CG][4];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          const int64_t i = i0 + r < m ? i0 + r : m - 1;
+#pragma unroll
+          for (int k = 0; k < CG; ++k) {
+            const int j = j0 + lane + 64 * k;
+            const int64_t o = i * A.ld + (j < n ? j : n - 1);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) a[r][k][p] = gload(A.p, p * A.ps + o);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < CG; ++k) {
+          const int j = j0 + lane + 64 * k;
+          const bool ok = j < n;
+          const int jc = ok ? j : 0;
+          const double vs0 = ok ? vs[jc] : 0.0, vx = ok ? vs[n + jc] : 0.0, vy = ok ? vs[2 * n + jc] : 0.0,
+                       vz = ok ? vs[3 * n + jc] : 0.0;
+#pragma unroll
+          for (int r = 0; r < RR; ++r) {
+            const double as = a[r][k][0], ax = a[r][k][1], ay = a[r][k][2], az = a[r][k][3];
+            acc[r][0] += as * vs0 - ax * vx - ay * vy - az * vz;
+            acc[r][1] += as * vx + ax * vs0 + ay * vz - az * vy;
+            acc[r][2] += as * vy - ax * vz + ay * vs0 + az * vx;
+            acc[r][3] += as * vz + ax * vy - ay * vx + az * vs0;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RR; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double t = wave_sum(acc[r][c]);
+          if (lane == 0 && i0 + r < m) ws[c * m + i0 + r] = t * inv;
+        }
+    }
+    __syncthreads();
+    double l2 = 0.0;
+    for (int e = tid; e < 4 * m; e += nthr) l2 += ws[e] * ws[e];
+    lam = wg_sum(l2, sh);
+    for (int c0 = 64 * wave; c0 < n; c0 += 64 * nw) {
+      const int j = c0 + lane;
+      const int jc = j < n ? j : n - 1;
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+      for (int i0 = 0; i0 < m; i0 += RC) {
+        float a[RC][4];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          const int64_t o = (int64_t)(i0 + r < m ? i0 + r : m - 1) * A.ld + jc;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) a[r][p] = gload(A.p, p * A.ps + o);
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          const int i = i0 + r;
+          const bool ok = i < m;
+          const int ic = ok ? i : 0;
+          const double w0 = ok ? ws[ic] : 0.0, wx = ok ? ws[m + ic] : 0.0, wy = ok ? ws[2 * m + ic] : 0.0,
+                       wz = ok ? ws[3 * m + ic] : 0.0;
+          const double as = a[r][0], ax = a[r][1], ay = a[r][2], az = a[r][3];
+          t0 += as * w0 + ax * wx + ay * wy + az * wz;
+          t1 += as * wx - ax * w0 - ay * wz + az * wy;
+          t2 += as * wy + ax * wz - ay * w0 - az * wx;
+          t3 += as * wz - ax * wy + ay * wx - az * w0;
+        }
+      }
+      if (j < n) {
+        vs[j] = t0;
+        vs[n + j] = t1;
+        vs[2 * n + j] = t2;
+        vs[3 * n + j] = t3;
+      }
+    }
+    __syncthreads();
+  }
+  return lam;
+}
+
 // Per-matrix set-up by one workgroup: finiteness and ||A||_F, the scaling (power iteration on A^H A
-// from the SplitMix64 start vector, or the given alpha) and X_0 = alpha A^H into X0.  `dw` holds
-// 4 (Dv + Dv) doubles with Dv >= max(m, n).  Returns false (info.status = ENONFINITE) for a non-finite A.
-__device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsigned long long seed, double alpha_given, const DM& A,
-                             const DM& X0, double* dw, int Dv, double* sh, float* lds, BInfo& info, double& normA,
-                             double& alpha) {
+// from the SplitMix64 start vector, or the given alpha) and X_0 = alpha A^H into X0; A is also copied
+// to Ac unless Ac.p is null.  The power iteration keeps its vectors in `lds` (lds_floats floats) when
+// they fit, else in `dw` (4 (Dv + Dv) doubles with Dv >= max(m, n)).  Returns false (info.status =
+// ENONFINITE) for a non-finite A.
+__device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsigned long long seed, double alpha_given,
+                                             const DM& A, const DM& Ac, const DM& X0, double* dw, int Dv, double* sh,
+                                             float* lds, int lds_floats, BInfo& info, double& normA, double& alpha) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int lane = tid & 63, nw = nthr >> 6;
   const int m = A.rows, n = A.cols;
+  // one wave per row, lanes along the row: coalesced, 4 chunks of 64 columns in flight per wave
+  constexpr int NG = 4;
   double fro2 = 0.0, nf = 0.0;
-  for (int e = tid; e < m * n; e += nthr) {
-    const int i = e / n, j = e - i * n;
-    for (int p = 0; p < 4; ++p) {
-      const double v = A.p[p * A.ps + (int64_t)i * A.ld + j];
-      if (!__builtin_isfinite(v)) nf += 1.0;
-      fro2 += v * v;
+  for (int i = tid >> 6; i < m; i += nw) {
+    for (int j0 = 0; j0 < n; j0 += 64 * NG) {
+      float a[NG][4];
+#pragma unroll
+      for (int k = 0; k < NG; ++k) {
+        const int j = j0 + lane + 64 * k;
+        const bool ok = j < n;
+        const int64_t o = (int64_t)i * A.ld + (ok ? j : n - 1);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const float x = gload(A.p, p * A.ps + o);
+          a[k][p] = ok ? x : 0.f;
+        }
+      }
+      if (Ac.p != nullptr) {
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+          const int j = j0 + lane + 64 * k;
+          if (j < n)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) gstore(Ac.p, p * Ac.ps + (int64_t)i * Ac.ld + j, a[k][p]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NG; ++k) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const double v = a[k][p];
+          if (!__builtin_isfinite(v)) nf += 1.0;
+          fro2 += v * v;
+        }
+      }
     }
   }
   fro2 = wg_sum(fro2, sh);
@@ -191,6 +337,11 @@ __device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsig
   normA = sqrt(fro2);
   if (scaling == 2) {
     alpha = alpha_given;
+  } else if (8 * (m + n) <= lds_floats) {
+    const double lam = power_lds(A, power_steps, seed, reinterpret_cast<double*>(lds),
+                                 reinterpret_cast<double*>(lds) + 4 * n, sh);
+    info.sigma1_sq = lam;
+    alpha = 1.0 / lam;
   } else {
     double* v = dw;            // 4n
     double* wv = dw + 4 * Dv;  // 4m
@@ -202,18 +353,35 @@ __device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsig
       for (int e = tid; e < 4 * n; e += nthr) nv += v[e] * v[e];
       nv = wg_sum(nv, sh);
       const double inv = 1.0 / sqrt(nv);
-      // w = A v: one wave per row, lanes along the row (coalesced), fixed-order wave reduction
-#pragma unroll 2
+      // w = A v: one wave per row, lanes along the row (coalesced), fixed-order wave reduction; NG
+      // column chunks in flight per row.
       for (int i = tid >> 6; i < m; i += nw) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int j = lane; j < n; j += 64) {
-          const int64_t o = (int64_t)i * A.ld + j;
-          const double as = A.p[o], ax = A.p[A.ps + o], ay = A.p[2 * A.ps + o], az = A.p[3 * A.ps + o];
-          const double vs = v[j], vx = v[n + j], vy = v[2 * n + j], vz = v[3 * n + j];
-          s0 += as * vs - ax * vx - ay * vy - az * vz;
-          s1 += as * vx + ax * vs + ay * vz - az * vy;
-          s2 += as * vy - ax * vz + ay * vs + az * vx;
-          s3 += as * vz + ax * vy - ay * vx + az * vs;
+        for (int j0 = 0; j0 < n; j0 += 64 * NG) {
+          float a[NG][4];
+          double vv[NG][4];
+#pragma unroll
+          for (int k = 0; k < NG; ++k) {
+            const int j = j0 + lane + 64 * k;
+            const bool ok = j < n;
+            const int64_t o = (int64_t)i * A.ld + (ok ? j : 0);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              const float x = gload(A.p, p * A.ps + o);
+              const double y = gload(v, p * n + (ok ? j : 0));
+              a[k][p] = ok ? x : 0.f;
+              vv[k][p] = ok ? y : 0.0;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < NG; ++k) {
+            const double as = a[k][0], ax = a[k][1], ay = a[k][2], az = a[k][3];
+            const double vs = vv[k][0], vx = vv[k][1], vy = vv[k][2], vz = vv[k][3];
+            s0 += as * vs - ax * vx - ay * vy - az * vz;
+            s1 += as * vx + ax * vs + ay * vz - az * vy;
+            s2 += as * vy - ax * vz + ay * vs + az * vx;
+            s3 += as * vz + ax * vy - ay * vx + az * vs;
+          }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -240,15 +408,32 @@ __device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsig
         const int j = j0 + lane;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         if (j < n) {
-#pragma unroll 4
-          for (int i = tid >> 6; i < m; i += nw) {
-            const int64_t o = (int64_t)i * A.ld + j;
-            const double as = A.p[o], ax = A.p[A.ps + o], ay = A.p[2 * A.ps + o], az = A.p[3 * A.ps + o];
-            const double ws = wv[i], wx = wv[m + i], wy = wv[2 * m + i], wz = wv[3 * m + i];
-            s0 += as * ws + ax * wx + ay * wy + az * wz;
-            s1 += as * wx - ax * ws - ay * wz + az * wy;
-            s2 += as * wy + ax * wz - ay * ws - az * wx;
-            s3 += as * wz - ax * wy + ay * wx - az * ws;
+          // rows i0 + k nw, k < NG, loaded together (fixed count, predicated)
+          for (int i0 = tid >> 6; i0 < m; i0 += NG * nw) {
+            float a[NG][4];
+            double ww[NG][4];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+              const int i = i0 + k * nw;
+              const bool ok = i < m;
+              const int64_t o = (int64_t)(ok ? i : 0) * A.ld + j;
+#pragma unroll
+              for (int p = 0; p < 4; ++p) {
+                const float x = gload(A.p, p * A.ps + o);
+                const double y = gload(wv, p * m + (ok ? i : 0));
+                a[k][p] = ok ? x : 0.f;
+                ww[k][p] = ok ? y : 0.0;
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+              const double as = a[k][0], ax = a[k][1], ay = a[k][2], az = a[k][3];
+              const double ws = ww[k][0], wx = ww[k][1], wy = ww[k][2], wz = ww[k][3];
+              s0 += as * ws + ax * wx + ay * wy + az * wz;
+              s1 += as * wx - ax * ws - ay * wz + az * wy;
+              s2 += as * wy + ax * wz - ay * ws - az * wx;
+              s3 += as * wz - ax * wy + ay * wx - az * ws;
+            }
           }
         }
         double* r = red + (int64_t)(tid >> 6) * 256 + lane * 4;
@@ -278,24 +463,33 @@ __device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsig
     alpha = 1.0 / lam;
   }
   info.alpha = alpha;
-  // X_0 = alpha A^H, transposed through 32 x 32 LDS tiles (coalesced reads and writes)
-  float* tile = lds;  // [32][33]
+  // X_0 = alpha A^H, transposed through 32 x 32 LDS tiles of all four planes (coalesced reads and writes)
+  float* tile = lds;  // [4][32][33]
   const int tr = tid >> 5, tc = tid & 31, rstep = nthr >> 5;
   for (int ib = 0; ib < m; ib += 32)
-    for (int jb = 0; jb < n; jb += 32)
-      for (int p = 0; p < 4; ++p) {
-        const double sc = p == 0 ? alpha : -alpha;
-        for (int r = tr; r < 32; r += rstep) {
-          const int i = ib + r, j = jb + tc;
-          tile[r * 33 + tc] = (i < m && j < n) ? A.p[p * A.ps + (int64_t)i * A.ld + j] : 0.f;
+    for (int jb = 0; jb < n; jb += 32) {
+      for (int r = tr; r < 32; r += rstep) {
+        const int i = ib + r, j = jb + tc;
+        const bool ok = i < m && j < n;
+        const int64_t o = (int64_t)(i < m ? i : m - 1) * A.ld + (j < n ? j : n - 1);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const float x = gload(A.p, p * A.ps + o);
+          tile[(p * 32 + r) * 33 + tc] = ok ? x : 0.f;
         }
-        __syncthreads();
-        for (int r = tr; r < 32; r += rstep) {
-          const int j = jb + r, i = ib + tc;
-          if (j < n && i < m) X0.p[p * X0.ps + (int64_t)j * X0.ld + i] = (float)(sc * (double)tile[tc * 33 + r]);
-        }
-        __syncthreads();
       }
+      __syncthreads();
+      for (int r = tr; r < 32; r += rstep) {
+        const int j = jb + r, i = ib + tc;
+        if (j < n && i < m) {
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+            gstore(X0.p, p * X0.ps + (int64_t)j * X0.ld + i,
+                   (float)((p == 0 ? alpha : -alpha) * (double)tile[(p * 32 + tc) * 33 + r]));
+        }
+      }
+      __syncthreads();
+    }
   __threadfence_block();
   __syncthreads();
   return true;
@@ -305,6 +499,7 @@ template <class MM, int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) batched_kernel(BParams P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) float smem[C::SMEM];
+  static_assert(C::SMEM >= 4 * 32 * 33 && C::SMEM >= 2 * 4 * 64 * 4, "set-up scratch fits in the staging LDS");
   __shared__ double sh[16];
   __shared__ int s_next;
   const int tid = threadIdx.x;
@@ -351,7 +546,10 @@ __global__ void __launch_bounds__(64 * WM * WN) batched_kernel(BParams P) {
 
     DM X[4] = {buf(BX, n, m), buf(BX + 1, n, m), buf(BX + 2, n, m), buf(BX + 3, n, m)};
     double normA = 0.0, alpha = 0.0;
-    if (!setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, X[0], dw, D, sh, smem,
+    DM none;
+    none.p = nullptr;
+    if (!setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, none, X[0], dw, D, sh, smem,
+                      C::SMEM,
                       info, normA, alpha)) {
       if (tid == 0) P.info[b] = info;
       continue;
@@ -483,7 +681,8 @@ __global__ void __launch_bounds__(64 * WM * WN) batched_kernel(BParams P) {
       const int rs = (j - 1) & 1;
       for (int e = tid; e < s * s; e += nthr) {
         const int i = e / s, c = e - i * s;
-        for (int p = 0; p < 4; ++p) W[(int64_t)(BR + rs) * 4 * PS + p * PS + (int64_t)i * D + c] = R.p[p * PS + (int64_t)i * D + c];
+        for (int p = 0; p < 4; ++p)
+          gstore(W, (int64_t)(BR + rs) * 4 * PS + p * PS + (int64_t)i * D + c, gload(R.p, p * PS + (int64_t)i * D + c));
       }
       __threadfence_block();
       __syncthreads();
@@ -561,7 +760,7 @@ __global__ void __launch_bounds__(64 * WM * WN) batched_kernel(BParams P) {
     const DM& Xr = X[done_buf];
     for (int e = tid; e < n * m; e += nthr) {
       const int i = e / m, j = e - i * m;
-      for (int p = 0; p < 4; ++p) d.X[p * d.psx + (int64_t)i * d.ldx + j] = Xr.p[p * PS + (int64_t)i * D + j];
+      for (int p = 0; p < 4; ++p) gstore(d.X, p * d.psx + (int64_t)i * d.ldx + j, gload(Xr.p, p * PS + (int64_t)i * D + j));
     }
     if (tid == 0) P.info[b] = info;
     __threadfence();
@@ -649,7 +848,9 @@ __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks) {
 }
 
 // Views of matrix b's work buffers: 10 of s x s (chain 0..7, residuals 8..9) and 5 of n x m (iterates
-// 0..3, candidate product 4).
+// 0..3, candidate product 4); when A's rows are not 16-byte aligned, a copy of A whose rows are
+// (BDesc::ldap > 0) follows them.  All have 16-byte aligned rows and planes, so every product takes
+// 16-byte operand loads.
 struct MBufs {
   float* base;
   int64_t lds, pss, ldw, psw;
@@ -866,7 +1067,7 @@ __device__ __forceinline__ GemmParams<float> gemm_params(const DM& Aop, const DM
   G.K = Aop.cols;
   G.tiles_m = (G.M + BM - 1) / BM;
   G.tiles_n = (G.N + BN - 1) / BN;
-  G.vec = ((Aop.ld | Aop.ps | Bop.ld | Bop.ps) & 3) == 0;
+  G.vec = ((Aop.ld | Aop.ps | Bop.ld | Bop.ps) & 3) == 0 && ((reinterpret_cast<uintptr_t>(Aop.p) | reinterpret_cast<uintptr_t>(Bop.p)) & 15) == 0;
   G.nout = e.nout;
   G.nin = e.nin;
   G.ref = e.ref;
@@ -888,6 +1089,16 @@ __device__ __forceinline__ GemmParams<float> gemm_params(const DM& Aop, const DM
   return G;
 }
 
+// Tile t of a product: 16-byte operand loads, edge tiles included, when both operands allow them (the
+// work buffers always do; the caller's A only with a 16-byte multiple row stride), else element loads.
+template <class MM, int BM, int BN, int BK, int WM, int WN>
+__device__ __forceinline__ void tile_any(const GemmParams<float>& G, int t, float* smem, double& a0, double& a1) {
+  if (G.vec)
+    gemm_tile<MM, BM, BN, BK, WM, WN, 128, kLoadVec>(G, t / G.tiles_n, t % G.tiles_n, smem, a0, a1);
+  else
+    gemm_tile<MM, BM, BN, BK, WM, WN, 128, kLoadScalar>(G, t / G.tiles_n, t % G.tiles_n, smem, a0, a1);
+}
+
 template <int BM, int BN>
 __device__ __forceinline__ int tiles_of(int rows, int cols) {
   return ((rows + BM - 1) / BM) * ((cols + BN - 1) / BN);
@@ -904,6 +1115,7 @@ template <class MM, int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) float smem[C::SMEM];
+  static_assert(C::SMEM >= 4 * 32 * 33 && C::SMEM >= 2 * 4 * 64 * 4, "set-up scratch fits in the staging LDS");
   __shared__ double sh[16];
   __shared__ int pref[SYNC_MAX + 1];
   __shared__ int s_mn[SYNC_MAX];  // m | n << 16 per matrix
@@ -945,8 +1157,12 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P
     double normA = 0.0, alpha = 0.0;
     const int Dv = d.m > d.n ? d.m : d.n;
     const unsigned long long t_set = wall_clock64();
-    const bool ok = setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, B.xw(0),
-                                 P.dwork + d.doff, Dv, sh, smem, info, normA, alpha);
+    DM Ac = A;  // the copy of A with 16-byte aligned rows, when there is one
+    Ac.p = d.ldap > 0 ? B.base + 10 * 4 * d.pss + 5 * 4 * d.psw : nullptr;
+    Ac.ld = d.ldap;
+    Ac.ps = d.psap;
+    const bool ok = setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, Ac, B.xw(0),
+                                 P.dwork + d.doff, Dv, sh, smem, C::SMEM, info, normA, alpha);
     if (P.trace && tid == 0 && kTraceCap / 2 + b < kTraceCap) P.trace[kTraceCap / 2 + b] = wall_clock64() - t_set;
     if (tid == 0) {
       LState S;
@@ -1049,7 +1265,7 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P
             if (i < d.n && c < d.m)
 #pragma unroll
               for (int p = 0; p < 4; ++p)
-                d.X[p * d.psx + (int64_t)i * d.ldx + c] = Xr.p[p * Xr.ps + (int64_t)i * Xr.ld + c];
+                gstore(d.X, p * d.psx + (int64_t)i * d.ldx + c, gload(Xr.p, p * Xr.ps + (int64_t)i * Xr.ld + c));
           }
           continue;
         }
@@ -1064,7 +1280,7 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P
           GemmParams<float> Gp = left ? gemm_params(Rr, Xr, eo, BM, BN) : gemm_params(Xr, Rr, eo, BM, BN);
           make_uniform(Gp);
           double a0 = 0.0, a1 = 0.0;
-          gemm_tile<MM, BM, BN, BK, WM, WN, 128>(Gp, t / Gp.tiles_n, t % Gp.tiles_n, smem, a0, a1);
+          tile_any<MM, BM, BN, BK, WM, WN>(Gp, t, smem, a0, a1);
           a0 = wg_sum(a0, sh);
           if (tid == 0) P.partial[d.poff + 2 * ((ph - 1) * tiles_of<BM, BN>(d.n, d.m) + t)] = a0;
           __syncthreads();
@@ -1083,10 +1299,11 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P
             e.a[1] = 1.f;
           }
           if (ph == 1) {
+            const bool copied = d.ldap > 0;
             DM A;
-            A.p = const_cast<float*>(d.A);
-            A.ld = d.lda;
-            A.ps = d.psa;
+            A.p = copied ? B.base + 10 * 4 * d.pss + 5 * 4 * d.psw : const_cast<float*>(d.A);
+            A.ld = copied ? d.ldap : d.lda;
+            A.ps = copied ? d.psap : d.psa;
             A.rows = d.m;
             A.cols = d.n;
             const DM Xc = B.xw(S.cur);
@@ -1097,7 +1314,7 @@ __global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P
           GemmParams<float> Gp = gemm_params(Aop, Bop, e, BM, BN);
           make_uniform(Gp);
           double a0 = 0.0, a1 = 0.0;
-          gemm_tile<MM, BM, BN, BK, WM, WN, 128>(Gp, t / Gp.tiles_n, t % Gp.tiles_n, smem, a0, a1);
+          tile_any<MM, BM, BN, BK, WM, WN>(Gp, t, smem, a0, a1);
           if (ph == np) {
             a0 = wg_sum(a0, sh);
             a1 = wg_sum(a1, sh);
@@ -1264,8 +1481,8 @@ static int occupancy_of() {
 template <class MM, int BM, int BN, int BK, int WM, int WN>
 static int occupancy_sync() {
   int nb = 0;
-  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_sync_kernel<MM, BM, BN, BK, WM, WN>, 64 * WM * WN,
-                                                      0));
+  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_sync_kernel<MM, BM, BN, BK, WM, WN>,
+                                                      64 * WM * WN, 0));
   return std::max(nb, 1);
 }
 
@@ -1308,8 +1525,12 @@ void batched_layout(std::vector<BDesc>& desc, int cfg, int64_t& pool, int64_t& p
     d.pss = s * d.lds;
     d.ldw = up4(d.m);
     d.psw = (int64_t)d.n * d.ldw;
+    // the side product takes 16-byte loads of A: a copy unless its rows and planes are 16-byte aligned
+    const bool aligned = ((d.lda | d.psa) & 3) == 0 && (reinterpret_cast<uintptr_t>(d.A) & 15) == 0;
+    d.ldap = aligned ? 0 : up4(d.n);
+    d.psap = (int64_t)d.m * d.ldap;
     d.off = pool;
-    pool += 4 * (10 * d.pss + 5 * d.psw);
+    pool += 4 * (10 * d.pss + 5 * d.psw + d.psap);
     d.poff = part;
     part += 4 * (int64_t)((d.n + ent.bm - 1) / ent.bm) * ((d.m + ent.bn - 1) / ent.bn);  // 2 products x 2
     d.doff = dwork;

@@ -18,6 +18,7 @@ struct BDesc {
   int m, n;
   int64_t off = 0, poff = 0, doff = 0;
   int64_t lds = 0, pss = 0, ldw = 0, psw = 0;
+  int64_t ldap = 0, psap = 0;  // copy of A with 16-byte aligned rows (ldap = 0: A itself is aligned)
 };
 
 // Per-matrix outcome written by the kernel.

@@ -26,9 +26,9 @@ namespace qp {
 // WALK = false: one tile per workgroup.  WALK = true: tiles blockIdx.x, blockIdx.x + gridDim.x, ...
 // (a separate instantiation, so that the loop's live state does not raise the register count, and
 // with it lower the occupancy, of the one-tile form).  With a grid that is a multiple of 8, every tile a
-// workgroup visits maps to the same XCD range, so the XCD-aware order is kept.  ALIGNED and DB as in
-// gemm_tile.
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, bool ALIGNED, bool WALK, int MINW>
+// workgroup visits maps to the same XCD range, so the XCD-aware order is kept.  LM (the operand load
+// mode) and DB as in gemm_tile.
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, int LM, bool WALK, int MINW>
 __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_kernel(GemmParams<typename MM::T> P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) typename MM::T smem[DB ? 2 * C::SMEM : C::SMEM];
@@ -39,12 +39,12 @@ __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_kernel(GemmParams<ty
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
       int tm, tn;
       tile_of_block(t, nt, P.tiles_m, P.tiles_n, tm, tn);
-      gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH, ALIGNED, DB>(P, tm, tn, smem, s_d, s_x);
+      gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH, LM, DB>(P, tm, tn, smem, s_d, s_x);
     }
   } else {
     int tm, tn;
     tile_of_block(blockIdx.x, nt, P.tiles_m, P.tiles_n, tm, tn);
-    gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH, ALIGNED, DB>(P, tm, tn, smem, s_d, s_x);
+    gemm_tile<MM, BM, BN, BK, WM, WN, FLUSH, LM, DB>(P, tm, tn, smem, s_d, s_x);
   }
   store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
 }
@@ -142,8 +142,26 @@ static KernelLimits kernel_limits(K kern, int threads) {
 }
 
 // Launches the configuration; returns the number of workgroups (partial sums) launched.  PER_CU as
-// TileConfig::per_cu; the aligned form is used whenever the shape and the views allow it.
+// TileConfig::per_cu.  The operand load mode is the most specific one the shape and the views allow.
 // MINW: waves per SIMD the register allocation must leave room for (launch bound).
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, int MINW, bool WALK, int LM>
+static void launch_mode(const GemmParams<typename MM::T>& P, int64_t grid, size_t dyn_lds, hipStream_t s) {
+  using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
+  hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, LM, WALK, MINW>), dim3((unsigned)grid), dim3(C::NT),
+                     dyn_lds, s, P);
+}
+
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, int MINW, bool WALK>
+static void launch_any_mode(const GemmParams<typename MM::T>& P, int64_t grid, size_t dyn_lds, hipStream_t s) {
+  if (P.vec && P.M % BM == 0 && P.N % BN == 0 && P.K % BK == 0)
+    launch_mode<MM, BM, BN, BK, WM, WN, FLUSH, DB, MINW, WALK, kLoadAligned>(P, grid, dyn_lds, s);
+  else if (P.vec)
+    launch_mode<MM, BM, BN, BK, WM, WN, FLUSH, DB, MINW, WALK, kLoadVec>(P, grid, dyn_lds, s);
+  else
+    launch_mode<MM, BM, BN, BK, WM, WN, FLUSH, DB, MINW, WALK, kLoadScalar>(P, grid, dyn_lds, s);
+  QP_HIP(hipGetLastError());
+}
+
 template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool DB, int PER_CU, int MINW = 1>
 static int64_t launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
@@ -152,28 +170,16 @@ static int64_t launch_cfg(const GemmParams<typename MM::T>& P0, hipStream_t s) {
   P.tiles_n = (P.N + BN - 1) / BN;
   const int64_t nt = (int64_t)P.tiles_m * P.tiles_n;
   if (nt == 0) return 0;
-  const bool aligned = P.vec && P.M % BM == 0 && P.N % BN == 0 && P.K % BK == 0;
   if constexpr (PER_CU > 0) {
-    auto walk = qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, true, MINW>;
-    static const KernelLimits kl = kernel_limits(walk, C::NT);
+    static const KernelLimits kl =
+        kernel_limits(qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, kLoadAligned, true, MINW>, C::NT);
     const LaunchShape ls = launch_shape(nt, PER_CU, kl.occ, kl.lds);
     if (ls.grid < nt) {
-      if (aligned)
-        hipLaunchKernelGGL(walk, dim3((unsigned)ls.grid), dim3(C::NT), ls.dyn_lds, s, P);
-      else
-        hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, true, MINW>), dim3((unsigned)ls.grid),
-                           dim3(C::NT), ls.dyn_lds, s, P);
-      QP_HIP(hipGetLastError());
+      launch_any_mode<MM, BM, BN, BK, WM, WN, FLUSH, DB, MINW, true>(P, ls.grid, ls.dyn_lds, s);
       return ls.grid;
     }
   }
-  if (aligned)
-    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, true, false, MINW>), dim3((unsigned)nt), dim3(C::NT),
-                       0, s, P);
-  else
-    hipLaunchKernelGGL((qgemm_kernel<MM, BM, BN, BK, WM, WN, FLUSH, DB, false, false, MINW>), dim3((unsigned)nt), dim3(C::NT),
-                       0, s, P);
-  QP_HIP(hipGetLastError());
+  launch_any_mode<MM, BM, BN, BK, WM, WN, FLUSH, DB, MINW, false>(P, nt, 0, s);
   return nt;
 }
 

@@ -47,14 +47,17 @@ struct MM16D {
 
 template <class T>
 struct V16;
+typedef double doublex2 __attribute__((ext_vector_type(2)));
 template <>
 struct V16<float> {
   using type = float4;
+  using nat = floatx4;  // the native vector type, for loads through address space 1
   static constexpr int n = 4;
 };
 template <>
 struct V16<double> {
   using type = double2;
+  using nat = doublex2;
   static constexpr int n = 2;
 };
 
@@ -76,6 +79,18 @@ struct GemmParams {
   double* partial;  // per-workgroup partial sums of the reduction (standalone kernels)
   int reduce;       // accumulate the reduction terms
 };
+
+// Global-memory accesses through address space 1.  A pointer that was loaded from memory (a batch
+// descriptor) or passed through readfirstlane is generic to the compiler, and generic (flat) accesses
+// count against the LDS wait counter too, so every LDS wait would also wait for loads in flight.
+template <class T>
+__device__ __forceinline__ T gload(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+template <class T>
+__device__ __forceinline__ void gstore(T* p, int64_t i, T v) {
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
+}
 
 // Hamilton product of one fragment set: acc_p += sum_q sign(p,q) a_q b_{r(p,q)}.
 template <class MM>
@@ -119,9 +134,18 @@ __device__ __forceinline__ void tile_of_block(int bid, int nb, int tiles_m, int 
 // The epilogue inputs in_u of plane p at one element (0 outside the output or beyond nin).
 template <class T>
 __device__ __forceinline__ void epilogue_inputs(const GemmParams<T>& P, int p, int row, int col, T (&inv)[3]) {
+  // the load address is clamped into the matrix and the value selected afterwards: no branch per load
   const bool ok = row < P.M && col < P.N;
+  const int64_t r = row < P.M ? row : P.M - 1, c = col < P.N ? col : P.N - 1;
 #pragma unroll
-  for (int u = 0; u < 3; ++u) inv[u] = (ok && u < P.nin) ? P.in[u][p * P.psi[u] + (int64_t)row * P.ldi[u] + col] : T(0);
+  for (int u = 0; u < 3; ++u) {
+    if (u < P.nin) {
+      const T x = gload(P.in[u], p * P.psi[u] + r * P.ldi[u] + c);
+      inv[u] = ok ? x : T(0);
+    } else {
+      inv[u] = T(0);
+    }
+  }
 }
 
 // out_t = a_t v + sum_u b_tu in_u + g_t I for plane p at one element, plus the reduction terms; inv
@@ -135,7 +159,7 @@ __device__ __forceinline__ void epilogue_apply(const GemmParams<T>& P, int p, in
   for (int t = 0; t < 3; ++t) {
     if (t < P.nout) {
       const T o = P.ca[t] * v + P.cg[t] * eye + P.cb[t][0] * inv[0] + P.cb[t][1] * inv[1] + P.cb[t][2] * inv[2];
-      P.out[t][p * P.pso[t] + (int64_t)row * P.ldo[t] + col] = o;
+      gstore(P.out[t], p * P.pso[t] + (int64_t)row * P.ldo[t] + col, o);
       if (t == 0 && P.reduce) {
         const double od = (double)o;
         const double ref = P.ref == 0 ? (double)inv[0] : P.ref == 1 ? (double)inv[1] : P.ref == 2 ? (double)inv[2] : 0.0;
@@ -198,15 +222,23 @@ struct GemmCfg {
   static_assert(LDS_BYTES <= 65536, "LDS budget");
 };
 
+// Operand load modes of gemm_tile.
+//   kLoadScalar:  any ld; tiles that cross the matrix edge load element by element.
+//   kLoadVec:     16-byte aligned bases, ld and plane strides (GemmParams::vec); edge tiles take the same
+//                 16-byte loads from a row and a k chunk clamped into the matrix.  A row may then be
+//                 read up to ld (never past it), and the elements outside the matrix are replaced by
+//                 zeros: any value there, NaN included, leaves the product unchanged.
+//   kLoadAligned: kLoadVec, and M % BM = N % BN = K % BK = 0: no clamps and no masks.
+enum : int { kLoadScalar = 0, kLoadVec = 1, kLoadAligned = 2 };
+
 // One BM x BN output tile (all four planes) of C = A B with the epilogue; the epilogue's reduction
 // terms are added to the caller's s_d, s_x.  Used by the standalone product kernel and by the batched
 // solver (a workgroup walks all tiles).
-//   ALIGNED: the caller guarantees 16-byte vector loads and M % BM = N % BN = K % BK = 0, so the loads
-//            carry no bounds checks or scalar fallbacks.
+//   LM:      the operand load mode (above).
 //   DB:      two LDS staging buffers (`smem` holds 2 C::SMEM elements): the next K step is written to
 //            one while the MFMAs read the other, one barrier per K step; otherwise one buffer
 //            (C::SMEM elements) and two barriers per K step.
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, bool ALIGNED = false, bool DB = false>
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, int LM = kLoadScalar, bool DB = false>
 __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, int tm, int tn, typename MM::T* smem,
                                           double& s_d, double& s_x) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
@@ -265,9 +297,16 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
   T ra[4][C::NA][VA];
   T rb[4][C::NB][VA];
 
+  // Edge tiles in kLoadScalar mode load every element from an address clamped into the matrix; in
+  // kLoadVec mode the 16-byte chunk is clamped.  Either way the elements outside the matrix are zeroed
+  // only when the registers go to LDS, so the loads stay in flight behind the MFMAs like full-tile ones.
+  constexpr bool ALIGNED = LM == kLoadAligned;
+  auto full_a = [&](int k0) { return ALIGNED || (LM == kLoadVec && (m0 + BM <= P.M) && (k0 + BK <= P.K)); };
+  auto full_b = [&](int k0) { return ALIGNED || (LM == kLoadVec && (n0 + BN <= P.N) && (k0 + BK <= P.K)); };
+  using VG = typename V16<T>::nat;
+  // last chunk start that holds an element of the matrix (kLoadVec): k chunks of A, column chunks of B
+  const int kc_last = ((P.K - 1) / VA) * VA, jc_last = ((P.N - 1) / VA) * VA;
   auto load = [&](int k0) {
-    const bool fullA = ALIGNED || (P.vec && (m0 + BM <= P.M) && (k0 + BK <= P.K));
-    const bool fullB = ALIGNED || (P.vec && (n0 + BN <= P.N) && (k0 + BK <= P.K));
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const T* Aq = P.A + q * P.psa;
@@ -277,15 +316,16 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
         const int i = c / (BK / VA), kc = (c % (BK / VA)) * VA;
         if (C::ACH % C::NT == 0 || c < C::ACH) {
           const int gi = m0 + i, gk = k0 + kc;
-          if (fullA) {
-            const VT v = *reinterpret_cast<const VT*>(Aq + (int64_t)gi * P.lda + gk);
-            const T* pv = reinterpret_cast<const T*>(&v);
+          if constexpr (LM == kLoadScalar) {
+            const int64_t ci = gi < P.M ? gi : P.M - 1;
 #pragma unroll
-            for (int e = 0; e < VA; ++e) ra[q][t][e] = pv[e];
+            for (int e = 0; e < VA; ++e) ra[q][t][e] = gload(Aq, ci * P.lda + (gk + e < P.K ? gk + e : P.K - 1));
           } else {
+            const int64_t ci = ALIGNED || gi < P.M ? gi : P.M - 1;
+            const int ck = ALIGNED || gk <= kc_last ? gk : kc_last;
+            const VG v = gload(reinterpret_cast<const VG*>(Aq + ci * P.lda + ck), 0);
 #pragma unroll
-            for (int e = 0; e < VA; ++e)
-              ra[q][t][e] = (gi < P.M && gk + e < P.K) ? Aq[(int64_t)gi * P.lda + gk + e] : T(0);
+            for (int e = 0; e < VA; ++e) ra[q][t][e] = v[e];
           }
         }
       }
@@ -296,22 +336,25 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
         const int k = c / (BN / VA), jc = (c % (BN / VA)) * VA;
         if (C::BCH % C::NT == 0 || c < C::BCH) {
           const int gk = k0 + k, gj = n0 + jc;
-          if (fullB) {
-            const VT v = *reinterpret_cast<const VT*>(Bq + (int64_t)gk * P.ldb + gj);
-            const T* pv = reinterpret_cast<const T*>(&v);
+          if constexpr (LM == kLoadScalar) {
+            const int64_t ck = gk < P.K ? gk : P.K - 1;
 #pragma unroll
-            for (int e = 0; e < VA; ++e) rb[q][t][e] = pv[e];
+            for (int e = 0; e < VA; ++e) rb[q][t][e] = gload(Bq, ck * P.ldb + (gj + e < P.N ? gj + e : P.N - 1));
           } else {
+            const int64_t ck = ALIGNED || gk < P.K ? gk : P.K - 1;
+            const int cj = ALIGNED || gj <= jc_last ? gj : jc_last;
+            const VG v = gload(reinterpret_cast<const VG*>(Bq + ck * P.ldb + cj), 0);
 #pragma unroll
-            for (int e = 0; e < VA; ++e)
-              rb[q][t][e] = (gk < P.K && gj + e < P.N) ? Bq[(int64_t)gk * P.ldb + gj + e] : T(0);
+            for (int e = 0; e < VA; ++e) rb[q][t][e] = v[e];
           }
         }
       }
     }
   };
 
-  auto store = [&](T* As, T* Bs) {
+  // registers of K step k0 to LDS
+  auto store = [&](T* As, T* Bs, int k0) {
+    const bool fullA = full_a(k0), fullB = full_b(k0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
 #pragma unroll
@@ -319,10 +362,11 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
         const int c = tid + t * C::NT;
         if (C::ACH % C::NT == 0 || c < C::ACH) {
           const int i = c / (BK / VA), kc = (c % (BK / VA)) * VA;
+          const bool rin = m0 + i < P.M;
           VT v;
           T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
-          for (int e = 0; e < VA; ++e) pv[e] = ra[q][t][e];
+          for (int e = 0; e < VA; ++e) pv[e] = (fullA || (rin && k0 + kc + e < P.K)) ? ra[q][t][e] : T(0);
           *reinterpret_cast<VT*>(&As[((q * (BK / VA) + kc / VA) * C::LDAC + i) * VA]) = v;
         }
       }
@@ -331,10 +375,11 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
         const int c = tid + t * C::NT;
         if (C::BCH % C::NT == 0 || c < C::BCH) {
           const int k = c / (BN / VA), jc = (c % (BN / VA)) * VA;
+          const bool kin = k0 + k < P.K;
           VT v;
           T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
-          for (int e = 0; e < VA; ++e) pv[e] = rb[q][t][e];
+          for (int e = 0; e < VA; ++e) pv[e] = (fullB || (kin && n0 + jc + e < P.N)) ? rb[q][t][e] : T(0);
           *reinterpret_cast<VT*>(&Bs[(q * BK + k) * C::LDB + jc]) = v;
         }
       }
@@ -386,7 +431,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
     if (P.K > 0) load(0);
     for (int k0 = 0; k0 < P.K; k0 += BK) {
       __syncthreads();
-      store(smem, smem + BOFF);
+      store(smem, smem + BOFF, k0);
       __syncthreads();
       if (k0 + BK < P.K) load(k0 + BK);
       compute(smem, smem + BOFF);
@@ -401,7 +446,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
     __syncthreads();  // the caller may have used the LDS just before (previous tile's epilogue)
     if (P.K > 0) {
       load(0);
-      store(smem, smem + BOFF);
+      store(smem, smem + BOFF, 0);
       if (BK < P.K) load(BK);
     }
     __syncthreads();
@@ -411,7 +456,7 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
       compute(Ac, Ac + BOFF);
       if (k0 + BK < P.K) {
         T* const An = smem + (cur ^ 1) * C::SMEM;
-        store(An, An + BOFF);
+        store(An, An + BOFF, k0 + BK);
         if (k0 + 2 * BK < P.K) load(k0 + 2 * BK);
       }
       if constexpr (FLUSH > 0) {
