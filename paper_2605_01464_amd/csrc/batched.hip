@@ -1111,8 +1111,10 @@ __device__ __forceinline__ int next_buf(const LState& S) {
   return nxt;
 }
 
-template <class MM, int BM, int BN, int BK, int WM, int WN>
-__global__ void __launch_bounds__(64 * WM * WN, 2) batched_sync_kernel(SParams P) {
+// PER_CU: resident workgroups per compute unit the register allocation leaves room for (and the
+// launch uses, at most).
+template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2>
+__global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SParams P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) float smem[C::SMEM];
   static_assert(C::SMEM >= 4 * 32 * 33 && C::SMEM >= 2 * 4 * 64 * 4, "set-up scratch fits in the staging LDS");
@@ -1465,9 +1467,9 @@ static void launch_batched(const BParams& P, int grid, hipStream_t s) {
   QP_HIP(hipGetLastError());
 }
 
-template <class MM, int BM, int BN, int BK, int WM, int WN>
+template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2>
 static void launch_sync(const SParams& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((batched_sync_kernel<MM, BM, BN, BK, WM, WN>), dim3(grid), dim3(64 * WM * WN), 0, s, P);
+  hipLaunchKernelGGL((batched_sync_kernel<MM, BM, BN, BK, WM, WN, PER_CU>), dim3(grid), dim3(64 * WM * WN), 0, s, P);
   QP_HIP(hipGetLastError());
 }
 
@@ -1478,12 +1480,12 @@ static int occupancy_of() {
   return std::max(nb, 1);
 }
 
-template <class MM, int BM, int BN, int BK, int WM, int WN>
+template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2>
 static int occupancy_sync() {
   int nb = 0;
-  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_sync_kernel<MM, BM, BN, BK, WM, WN>,
+  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_sync_kernel<MM, BM, BN, BK, WM, WN, PER_CU>,
                                                       64 * WM * WN, 0));
-  return std::max(nb, 1);
+  return std::min(std::max(nb, 1), PER_CU);
 }
 
 // Queue kernels (one workgroup per matrix) and phase-synchronous kernels (all workgroups per product).
@@ -1507,11 +1509,14 @@ static const std::vector<BatchedEntry>& batched_table() {
        occupancy_sync<MM16F, 32, 32, 16, 2, 2>, 32, 32},
       {"batched_sync_f32_64x64x16_mfma32", nullptr, launch_sync<MM32F, 64, 64, 16, 2, 2>,
        occupancy_sync<MM32F, 64, 64, 16, 2, 2>, 64, 64},
+      {"batched_sync_f32_32x32x32_mfma16", nullptr, launch_sync<MM16F, 32, 32, 32, 2, 2>,
+       occupancy_sync<MM16F, 32, 32, 32, 2, 2>, 32, 32},
   };
   return t;
 }
 
 int batched_num_configs() { return (int)batched_table().size(); }
+
 const char* batched_config_name(int cfg) { return batched_table().at(cfg).name; }
 bool batched_is_sync(int cfg) { return batched_table().at(cfg).sfn != nullptr; }
 
@@ -1595,7 +1600,7 @@ static void build_sync(BatchedState& st, const BKey& key, int64_t pool_cap, int6
   QP_HIP(hipGetDevice(&dev));
   QP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   // every workgroup must be resident for the grid barrier: at most the occupancy per compute unit
-  st.grid = std::max(1, cus * std::min(ent.occ(), 2));
+  st.grid = std::max(1, cus * ent.occ());
   QP_HIP(hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking));
   QP_HIP(hipEventCreateWithFlags(&st.ev0, hipEventDisableTiming));
   QP_HIP(hipEventCreateWithFlags(&st.ev1, hipEventDisableTiming));

@@ -70,5 +70,9 @@ void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& de
 
 int batched_num_configs();
 const char* batched_config_name(int cfg);
+// configurations used without autotuning: phase-synchronous 32 x 32 x 32 tiles, and the queue form
+// with 64 x 64 tiles for batches beyond the phase-synchronous limit
+constexpr int kBatchedDefaultSync = 5;
+constexpr int kBatchedDefaultQueue = 2;
 
 }  // namespace qp

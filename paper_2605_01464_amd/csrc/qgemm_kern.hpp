@@ -247,8 +247,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
   using VT = typename V16<T>::type;
   constexpr int VA = C::VA;
   static_assert(FLUSH == 0 || FLUSH % BK == 0, "flush interval is a whole number of K tiles");
+  static_assert(MM::NR <= 4 || C::NW * MM::BLK * MM::BLK <= C::SMEM, "epilogue slabs fit in the staging LDS");
 
-  static_assert(C::NW * MM::BLK * MM::BLK <= C::SMEM, "epilogue staging fits in LDS");
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -469,45 +469,56 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
   flush();
 
   // ---------------------------------------------------------------- epilogue
-  // Each MFMA block of each plane goes through a per-wave LDS slab, so the accumulators are only
-  // read with compile-time indices and the output pass runs row-contiguous.
-  T* const slab = smem + w * MM::BLK * MM::BLK;
+  // Register r of a lane holds element (crow(lane, r), ccol(lane)) of its MFMA block.  With 4 registers
+  // per block (16 x 16 MFMA) the outputs go straight from the accumulators: a store instruction writes
+  // 16-element row segments, as coalesced as a pass through LDS would be, without its barriers.  With
+  // 16 (32 x 32 MFMA) each block goes through a per-wave LDS slab first, which keeps the accumulators
+  // read with compile-time indices and the register count at the K loop's.  Either way the inputs of
+  // up to 4 elements are loaded first (one memory latency per group), then their outputs written.
+  constexpr int NE = MM::BLK * MM::BLK / 64, NG = NE < 4 ? NE : 4;
+  auto value = [&](int p, int i, int j, int r) -> T {
+    if constexpr (FLUSH > 0)
+      return tot[p][i][j][r];
+    else
+      return acc[p][i][j][r];
+  };
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-    for (int j = 0; j < C::TN; ++j)
+    for (int j = 0; j < C::TN; ++j) {
+      const int rb = m0 + wm * C::WTM + i * MM::BLK, cb = n0 + wn * C::WTN + j * MM::BLK;
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        __syncthreads();
+        if constexpr (MM::NR <= 4) {
+          T inv[MM::NR][3];
 #pragma unroll
-        for (int r = 0; r < MM::NR; ++r) {
-          T v;
-          if constexpr (FLUSH > 0)
-            v = tot[p][i][j][r];
-          else
-            v = acc[p][i][j][r];
-          slab[MM::crow(lane, r) * MM::BLK + MM::ccol(lane)] = v;
-        }
-        __syncthreads();
-        const int rb = m0 + wm * C::WTM + i * MM::BLK, cb = n0 + wn * C::WTN + j * MM::BLK;
-        // the input loads of 4 of this lane's elements at a time first (one memory latency per group),
-        // then their outputs
-        constexpr int NE = MM::BLK * MM::BLK / 64, NG = NE < 4 ? NE : 4;
-        for (int k0 = 0; k0 < NE; k0 += NG) {
-          T inv[NG][3];
+          for (int r = 0; r < MM::NR; ++r) epilogue_inputs(P, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
 #pragma unroll
-          for (int k = 0; k < NG; ++k) {
-            const int e = lane + 64 * (k0 + k);
-            epilogue_inputs(P, p, rb + e / MM::BLK, cb + e % MM::BLK, inv[k]);
-          }
+          for (int r = 0; r < MM::NR; ++r)
+            epilogue_apply(P, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), value(p, i, j, r), inv[r], s_d, s_x);
+        } else {
+          T* const slab = smem + w * MM::BLK * MM::BLK;
+          __syncthreads();
 #pragma unroll
-          for (int k = 0; k < NG; ++k) {
-            const int e = lane + 64 * (k0 + k);
-            epilogue_apply(P, p, rb + e / MM::BLK, cb + e % MM::BLK, slab[e], inv[k], s_d, s_x);
+          for (int r = 0; r < MM::NR; ++r) slab[MM::crow(lane, r) * MM::BLK + MM::ccol(lane)] = value(p, i, j, r);
+          __syncthreads();
+          for (int k0 = 0; k0 < NE; k0 += NG) {
+            T inv[NG][3];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+              const int e = lane + 64 * (k0 + k);
+              epilogue_inputs(P, p, rb + e / MM::BLK, cb + e % MM::BLK, inv[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+              const int e = lane + 64 * (k0 + k);
+              epilogue_apply(P, p, rb + e / MM::BLK, cb + e % MM::BLK, slab[e], inv[k], s_d, s_x);
+            }
           }
         }
       }
-  __syncthreads();  // the LDS slabs / tiles are reused by whatever runs next in this workgroup
+    }
+  __syncthreads();  // the staging LDS is reused by whatever runs next in this workgroup
 }
 
 

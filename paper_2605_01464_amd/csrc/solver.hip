@@ -1274,7 +1274,9 @@ int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A,
     key.cfg = best_cfg;
     c.batched_tuned[sig] = best_cfg;
   } else {
-    key.cfg = 0;
+    // measured on the 512-matrix workload: phase-synchronous 32 x 32 x 32 tiles first, then the
+    // queue form with 64 x 64 tiles (batches above the phase-synchronous limit)
+    key.cfg = usable(kBatchedDefaultSync) ? kBatchedDefaultSync : kBatchedDefaultQueue;
   }
   run_batched(*c.batched, key, desc, order_v, alphas, out, s, c.opt.verbose != 0);
   const double secs = now_s() - t0;

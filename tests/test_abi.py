@@ -54,6 +54,18 @@ def test_strerror_and_bad_arguments_without_gpu():
     assert used == q.EINVAL
 
 
+def test_batched_configuration_table_without_gpu():
+    """The batched forms the library uses without autotuning (phase-synchronous 32 x 32 x 32 tiles,
+    index 5; the queue form with 64 x 64 tiles, index 2) sit where the library expects them."""
+    import paper_2605_01464_amd as q
+
+    n = q.qpinv_num_batched_configs()
+    names = [q.qpinv_batched_config_name(c) for c in range(n)]
+    assert names[5] == "batched_sync_f32_32x32x32_mfma16"
+    assert names[2] == "batched_f32_64x64x16_mfma16"
+    assert all(nm.startswith(("batched_f32_", "batched_sync_f32_")) for nm in names)
+
+
 # ------------------------------------------------------------------ stop-rule controller (host logic)
 def test_controller_dx_abs_and_rel():
     import paper_2605_01464_amd as q

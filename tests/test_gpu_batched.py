@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 # kernel forms: the queue kernel (one workgroup per matrix) and the phase-synchronous kernel (all
 # workgroups per product), with the same 32 x 32 tile routine
-FORMS = {"queue": 0, "sync": 3}
+FORMS = {"queue": 0, "sync": 3, "sync_bk32": 5}
 
 
 @pytest.fixture(autouse=True, params=sorted(FORMS))
