@@ -116,6 +116,7 @@ def main() -> int:
     ap.add_argument("--learned-count", type=int, default=256)
     ap.add_argument("--no-methods", action="store_true", help="skip the other methods on the 2048x1536 input")
     ap.add_argument("--no-small", action="store_true", help="skip the 64x48 FP64 latency section")
+    ap.add_argument("--no-lorenz", action="store_true", help="skip the Lorenz filter-design section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -362,6 +363,32 @@ def main() -> int:
         res["input_and_feature_s"] = t_g
         out["learned_scaling"] = res
         del ev
+
+    if not args.no_lorenz:
+        # filter design of Section 5.2 on the delayed noisy Lorenz record [0, 40] (tau = 1, noise std 1):
+        # square Toeplitz systems of 401..2001 unknowns, FP64 pseudoinverse + both products on the GPU
+        res = {}
+        for dt in qsynth.LORENZ_STEPS:
+            d = qsynth.lorenz_filter_instance(dt)
+            Xd = torch.from_numpy(d["X"]).cuda()
+            sd = torch.from_numpy(d["s"]).cuda()
+            row = {"n": int(d["p"] + 1)}
+            for meth in ("qsai", "qhpi19"):
+                q.filter_design(ctx, Xd, sd, method=meth)
+                torch.cuda.synchronize()
+                times = []
+                for _ in range(3):
+                    t = time.perf_counter()
+                    h, s_hat, inf_f = q.filter_design(ctx, Xd, sd, method=meth)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t)
+                eps = float(torch.linalg.vector_norm(s_hat - sd) / torch.linalg.vector_norm(sd))
+                row[meth] = {"ms": 1e3 * float(np.median(times)), "iters": inf_f["iters"], "eps": eps}
+            res[f"dt_{dt}"] = row
+            del Xd, sd
+        out["lorenz_filtering"] = {"workload": "Lorenz (sigma 10, delta 8/3, gamma 28, x0 [1,1,1]) on [0,40], delay 1, "
+                                               "imaginary noise N(0,1), (p+1)x(p+1) Toeplitz X, h = X^+ s, FP64, "
+                                               "guarded stop tol 1e-13", "results": res}
 
     if not args.no_cpu_baseline:
         # FP64 oracle on the host: one iteration of the same method on the same input (left side),

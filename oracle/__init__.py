@@ -16,8 +16,9 @@ It is written to be plain and checkable against the paper by eye:
                  rules, stop rules, Penrose residuals E1--E4 (Section 4) and the exact-arithmetic
                  spectral model of every iterate.
 * ``mlp``     -- float64 forward/backward of the scaling network, for gradient checks.
+* ``filtering`` -- the quaternion filter design of Section 5.2 (h = X^dagger s, s_hat = X h, eps).
 
 Every function cites the passage it follows.  Functions whose result no independent pin checks are
 marked "parity unpinned" in their docstring.
 """
-from . import quat, methods  # noqa: F401
+from . import quat, methods, filtering  # noqa: F401

@@ -426,6 +426,16 @@ def qgemm(ctx: Context, A, B, C=None, alpha=1.0, beta=0.0, gamma=0.0, gemm_prec=
     return C
 
 
+def filter_design(ctx: Context, X, s, method="qsai", order=None, tol=1e-13, max_iter=100, stop="guarded",
+                  precision=None):
+    """Quaternion filter design of Section 5.2: h = X^dagger s and s_hat = X h.  The pseudoinverse comes
+    from the chosen iteration, both products from the quaternion GEMM.  Returns (h, s_hat, info)."""
+    Xp, info = solve(ctx, X, method, order=order, tol=tol, max_iter=max_iter, stop=stop, precision=precision)
+    h = qgemm(ctx, Xp, s)
+    s_hat = qgemm(ctx, X, h)
+    return h, s_hat, info
+
+
 def features(ctx: Context, A, power_steps=0, stream=None):
     st, out = qpinv_features(ctx.handle, A, power_steps, stream)
     _err(st, "qpinv_features")

@@ -30,6 +30,7 @@ __all__ = [
     "structured_spectral", "structured_pinv", "mp_quantiles",
     "c1_instance", "c2_instance", "c3_instance", "c4_sizes", "c4_instance",
     "c5_spectrum", "c5_sample", "small_spectral_instance",
+    "lorenz_trajectory", "lorenz_filter_instance", "LORENZ_STEPS",
 ]
 
 
@@ -301,3 +302,63 @@ def small_spectral_instance(seed: int, m: int, n: int, s: np.ndarray) -> dict:
     U = stiefel(2 * seed + 1, m, r)
     V = stiefel(2 * seed + 2, n, r)
     return {"A": from_factors(U, np.asarray(s, dtype=np.float64), V), "U": U, "s": np.asarray(s), "V": V}
+
+
+# ----------------------------------------------------------------------------------------------
+# Lorenz filtering workload (Section 5.2): a delayed, noisy quaternion observation of a Lorenz
+# trajectory and the square Toeplitz data matrix of the filter design X h = s
+# ----------------------------------------------------------------------------------------------
+LORENZ_STEPS = (0.01, 0.02, 0.03, 0.04, 0.05)  # the sampling steps of the paper's filtering table
+
+
+def lorenz_trajectory(T: float, dt: float, x0=(1.0, 1.0, 1.0), sigma: float = 10.0, delta: float = 8.0 / 3.0,
+                      gamma: float = 28.0, sub: int = 10) -> np.ndarray:
+    """(u, v, w) of the Lorenz system (Section 5.2: du/dt = sigma (v - u), dv/dt = u (gamma - w) - v,
+    dw/dt = u v - delta w) at t = 0, dt, ..., round(T/dt) dt, from x0 at t = 0.  Classical fourth-order
+    Runge-Kutta with `sub` steps per sample (the paper used an adaptive solver; the trajectory is
+    chaotic, so sample values depend on the integrator beyond t ~ 20 either way).  Shape (n + 1, 3)."""
+    n = int(round(T / dt))
+    h = dt / sub
+
+    def f(u, v, w):
+        return sigma * (v - u), u * (gamma - w) - v, u * v - delta * w
+
+    u, v, w = (float(c) for c in x0)
+    out = np.empty((n + 1, 3))
+    out[0] = (u, v, w)
+    for k in range(n):
+        for _ in range(sub):
+            a = f(u, v, w)
+            b = f(u + 0.5 * h * a[0], v + 0.5 * h * a[1], w + 0.5 * h * a[2])
+            c = f(u + 0.5 * h * b[0], v + 0.5 * h * b[1], w + 0.5 * h * b[2])
+            d = f(u + h * c[0], v + h * c[1], w + h * c[2])
+            u += h / 6.0 * (a[0] + 2.0 * b[0] + 2.0 * c[0] + d[0])
+            v += h / 6.0 * (a[1] + 2.0 * b[1] + 2.0 * c[1] + d[1])
+            w += h / 6.0 * (a[2] + 2.0 * b[2] + 2.0 * c[2] + d[2])
+        out[k + 1] = (u, v, w)
+    return out
+
+
+def lorenz_filter_instance(dt: float, T: float = 40.0, tau: float = 1.0, noise: float = 1.0,
+                           seed: int = 500) -> dict:
+    """Filter-design system of Section 5.2 for sampling step dt on [0, T].
+
+    Samples k = 0..n (n = round(T/dt)).  Reference s_k = u_k i + v_k j + w_k k (pure quaternion).
+    Observation x_k = s_{k-d} + eta_k with d = round(tau/dt) (held at s_0 before the record starts) and
+    eta_k purely imaginary, iid N(0, noise^2) per imaginary component (PCG64 stream `seed`).  With
+    p = n // 2, the data matrix is the (p+1) x (p+1) Toeplitz X[i, j] = x_{p+i-j} (first row x_p, x_{p-1},
+    ..., x_0; last row x_{2p}, ..., x_p) and the target s = (s_p, ..., s_{2p}).
+    Returns X (4, p+1, p+1), s (4, p+1, 1), x (4, n+1), ref (4, n+1) and the sizes."""
+    traj = lorenz_trajectory(T, dt)
+    n = traj.shape[0] - 1
+    d = int(round(tau / dt))
+    ref = np.zeros((4, n + 1))
+    ref[1:] = traj.T
+    rng = np.random.default_rng(seed)
+    x = np.zeros((4, n + 1))
+    x[1:] = ref[1:, np.maximum(np.arange(n + 1) - d, 0)] + noise * rng.standard_normal((3, n + 1))
+    p = n // 2
+    i = np.arange(p + 1)
+    X = np.ascontiguousarray(x[:, p + i[:, None] - i[None, :]])
+    s = np.ascontiguousarray(ref[:, p:2 * p + 1, None])
+    return {"X": X, "s": s, "x": x, "ref": ref, "p": p, "delay": d, "dt": dt, "T": T}
