@@ -223,6 +223,20 @@ int qpinv_qgemm(qpinv_ctx* ctx, int gemm_prec, const qpinv_qmat* A, const qpinv_
  * Errors: EINVAL, EHIP. */
 int qpinv_x0(qpinv_ctx* ctx, const qpinv_qmat* A, double alpha, qpinv_qmat* X, void* hip_stream);
 
+/* Submatrix B = A(rows, cols) (Section 5.1: the CUR factors C = A(:, J) and R = A(I, :)).  rows and
+ * cols are DEVICE arrays of nrows / ncols 0-based indices, or NULL to take every row / column in order
+ * (then nrows / ncols must equal A's).  B is nrows x ncols with A's dtype, written for all four planes.
+ * An index outside A gives NaN in the corresponding row / column of B (the kernel never reads outside
+ * A).  Errors: EINVAL (shapes, dtypes, counts). */
+int qpinv_submatrix(qpinv_ctx* ctx, const qpinv_qmat* A, const int* rows, int nrows, const int* cols, int ncols,
+                    qpinv_qmat* B, void* hip_stream);
+
+/* Masked merge of the impute-reconstruct loop (Section 5.1): Y = Omega (.) M + (1 - Omega) (.) X for all
+ * four planes, Omega given as a DEVICE byte array (rows x cols, row stride mask_ld; nonzero = observed).
+ * M, X and Y share one shape and dtype; Y may be M or X itself.  Errors: EINVAL. */
+int qpinv_masked_merge(qpinv_ctx* ctx, const qpinv_qmat* M, const unsigned char* mask, int64_t mask_ld,
+                       const qpinv_qmat* X, qpinv_qmat* Y, void* hip_stream);
+
 /* Scaling features of A (used by ALPHA_POWER / ALPHA_LEARNED) into host out[7]:
  *   {sigma1_est^2 (power_steps steps on A^H A from the SplitMix64 start vector, seed power_seed),
  *    ||A||_F, ||A||_1, ||A||_inf, rows, cols, the estimate of the step before the last}.

@@ -80,6 +80,8 @@ def _load() -> ctypes.CDLL:
         "qpinv_qgemm": (I, [P, I, QP, QP, QP, D, D, D, P]),
         "qpinv_qgemm_cfg": (I, [P, I, I, QP, QP, QP, D, D, D, P]),
         "qpinv_x0": (I, [P, QP, D, QP, P]),
+        "qpinv_submatrix": (I, [P, QP, P, I, P, I, QP, P]),
+        "qpinv_masked_merge": (I, [P, QP, P, I64, QP, QP, P]),
         "qpinv_features": (I, [P, QP, I, DP, P]),
         "qpinv_autotune": (I, [P, I, I64, I64, I64, DP, P]),
         "qpinv_num_tile_configs": (I, [I]),
@@ -212,6 +214,17 @@ def qpinv_qgemm_cfg(ctx, gemm_prec, cfg, A, B, C, alpha=1.0, beta=0.0, gamma=0.0
 
 def qpinv_x0(ctx, A, alpha, X, stream=None) -> int:
     return _lib.qpinv_x0(ctx, ctypes.byref(qmat(A)), float(alpha), ctypes.byref(qmat(X)), _stream(stream))
+
+
+def qpinv_submatrix(ctx, A, rows, nrows, cols, ncols, B, stream=None) -> int:
+    return _lib.qpinv_submatrix(ctx, ctypes.byref(qmat(A)), _ptr(rows) if rows is not None else None, int(nrows),
+                                _ptr(cols) if cols is not None else None, int(ncols), ctypes.byref(qmat(B)),
+                                _stream(stream))
+
+
+def qpinv_masked_merge(ctx, M, mask, mask_ld, X, Y, stream=None) -> int:
+    return _lib.qpinv_masked_merge(ctx, ctypes.byref(qmat(M)), _ptr(mask), int(mask_ld), ctypes.byref(qmat(X)),
+                                   ctypes.byref(qmat(Y)), _stream(stream))
 
 
 def qpinv_features(ctx, A, power_steps=0, stream=None):
@@ -434,6 +447,62 @@ def filter_design(ctx: Context, X, s, method="qsai", order=None, tol=1e-13, max_
     h = qgemm(ctx, Xp, s)
     s_hat = qgemm(ctx, X, h)
     return h, s_hat, info
+
+
+def submatrix(ctx: Context, A, rows=None, cols=None, out=None, stream=None):
+    """A[rows, cols] for device int32 index tensors (None: all rows / columns)."""
+    import torch
+
+    nr = A.shape[1] if rows is None else int(rows.numel())
+    nc = A.shape[2] if cols is None else int(cols.numel())
+    for t in (rows, cols):
+        if t is not None and (t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("index sets are contiguous int32 device tensors")
+    if out is None:
+        out = torch.empty((4, nr, nc), dtype=A.dtype, device=A.device)
+    _err(qpinv_submatrix(ctx.handle, A, rows, nr, cols, nc, out, stream), "qpinv_submatrix")
+    return out
+
+
+def masked_merge(ctx: Context, M, mask, X, out=None, stream=None):
+    """mask ? M : X elementwise (mask: contiguous uint8 device tensor rows x cols)."""
+    import torch
+
+    if mask.dtype != torch.uint8 or not mask.is_cuda or mask.dim() != 2 or mask.stride(1) != 1:
+        raise ValueError("the mask is a row-major uint8 device tensor")
+    if out is None:
+        out = torch.empty_like(X)
+    _err(qpinv_masked_merge(ctx.handle, M, mask, mask.stride(0), X, out, stream), "qpinv_masked_merge")
+    return out
+
+
+def cur_reconstruct(ctx: Context, A, rows, cols, method="qhpi19", tol=1e-10, max_iter=100, stop="guarded",
+                    precision=None, stream=None):
+    """CUR approximation of Section 5.1 with the Frobenius-optimal coupling U = C^dagger A R^dagger:
+    C = A[:, cols], R = A[rows, :], returns (C U R, U, infos of the two pseudoinverse solves)."""
+    C = submatrix(ctx, A, None, cols, stream=stream)
+    R = submatrix(ctx, A, rows, None, stream=stream)
+    Cp, ic = solve(ctx, C, method, tol=tol, max_iter=max_iter, stop=stop, precision=precision, stream=stream)
+    Rp, ir = solve(ctx, R, method, tol=tol, max_iter=max_iter, stop=stop, precision=precision, stream=stream)
+    U = qgemm(ctx, Cp, qgemm(ctx, A, Rp, stream=stream), stream=stream)
+    X = qgemm(ctx, qgemm(ctx, C, U, stream=stream), R, stream=stream)
+    return X, U, (ic, ir)
+
+
+def cur_complete(ctx: Context, M, mask, rows, cols, iters=25, method="qhpi19", tol=1e-10, max_iter=100,
+                 stop="guarded", precision=None, on_iter=None, stream=None):
+    """Impute-reconstruct completion of Section 5.1: X_t = CUR(C_t), C_{t+1} = mask ? M : X_t, from
+    C_0 = mask ? M : 0.  on_iter(t, X_t) is called after every reconstruction.  Returns X_{iters-1}."""
+    import torch
+
+    Ct = masked_merge(ctx, M, mask, torch.zeros_like(M), stream=stream)
+    X = None
+    for t in range(iters):
+        X, _, _ = cur_reconstruct(ctx, Ct, rows, cols, method, tol, max_iter, stop, precision, stream)
+        if on_iter is not None:
+            on_iter(t, X)
+        masked_merge(ctx, M, mask, X, out=Ct, stream=stream)
+    return X
 
 
 def features(ctx: Context, A, power_steps=0, stream=None):

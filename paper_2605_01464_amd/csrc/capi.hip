@@ -3,6 +3,7 @@
 #include <string>
 
 #include "../../include/qpinv.h"
+#include "apps.hpp"
 #include "aux.hpp"
 #include "batched.hpp"
 #include "controller.hpp"
@@ -298,6 +299,49 @@ int qpinv_x0(qpinv_ctx* c, const qpinv_qmat* A, double alpha, qpinv_qmat* X, voi
       qp::x0_scaled_adjoint<double, float>(Am.v, Am.rows, Am.cols, alpha, Xm.v, s);
     else
       qp::x0_scaled_adjoint<double, double>(Am.v, Am.rows, Am.cols, alpha, Xm.v, s);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_submatrix(qpinv_ctx* c, const qpinv_qmat* A, const int* rows, int nrows, const int* cols, int ncols,
+                    qpinv_qmat* B, void* hip_stream) {
+  return guarded([&]() {
+    ctx_of(c);
+    qp::validate(A, "A");
+    qp::validate(B, "B");
+    if (nrows < 0 || ncols < 0) throw qp::Error(QPINV_EINVAL, "submatrix: negative index count");
+    if ((!rows && nrows != A->rows) || (!cols && ncols != A->cols))
+      throw qp::Error(QPINV_EINVAL, "submatrix: a null index set selects all rows / columns");
+    if (B->rows != nrows || B->cols != ncols) throw qp::Error(QPINV_EINVAL, "submatrix: B must be nrows x ncols");
+    if (A->dtype != B->dtype) throw qp::Error(QPINV_EINVAL, "submatrix: A and B must share the dtype");
+    const qp::Mat Am = qp::from_abi(*A), Bm = qp::from_abi(*B);
+    hipStream_t s = stream_of(hip_stream);
+    if (Am.dtype == QPINV_F32)
+      qp::submatrix<float>(Am.v, Am.rows, Am.cols, rows, nrows, cols, ncols, Bm.v, s);
+    else
+      qp::submatrix<double>(Am.v, Am.rows, Am.cols, rows, nrows, cols, ncols, Bm.v, s);
+    return QPINV_OK;
+  });
+}
+
+int qpinv_masked_merge(qpinv_ctx* c, const qpinv_qmat* M, const unsigned char* mask, int64_t mask_ld,
+                       const qpinv_qmat* X, qpinv_qmat* Y, void* hip_stream) {
+  return guarded([&]() {
+    ctx_of(c);
+    qp::validate(M, "M");
+    qp::validate(X, "X");
+    qp::validate(Y, "Y");
+    if (M->rows != X->rows || M->cols != X->cols || Y->rows != X->rows || Y->cols != X->cols)
+      throw qp::Error(QPINV_EINVAL, "masked_merge: M, X and Y must have one shape");
+    if (M->dtype != X->dtype || Y->dtype != X->dtype) throw qp::Error(QPINV_EINVAL, "masked_merge: one dtype");
+    if (!mask && X->rows > 0 && X->cols > 0) throw qp::Error(QPINV_EINVAL, "masked_merge: null mask");
+    if (mask_ld < X->cols) throw qp::Error(QPINV_EINVAL, "masked_merge: mask_ld < cols");
+    const qp::Mat Mm = qp::from_abi(*M), Xm = qp::from_abi(*X), Ym = qp::from_abi(*Y);
+    hipStream_t s = stream_of(hip_stream);
+    if (Xm.dtype == QPINV_F32)
+      qp::masked_merge<float>(Mm.v, mask, mask_ld, Xm.v, Ym.v, Xm.rows, Xm.cols, s);
+    else
+      qp::masked_merge<double>(Mm.v, mask, mask_ld, Xm.v, Ym.v, Xm.rows, Xm.cols, s);
     return QPINV_OK;
   });
 }

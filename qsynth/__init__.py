@@ -30,7 +30,7 @@ __all__ = [
     "structured_spectral", "structured_pinv", "mp_quantiles",
     "c1_instance", "c2_instance", "c3_instance", "c4_sizes", "c4_instance",
     "c5_spectrum", "c5_sample", "small_spectral_instance",
-    "lorenz_trajectory", "lorenz_filter_instance", "LORENZ_STEPS",
+    "lorenz_trajectory", "lorenz_filter_instance", "LORENZ_STEPS", "cur_image_instance",
 ]
 
 
@@ -362,3 +362,40 @@ def lorenz_filter_instance(dt: float, T: float = 40.0, tau: float = 1.0, noise: 
     X = np.ascontiguousarray(x[:, p + i[:, None] - i[None, :]])
     s = np.ascontiguousarray(ref[:, p:2 * p + 1, None])
     return {"X": X, "s": s, "x": x, "ref": ref, "p": p, "delay": d, "dt": dt, "T": T}
+
+
+# ----------------------------------------------------------------------------------------------
+# CUR image completion workload (Section 5.1) on a synthetic colour image (the paper's Kodak image is
+# not available): pure-quaternion pixels (0, R, G, B), a random mask of observed pixels and the row /
+# column index sets of the CUR factors
+# ----------------------------------------------------------------------------------------------
+def cur_image_instance(m: int = 512, n: int = 768, terms: int = 40, texture: float = 0.02, missing: float = 0.7,
+                       rank: int = 60, seed: int = 600) -> dict:
+    """Image = 0.5 + sum of `terms` separable smooth patterns f_k(y) g_k(x) with random colour weights
+    (each f, g a sum of 3 sinusoids of random low frequency and phase), scaled to a 0.35 amplitude per
+    channel, plus iid N(0, texture^2) per channel.  Mask: each pixel observed with probability
+    1 - missing.  rows / cols: `rank` distinct indices each, uniform, sorted.
+    Returns image (4, m, n) with plane 0 zero, mask (m, n) uint8, rows, cols (int32)."""
+    rng = np.random.default_rng(seed)
+    y = np.linspace(0.0, 1.0, m)[:, None]
+    x = np.linspace(0.0, 1.0, n)[None, :]
+
+    def smooth(t, k):
+        f = np.zeros_like(t)
+        for _ in range(3):
+            f = f + rng.standard_normal() * np.sin(2.0 * np.pi * (rng.uniform(0.2, 1.0 + 0.25 * k) * t + rng.uniform()))
+        return f
+
+    img = np.zeros((4, m, n))
+    for k in range(terms):
+        pat = smooth(y, k) * smooth(x, k)
+        w = rng.standard_normal(3) / (1.0 + k)
+        for c in range(3):
+            img[1 + c] += w[c] * pat
+    for c in range(3):
+        img[1 + c] *= 0.35 / max(np.abs(img[1 + c]).max(), 1e-12)
+    img[1:] += 0.5 + texture * rng.standard_normal((3, m, n))
+    mask = (rng.uniform(size=(m, n)) >= missing).astype(np.uint8)
+    rows = np.sort(rng.choice(m, size=rank, replace=False)).astype(np.int32)
+    cols = np.sort(rng.choice(n, size=rank, replace=False)).astype(np.int32)
+    return {"image": img, "mask": mask, "rows": rows, "cols": cols}
