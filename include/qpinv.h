@@ -231,6 +231,28 @@ int qpinv_x0(qpinv_ctx* ctx, const qpinv_qmat* A, double alpha, qpinv_qmat* X, v
 int qpinv_submatrix(qpinv_ctx* ctx, const qpinv_qmat* A, const int* rows, int nrows, const int* cols, int ncols,
                     qpinv_qmat* B, void* hip_stream);
 
+/* Global quaternion Krylov solve of A X = B (Section 3.5 and Section 4, Example 4: Gl-QFOM and
+ * Gl-QGMRES, optionally with a left preconditioner M such as a QSAI iterate: M A X = M B).
+ *   method      QPINV_KRYLOV_FOM or QPINV_KRYLOV_GMRES; the basis is orthonormal in
+ *               <X, Y> = Re tr(X^H Y) and never restarted (max_iter + 1 basis matrices of device memory).
+ *   A, M        n x n (M may be NULL); B and X n x m; all FP64.  X holds X_0 on entry and the solution on
+ *               return, and must be contiguous (ld = cols, plane_stride = rows * cols).
+ *   tol         stop when RR = ||B - A X_j||_F / ||B - A X_0||_F <= tol (Example 4's test).  The method
+ *               tracks the iterated system's ||M (B - A X_j)||_F / ||M (B - A X_0)||_F (M = I when NULL;
+ *               GMRES: the rotated right-hand side, FOM: that norm over the last rotation's cosine);
+ *               with M, RR itself is evaluated at every step once the tracked value is <= tol.
+ *   iters, rr   steps taken and the tracked relative residual at the last step; true_rr = RR of the
+ *               returned X; history[j] = tracked value after step j (host, history_cap entries; may be
+ *               NULL with history_cap 0).  Any of iters, rr, true_rr may be NULL.
+ * The call synchronises the stream (one host transfer of the new Hessenberg column per step).
+ * Returns QPINV_OK, QPINV_ENOTCONVERGED (max_iter steps without reaching tol; X is still the step's
+ * solution), EINVAL, ENOMEM, EHIP. */
+#define QPINV_KRYLOV_FOM 0
+#define QPINV_KRYLOV_GMRES 1
+int qpinv_gl_krylov(qpinv_ctx* ctx, int method, const qpinv_qmat* A, const qpinv_qmat* B, const qpinv_qmat* M,
+                    qpinv_qmat* X, double tol, int max_iter, int* iters, double* rr, double* true_rr, double* history,
+                    int history_cap, void* hip_stream);
+
 /* Masked merge of the impute-reconstruct loop (Section 5.1): Y = Omega (.) M + (1 - Omega) (.) X for all
  * four planes, Omega given as a DEVICE byte array (rows x cols, row stride mask_ld; nonzero = observed).
  * M, X and Y share one shape and dtype; Y may be M or X itself.  Errors: EINVAL. */

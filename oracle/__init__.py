@@ -18,8 +18,9 @@ It is written to be plain and checkable against the paper by eye:
 * ``mlp``     -- float64 forward/backward of the scaling network, for gradient checks.
 * ``filtering`` -- the quaternion filter design of Section 5.2 (h = X^dagger s, s_hat = X h, eps).
 * ``cur``     -- the CUR approximation and impute-reconstruct completion of Section 5.1.
+* ``krylov``  -- global quaternion FOM / GMRES (Section 3.5, Example 4), plain and preconditioned.
 
 Every function cites the passage it follows.  Functions whose result no independent pin checks are
 marked "parity unpinned" in their docstring.
 """
-from . import quat, methods, filtering, cur  # noqa: F401
+from . import quat, methods, filtering, cur, krylov  # noqa: F401

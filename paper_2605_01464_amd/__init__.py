@@ -82,6 +82,7 @@ def _load() -> ctypes.CDLL:
         "qpinv_x0": (I, [P, QP, D, QP, P]),
         "qpinv_submatrix": (I, [P, QP, P, I, P, I, QP, P]),
         "qpinv_masked_merge": (I, [P, QP, P, I64, QP, QP, P]),
+        "qpinv_gl_krylov": (I, [P, I, QP, QP, QP, QP, D, I, ctypes.POINTER(I), DP, DP, DP, I, P]),
         "qpinv_features": (I, [P, QP, I, DP, P]),
         "qpinv_autotune": (I, [P, I, I64, I64, I64, DP, P]),
         "qpinv_num_tile_configs": (I, [I]),
@@ -225,6 +226,16 @@ def qpinv_submatrix(ctx, A, rows, nrows, cols, ncols, B, stream=None) -> int:
 def qpinv_masked_merge(ctx, M, mask, mask_ld, X, Y, stream=None) -> int:
     return _lib.qpinv_masked_merge(ctx, ctypes.byref(qmat(M)), _ptr(mask), int(mask_ld), ctypes.byref(qmat(X)),
                                    ctypes.byref(qmat(Y)), _stream(stream))
+
+
+def qpinv_gl_krylov(ctx, method, A, B, M, X, tol, max_iter, history_cap=0, stream=None):
+    iters, rr, trr = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    hist = (ctypes.c_double * max(history_cap, 1))()
+    st = _lib.qpinv_gl_krylov(ctx, int(method), ctypes.byref(qmat(A)), ctypes.byref(qmat(B)),
+                              ctypes.byref(qmat(M)) if M is not None else None, ctypes.byref(qmat(X)), float(tol),
+                              int(max_iter), ctypes.byref(iters), ctypes.byref(rr), ctypes.byref(trr),
+                              hist if history_cap > 0 else None, int(history_cap), _stream(stream))
+    return st, iters.value, rr.value, trr.value, list(hist[:min(iters.value, history_cap)])
 
 
 def qpinv_features(ctx, A, power_steps=0, stream=None):
@@ -447,6 +458,24 @@ def filter_design(ctx: Context, X, s, method="qsai", order=None, tol=1e-13, max_
     h = qgemm(ctx, Xp, s)
     s_hat = qgemm(ctx, X, h)
     return h, s_hat, info
+
+
+KRYLOV = {"fom": 0, "gmres": 1}
+
+
+def gl_krylov(ctx: Context, A, B, method="gmres", M=None, X0=None, tol=1e-6, max_iter=3000, history=False,
+              stream=None):
+    """Global quaternion FOM / GMRES for A X = B (FP64), left-preconditioned by M when given.  Returns
+    (X, info) with info = {status, iters, rr, true_rr, history}."""
+    import torch
+
+    X = torch.zeros((4, A.shape[2], B.shape[2]), dtype=torch.float64, device=A.device) if X0 is None else \
+        X0.clone().contiguous()
+    st, it, rr, trr, hist = qpinv_gl_krylov(ctx.handle, KRYLOV[method], A, B, M, X, tol, max_iter,
+                                            max_iter if history else 0, stream)
+    if st not in (OK, ENOTCONVERGED):
+        _err(st, "qpinv_gl_krylov")
+    return X, {"status": st, "iters": it, "rr": rr, "true_rr": trr, "history": hist}
 
 
 def submatrix(ctx: Context, A, rows=None, cols=None, out=None, stream=None):

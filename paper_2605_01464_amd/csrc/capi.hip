@@ -7,6 +7,7 @@
 #include "aux.hpp"
 #include "batched.hpp"
 #include "controller.hpp"
+#include "krylov.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
 
@@ -343,6 +344,43 @@ int qpinv_masked_merge(qpinv_ctx* c, const qpinv_qmat* M, const unsigned char* m
     else
       qp::masked_merge<double>(Mm.v, mask, mask_ld, Xm.v, Ym.v, Xm.rows, Xm.cols, s);
     return QPINV_OK;
+  });
+}
+
+int qpinv_gl_krylov(qpinv_ctx* c, int method, const qpinv_qmat* A, const qpinv_qmat* B, const qpinv_qmat* M,
+                    qpinv_qmat* X, double tol, int max_iter, int* iters, double* rr, double* true_rr, double* history,
+                    int history_cap, void* hip_stream) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    if (method != QPINV_KRYLOV_FOM && method != QPINV_KRYLOV_GMRES) throw qp::Error(QPINV_EINVAL, "krylov: method");
+    qp::validate(A, "A");
+    qp::validate(B, "B");
+    qp::validate(X, "X");
+    if (M) qp::validate(M, "M");
+    if (A->rows != A->cols || B->rows != A->rows || X->rows != A->cols || X->cols != B->cols ||
+        (M && (M->rows != A->rows || M->cols != A->rows)))
+      throw qp::Error(QPINV_EINVAL, "krylov: A n x n, B and X n x m, M n x n");
+    if (A->dtype != QPINV_F64 || B->dtype != QPINV_F64 || X->dtype != QPINV_F64 || (M && M->dtype != QPINV_F64))
+      throw qp::Error(QPINV_EINVAL, "krylov: FP64 matrices");
+    if (X->cols > 1 && X->ld != X->cols) throw qp::Error(QPINV_EINVAL, "krylov: X must have ld = cols");
+    if (X->plane_stride != X->rows * X->cols) throw qp::Error(QPINV_EINVAL, "krylov: X planes must be contiguous");
+    if (max_iter < 1 || !(tol >= 0.0)) throw qp::Error(QPINV_EINVAL, "krylov: max_iter >= 1, tol >= 0");
+    if (history_cap < 0 || (history_cap > 0 && !history)) throw qp::Error(QPINV_EINVAL, "krylov: history");
+    if (A->rows == 0 || B->cols == 0) {
+      if (iters) *iters = 0;
+      if (rr) *rr = 0.0;
+      if (true_rr) *true_rr = 0.0;
+      return QPINV_OK;
+    }
+    const qp::Mat Am = qp::from_abi(*A), Bm = qp::from_abi(*B), Xm = qp::from_abi(*X);
+    qp::Mat Mm;
+    if (M) Mm = qp::from_abi(*M);
+    const qp::KrylovResult r = qp::gl_krylov(cx, method, Am, Bm, M ? &Mm : nullptr, Xm, tol, max_iter, history,
+                                             history_cap, stream_of(hip_stream));
+    if (iters) *iters = r.iters;
+    if (rr) *rr = r.rr;
+    if (true_rr) *true_rr = r.true_rr;
+    return r.status;
   });
 }
 

@@ -30,7 +30,7 @@ __all__ = [
     "structured_spectral", "structured_pinv", "mp_quantiles",
     "c1_instance", "c2_instance", "c3_instance", "c4_sizes", "c4_instance",
     "c5_spectrum", "c5_sample", "small_spectral_instance",
-    "lorenz_trajectory", "lorenz_filter_instance", "LORENZ_STEPS", "cur_image_instance",
+    "lorenz_trajectory", "lorenz_filter_instance", "LORENZ_STEPS", "cur_image_instance", "krylov_instance",
 ]
 
 
@@ -399,3 +399,36 @@ def cur_image_instance(m: int = 512, n: int = 768, terms: int = 40, texture: flo
     rows = np.sort(rng.choice(m, size=rank, replace=False)).astype(np.int32)
     cols = np.sort(rng.choice(n, size=rank, replace=False)).astype(np.int32)
     return {"image": img, "mask": mask, "rows": rows, "cols": cols}
+
+
+# ----------------------------------------------------------------------------------------------
+# Preconditioned Krylov workload (Section 4, Example 4): A = A_s (1 - i + 2 j + 1.5 k) with a real
+# nonsymmetric A_s standing in for the 238 x 238 Matrix-Market matrix the paper uses (not available)
+# ----------------------------------------------------------------------------------------------
+def krylov_instance(m: int, grid=(14, 17), contrast: float = 2.0, convection: float = 0.5, shift: float = 1e-3,
+                    seed: int = 700) -> dict:
+    """A_s: a five-point finite-volume operator on a grid[0] x grid[1] mesh (n = 238 by default, the
+    size of the paper's matrix) with log-normal transmissibilities exp(contrast N(0,1)) on the mesh
+    edges, a skew (convective) part convection * t * N(0,1) on the same edges, and a diagonal
+    accumulation term shift * mean(t).  The quaternion coefficient matrix follows Example 4:
+    A^(x) = -A_s, A^(y) = 2 A_s, A^(z) = 1.5 A_s.  B: n x m, every plane iid uniform [0, 1)."""
+    rng = np.random.default_rng(seed)
+    nx, ny = grid
+    n = nx * ny
+    As = np.zeros((n, n))
+    ts = []
+    for i in range(nx):
+        for j in range(ny):
+            a = i * ny + j
+            for b in ([a + ny] if i + 1 < nx else []) + ([a + 1] if j + 1 < ny else []):
+                t = float(np.exp(contrast * rng.standard_normal()))
+                u = convection * t * float(rng.standard_normal())
+                ts.append(t)
+                As[a, a] += t
+                As[b, b] += t
+                As[a, b] += -t + u
+                As[b, a] += -t - u
+    As += shift * float(np.mean(ts)) * np.eye(n)
+    A = np.stack([As, -As, 2.0 * As, 1.5 * As])
+    B = rng.uniform(size=(4, n, m))
+    return {"A": A, "B": B, "As": As}
