@@ -100,6 +100,95 @@ def measured_traffic(config_name):
     return None
 
 
+def section_lorenz(q, ctx, torch):
+    import qsynth
+
+    # filter design of Section 5.2 on the delayed noisy Lorenz record [0, 40] (tau = 1, noise std 1):
+    # square Toeplitz systems of 401..2001 unknowns, FP64 pseudoinverse + both products on the GPU
+    res = {}
+    for dt in qsynth.LORENZ_STEPS:
+        d = qsynth.lorenz_filter_instance(dt)
+        Xd = torch.from_numpy(d["X"]).cuda()
+        sd = torch.from_numpy(d["s"]).cuda()
+        row = {"n": int(d["p"] + 1)}
+        for meth in ("qsai", "qhpi19"):
+            q.filter_design(ctx, Xd, sd, method=meth)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(3):
+                t = time.perf_counter()
+                h, s_hat, inf_f = q.filter_design(ctx, Xd, sd, method=meth)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t)
+            eps = float(torch.linalg.vector_norm(s_hat - sd) / torch.linalg.vector_norm(sd))
+            row[meth] = {"ms": 1e3 * float(np.median(times)), "iters": inf_f["iters"], "eps": eps}
+        res[f"dt_{dt}"] = row
+        del Xd, sd
+    return {"workload": "Lorenz (sigma 10, delta 8/3, gamma 28, x0 [1,1,1]) on [0,40], delay 1, imaginary noise "
+                        "N(0,1), (p+1)x(p+1) Toeplitz X, h = X^+ s, FP64, guarded stop tol 1e-13", "results": res}
+
+
+def section_cur(q, ctx, torch):
+    import qsynth
+
+    # CUR image completion of Section 5.1 on a synthetic 512 x 768 colour image (70% of pixels
+    # missing, rank-60 factors, 25 impute-reconstruct iterations), every step on the GPU
+    def psnr_db(X, ref):  # over the three colour planes, peak 1
+        return float(10.0 * np.log10(1.0 / np.mean((X[1:] - ref[1:]) ** 2)))
+
+    d = qsynth.cur_image_instance()
+    res = {"masked_psnr_db": psnr_db(d["image"] * d["mask"][None], d["image"])}
+    mask_d = torch.from_numpy(d["mask"]).cuda()
+    rows_d = torch.from_numpy(d["rows"]).cuda()
+    cols_d = torch.from_numpy(d["cols"]).cuda()
+    for prec in ("f32", "f64"):
+        Md = torch.from_numpy(d["image"]).to(torch.float32 if prec == "f32" else torch.float64).cuda()
+        for meth in ("qhpi19", "qsai"):
+            kw = dict(iters=25, method=meth, tol=1e-6 if prec == "f32" else 1e-12)
+            q.cur_complete(ctx, Md, mask_d, rows_d, cols_d, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            X = q.cur_complete(ctx, Md, mask_d, rows_d, cols_d, **kw)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t
+            res[f"{meth}_{prec}"] = {"total_ms": 1e3 * dt_s, "ms_per_iteration": 1e3 * dt_s / 25,
+                                     "psnr_db": psnr_db(X.double().cpu().numpy(), d["image"])}
+    return {"workload": "synthetic 512x768 pure-quaternion colour image (40 smooth separable terms + N(0, 0.02^2) "
+                        "texture), 70% of pixels missing, rank-60 row/column sets, 25 impute-reconstruct iterations, "
+                        "U = C^+ A R^+", "results": res}
+
+
+def section_krylov(q, ctx, torch):
+    import qsynth
+
+    # Example 4: global quaternion FOM / GMRES on A X = B (n = 238 stand-in operator, m = 3..12 right-hand
+    # sides), plain and left-preconditioned by 4 QSAI updates; RR <= 1e-6; preconditioned times include
+    # building M
+    res = {}
+    for m_rhs in (3, 6, 9, 12):
+        d = qsynth.krylov_instance(m_rhs)
+        Ad = torch.from_numpy(d["A"]).cuda()
+        Bd = torch.from_numpy(d["B"]).cuda()
+        row = {}
+        for name, meth, pre in (("gl_qfom", "fom", False), ("gl_qgmres", "gmres", False),
+                                ("pre_gl_qfom", "fom", True), ("pre_gl_qgmres", "gmres", True)):
+            for rep in range(2):  # first pass warms the workspaces
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                Md = None
+                if pre:
+                    Md, _ = q.solve(ctx, Ad, "qsai", tol=0.0, max_iter=4, stop="dx_abs", precision="f64")
+                _, inf_k = q.gl_krylov(ctx, Ad, Bd, method=meth, M=Md, tol=1e-6, max_iter=3000)
+                torch.cuda.synchronize()
+                dt_s = time.perf_counter() - t
+            row[name] = {"iters": inf_k["iters"], "ms": 1e3 * dt_s, "rr": inf_k["true_rr"],
+                         "status": inf_k["status"]}
+        res[f"m_{m_rhs}"] = row
+    return {"workload": "A = A_s (1 - i + 2j + 1.5k), A_s a 238x238 nonsymmetric five-point operator (log-normal "
+                        "transmissibilities, skew part), B uniform [0,1), X_0 = 0, RR <= 1e-6, QSAI preconditioner of "
+                        "4 updates, FP64", "results": res}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,87 +456,11 @@ def main() -> int:
         del ev
 
     if not args.no_lorenz:
-        # filter design of Section 5.2 on the delayed noisy Lorenz record [0, 40] (tau = 1, noise std 1):
-        # square Toeplitz systems of 401..2001 unknowns, FP64 pseudoinverse + both products on the GPU
-        res = {}
-        for dt in qsynth.LORENZ_STEPS:
-            d = qsynth.lorenz_filter_instance(dt)
-            Xd = torch.from_numpy(d["X"]).cuda()
-            sd = torch.from_numpy(d["s"]).cuda()
-            row = {"n": int(d["p"] + 1)}
-            for meth in ("qsai", "qhpi19"):
-                q.filter_design(ctx, Xd, sd, method=meth)
-                torch.cuda.synchronize()
-                times = []
-                for _ in range(3):
-                    t = time.perf_counter()
-                    h, s_hat, inf_f = q.filter_design(ctx, Xd, sd, method=meth)
-                    torch.cuda.synchronize()
-                    times.append(time.perf_counter() - t)
-                eps = float(torch.linalg.vector_norm(s_hat - sd) / torch.linalg.vector_norm(sd))
-                row[meth] = {"ms": 1e3 * float(np.median(times)), "iters": inf_f["iters"], "eps": eps}
-            res[f"dt_{dt}"] = row
-            del Xd, sd
-        out["lorenz_filtering"] = {"workload": "Lorenz (sigma 10, delta 8/3, gamma 28, x0 [1,1,1]) on [0,40], delay 1, "
-                                               "imaginary noise N(0,1), (p+1)x(p+1) Toeplitz X, h = X^+ s, FP64, "
-                                               "guarded stop tol 1e-13", "results": res}
-
+        out["lorenz_filtering"] = section_lorenz(q, ctx, torch)
     if not args.no_cur:
-        # CUR image completion of Section 5.1 on a synthetic 512 x 768 colour image (70% of pixels
-        # missing, rank-60 factors, 25 impute-reconstruct iterations), every step on the GPU
-        def psnr_db(X, ref):  # over the three colour planes, peak 1
-            return float(10.0 * np.log10(1.0 / np.mean((X[1:] - ref[1:]) ** 2)))
-
-        d = qsynth.cur_image_instance()
-        res = {"masked_psnr_db": psnr_db(d["image"] * d["mask"][None], d["image"])}
-        mask_d = torch.from_numpy(d["mask"]).cuda()
-        rows_d = torch.from_numpy(d["rows"]).cuda()
-        cols_d = torch.from_numpy(d["cols"]).cuda()
-        for prec in ("f32", "f64"):
-            Md = torch.from_numpy(d["image"]).to(torch.float32 if prec == "f32" else torch.float64).cuda()
-            for meth in ("qhpi19", "qsai"):
-                kw = dict(iters=25, method=meth, tol=1e-6 if prec == "f32" else 1e-12)
-                q.cur_complete(ctx, Md, mask_d, rows_d, cols_d, **kw)
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                X = q.cur_complete(ctx, Md, mask_d, rows_d, cols_d, **kw)
-                torch.cuda.synchronize()
-                dt_s = time.perf_counter() - t
-                res[f"{meth}_{prec}"] = {"total_ms": 1e3 * dt_s, "ms_per_iteration": 1e3 * dt_s / 25,
-                                         "psnr_db": psnr_db(X.double().cpu().numpy(), d["image"])}
-        out["cur_completion"] = {"workload": "synthetic 512x768 pure-quaternion colour image (40 smooth separable "
-                                             "terms + N(0, 0.02^2) texture), 70% of pixels missing, rank-60 row/column "
-                                             "sets, 25 impute-reconstruct iterations, U = C^+ A R^+",
-                                 "results": res}
-
+        out["cur_completion"] = section_cur(q, ctx, torch)
     if not args.no_krylov:
-        # Example 4: global quaternion FOM / GMRES on A X = B (n = 238 stand-in operator, m = 3..12 right-hand
-        # sides), plain and left-preconditioned by 4 QSAI updates; RR <= 1e-6; preconditioned times include
-        # building M
-        res = {}
-        for m_rhs in (3, 6, 9, 12):
-            d = qsynth.krylov_instance(m_rhs)
-            Ad = torch.from_numpy(d["A"]).cuda()
-            Bd = torch.from_numpy(d["B"]).cuda()
-            row = {}
-            for name, meth, pre in (("gl_qfom", "fom", False), ("gl_qgmres", "gmres", False),
-                                    ("pre_gl_qfom", "fom", True), ("pre_gl_qgmres", "gmres", True)):
-                for rep in range(2):  # first pass warms the workspaces
-                    torch.cuda.synchronize()
-                    t = time.perf_counter()
-                    Md = None
-                    if pre:
-                        Md, _ = q.solve(ctx, Ad, "qsai", tol=0.0, max_iter=4, stop="dx_abs", precision="f64")
-                    _, inf_k = q.gl_krylov(ctx, Ad, Bd, method=meth, M=Md, tol=1e-6, max_iter=3000)
-                    torch.cuda.synchronize()
-                    dt_s = time.perf_counter() - t
-                row[name] = {"iters": inf_k["iters"], "ms": 1e3 * dt_s, "rr": inf_k["true_rr"],
-                             "status": inf_k["status"]}
-            res[f"m_{m_rhs}"] = row
-        out["krylov_preconditioning"] = {"workload": "A = A_s (1 - i + 2j + 1.5k), A_s a 238x238 nonsymmetric "
-                                                     "five-point operator (log-normal transmissibilities, skew part), "
-                                                     "B uniform [0,1), X_0 = 0, RR <= 1e-6, QSAI preconditioner of 4 "
-                                                     "updates, FP64", "results": res}
+        out["krylov_preconditioning"] = section_krylov(q, ctx, torch)
 
     if not args.no_cpu_baseline:
         # FP64 oracle on the host: one iteration of the same method on the same input (left side),
