@@ -158,3 +158,23 @@ def test_error_paths(qctx):
     Z = torch.zeros((4, 6, 4), dtype=torch.float64, device="cuda")
     Xz, info = q.solve(qctx, Z, "qhpi19", precision="f64")
     assert float(Xz.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("method", ["qhpi19", "qsai", "ns", "qrapid"])
+def test_degenerate_shapes(qctx, method):
+    """1 x 1, column and row vectors (closed form a^H / ||a||^2, Section 2), and empty matrices."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    rng = np.random.default_rng(19)
+    for shape in ((1, 1), (9, 1), (1, 7)):
+        A = rng.standard_normal((4,) + shape)
+        X, info = q.solve(qctx, to_dev(A, "f64"), method, tol=1e-13, max_iter=200, stop="e1_rel", precision="f64")
+        ref = Q.qH(A) / np.sum(A * A)
+        assert info["status"] == q.OK, (shape, info)
+        assert Q.fro(to_np(X) - ref) <= 1e-12 * Q.fro(ref), shape
+    for shape in ((0, 5), (5, 0)):
+        A = torch.zeros((4,) + shape, dtype=torch.float64, device="cuda")
+        X, info = q.solve(qctx, A, method, precision="f64")
+        assert tuple(X.shape) == (4, shape[1], shape[0]) and info["status"] == q.OK
