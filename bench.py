@@ -364,10 +364,17 @@ def main() -> int:
         A3d = A3.double()
         X3 = torch.empty((4, A3.shape[2], A3.shape[1]), dtype=torch.float64, device="cuda")
         res = {}
-        for label, prec, Ain in (("mixed_bf16_f32_f64", "mixed", A3), ("plain_f32_f64finish", "f32_f64finish", A3),
-                                 ("plain_f64", "f64", A3d), ("mixed_bf16_f32_f64refined", "mixed", A3)):
-            ctx.set("f64_refined", 1 if label.endswith("refined") else 0)
-            for method in (("qhpi19",) if label.endswith("refined") else ("qhpi19", "qrapid")):
+        # default FP64 finish: Newton-Schulz updates with FP64 residual and sum around an FP32 product;
+        # "allfp64": every finish product in FP64; "samefinish": the solve's own method, all in FP64
+        # (the default ladder runs last, so X3 holds its QHPI19 result for the sampled-row check below)
+        for label, prec, Ain, refined, finish in (("plain_f32_f64finish", "f32_f64finish", A3, 1, 0),
+                                                  ("plain_f64", "f64", A3d, 1, 0),
+                                                  ("mixed_bf16_f32_f64allfp64", "mixed", A3, 0, 0),
+                                                  ("mixed_bf16_f32_f64samefinish", "mixed", A3, 0, -1),
+                                                  ("mixed_bf16_f32_f64", "mixed", A3, 1, 0)):
+            ctx.set("f64_refined", refined)
+            ctx.set("finish_method", finish)
+            for method in (("qhpi19",) if label.endswith(("allfp64", "samefinish")) else ("qrapid", "qhpi19")):
                 kw = dict(method=method, order=None, scaling="power", tol=1e-6, max_iter=100, stop="guarded",
                           precision=prec, X=X3)
                 q.solve(ctx, Ain, **kw)  # warm-up (and tile tuning)
@@ -381,7 +388,8 @@ def main() -> int:
                 res[f"{label}:{method}"] = {"pinv_per_s": 1.0 / dt, "ms": 1e3 * dt, "iters_bf16": inf3["iters_bf16"],
                                             "iters_f32": inf3["iters_f32"], "iters_f64": inf3["iters_f64"],
                                             "E_rel_fp64": Er}
-        ctx.set("f64_refined", 0)
+        ctx.set("f64_refined", 1)
+        ctx.set("finish_method", 0)
         out["mixed_vs_plain"] = {"workload": "4096x4096 quaternion, cond 1e3, geometric spectrum, unit-variance "
                                              "components (FP32 input), guarded stop tol 1e-6",
                                  "input_generation_s": t_g, "results": res}
@@ -487,8 +495,8 @@ def main() -> int:
         Xc = Q.pinv_from_factors(inst["U"], inst["s"], inst["V"])
         out["rel_err_vs_rank1024_pinv"] = float(np.linalg.norm(Xd - Xc) / np.linalg.norm(Xc))
         if mixed_inst is not None:
-            # sampled rows of the last mixed-section result (the ladder with the refined finish) vs the exact inverse of the
-            # FP32 input: relative residual of rows of A X - I, times the condition number
+            # sampled rows of the default ladder's QHPI19 result (the mixed section's last) vs the exact inverse of
+            # the FP32 input: relative residual of rows of A X - I, times the condition number
             A3h = mixed_inst["A"]
             X3h = X3.detach().cpu().numpy()
             rows = np.random.default_rng(5).choice(A3h.shape[1], 8, replace=False)

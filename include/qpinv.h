@@ -93,8 +93,9 @@ typedef enum {
   QPINV_PREC_F32 = 1,          /* every product in FP32 (MFMA f32, FP32 accumulate) */
   QPINV_PREC_F32_F64FINISH = 2,/* FP32 until its stop rule fires or the relative change d satisfies
                                   d <= 0.5 and d^p <= 1e-6 (the FP32 floor; p = convergence order),
-                                  then FP64 iterations until d <= tol, or d <= 0.5 and d^p <= tol,
-                                  or d rises, or option f64_finish_iters (default 2) FP64 updates */
+                                  then FP64 iterations (option finish_method, default Newton--Schulz)
+                                  until d <= tol, or d <= 0.5 and d^q <= tol (q >= 3, the finish method's
+                                  order), or d rises, or option f64_finish_iters (default 2) FP64 updates */
   QPINV_PREC_MIXED = 3         /* BF16 operands (FP32 accumulate) first; leave BF16 when ||R||_2
                                   (power estimate, option mixed_rnorm_steps) or ||R||_2^p drops below
                                   option mixed_switch (1e-2), or ||R||_2 < 0.9 fails to halve in one
@@ -137,10 +138,12 @@ typedef struct qpinv_ctx qpinv_ctx;
 int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
 
 /* Set a numeric option: side (qpinv_side), power_steps (>= 1), power_seed, autotune (0/1),
- * f64_finish_iters (1..4), f64_refined (0/1, default 0 = every finish product in FP64; 1: FP64
+ * f64_finish_iters (1..4), finish_method (method of the FP64 finish updates: QPINV_NS (default),
+ * QPINV_QSAI, QPINV_QHPI19, or -1 for the solve's own method), f64_refined (0/1, default 1: FP64
  * finish updates of NS, HPI, QSAI and QHPI19 form the residual R and the sum X + (T - I) X in FP64
- * and the polynomial T - I of R and its product with X in FP32 -- faster, but the correction then
- * carries FP32 rounding relative to |(T - I) X|, about u32 |R_f32 floor| |X|), mixed_switch (||R||_2
+ * and the polynomial T - I of R and its product with X in FP32, so the correction carries FP32
+ * rounding relative to |(T - I) X| -- for the default Newton-Schulz finish T - I = R, and the second
+ * update's correction is already at the FP64 level; 0: every finish product in FP64), mixed_switch (||R||_2
  * threshold, default 1e-2), mixed_rnorm_steps,
  * max_bf16_iters, gemm_timing (0/1), gemm_cfg_f64 / gemm_cfg_f32 / gemm_cfg_bf16 (tile configuration
  * index used for every product of that precision, -1 = tuned or heuristic choice), batched_cfg

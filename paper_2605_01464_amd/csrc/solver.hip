@@ -933,6 +933,13 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
 
   StopController ctl(stop, tol);
   const int p_order = convergence_order(method, order);
+  // FP64 finish updates: by default Newton-Schulz, the order-2 member of the family.  The finish starts
+  // from an iterate at the FP32 floor, where squaring the error reaches the FP64 tolerance in one or
+  // two updates of 2 products each, fewer products than one update of a higher order.
+  int fin_method = c.opt.finish_method >= 0 ? c.opt.finish_method : method;
+  int fin_order = c.opt.finish_method >= 0 ? 0 : order;
+  check_method(fin_method, fin_order);
+  const int p_finish = convergence_order(fin_method, fin_order);
   const double kF32Floor = 1e-6;  // relative error FP32 iterates cannot improve on
   std::vector<double> xnorm_hist(1, 0.0);  // ||X_j||_F by j (X_0 unknown = 0)
   int best_pair[2] = {-1, -1};             // buffer indices of X_{j*-1}, X_{j*}
@@ -971,11 +978,13 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     // the classical alpha (mu = 1) carries no more risk than the default; only a larger learned mu is checked
     const bool guard_R = learned && j == 0 && inf.mu_used > 1.0;
     const bool want_R = (p == P_BF16) || keep_R || guard_R;
-    const bool refined = has_finish && ph == phases.size() - 1 && c.opt.f64_refined && method != QPINV_QRAPID;
+    const bool in_finish = has_finish && ph == phases.size() - 1;
+    const int it_method = in_finish ? fin_method : method, it_order = in_finish ? fin_order : order;
+    const bool refined = in_finish && c.opt.f64_refined && it_method != QPINV_QRAPID;
     if (refined)
-      chain_refined(c, method, order, side, Adt, S->b[cur], S->b[nxt], red, s);
+      chain_refined(c, it_method, it_order, side, Adt, S->b[cur], S->b[nxt], red, s);
     else
-      chain(c, method, order, side, p, Adt, S->b[cur], S->b[nxt], red, s, want_R ? &R : nullptr);
+      chain(c, it_method, it_order, side, p, Adt, S->b[cur], S->b[nxt], red, s, want_R ? &R : nullptr);
     if (guard_R) {
       // Theorem 1: alpha is admissible iff every |1 - alpha sigma_i^2| < 1; R_0 = I - X_0 A (or I - A X_0)
       // has exactly these eigenvalues (and 1 on the null space), so ||R_0||_2 > 1 means divergence
@@ -1075,8 +1084,10 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
       const double d = xn > 0 ? d_abs / xn : 0.0;
       const int fin_it = inf.iters_f64;
       // in the asymptotic regime the next change is about d^p: once that is below tol the FP64 iterate
-      // just computed is converged and a confirming step is not needed
-      const bool predicted = d <= 0.5 && std::pow(d, (double)p_order) <= tol;
+      // just computed is converged and a confirming step is not needed.  Not for order 2: the error of a
+      // Newton-Schulz update is E A E, whose relative size carries a condition-number factor that d^2
+      // does not, so that finish stops on its measured change
+      const bool predicted = p_finish >= 3 && d <= 0.5 && std::pow(d, (double)p_finish) <= tol;
       if (d <= tol || predicted) {
         inf.stop_reason = QPINV_REASON_TOL;
         returned_buf = nxt;

@@ -30,7 +30,8 @@ struct Options {
   uint64_t power_seed = 0x5EED;
   int autotune = 0;
   int f64_finish_iters = 2;
-  int f64_refined = 0;  // 1: FP64 finish updates with FP64 residual and sum, FP32 polynomial (NS, HPI, QSAI, QHPI19)
+  int f64_refined = 1;  // 1: FP64 finish updates with FP64 residual and sum, FP32 polynomial (NS, HPI, QSAI, QHPI19)
+  int finish_method = QPINV_NS;  // method of the FP64 finish updates (-1: the solve's own method)
   double mixed_switch = 1e-2;
   int mixed_rnorm_steps = 6;
   int max_bf16_iters = 8;

@@ -51,7 +51,7 @@ def test_f64_finish_forms_vs_oracle(qctx, sq512, method, order):
                               precision="f32_f64finish", out_dtype=torch.float64, max_iter=200)
             out[refined] = (rel_fro(to_np(X), ref), info)
     finally:
-        qctx.set("f64_refined", 0)
+        qctx.set("f64_refined", 1)
     (e0, i0), (e1, i1) = out[0], out[1]
     assert (i0["iters_f32"], i0["iters_f64"]) == (i1["iters_f32"], i1["iters_f64"]), (i0, i1)
     assert 1 <= i1["iters_f64"] <= 2
@@ -102,3 +102,29 @@ def test_full_size_mixed_sampled_rows(qctx):
     s = inst["s"]
     assert res * (s[0] / s[-1]) <= 1e-6, (res, info)
     assert info["iters_bf16"] >= 1 and 1 <= info["iters_f64"] <= 2
+
+
+@pytest.mark.parametrize("precision", ["mixed", "f32_f64finish"])
+def test_newton_schulz_finish_vs_same_method(qctx, sq512, precision):
+    """The default FP64 finish (Newton-Schulz, 2 products per update) reaches the 1e-6 target like a finish
+    with the solve's own QHPI19 updates (7 products), with fewer product flops."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    A = sq512["A"]
+    ref = Q.pinv_svd(A)
+    out = {}
+    try:
+        for fm in (0, -1):
+            qctx.set("finish_method", fm)
+            X, info = q.solve(qctx, to_dev(A, "f32"), "qhpi19", scaling="power", tol=1e-6, stop="guarded",
+                              precision=precision, out_dtype=torch.float64, max_iter=200)
+            out[fm] = (rel_fro(to_np(X), ref), info)
+    finally:
+        qctx.set("finish_method", 0)
+    (e_ns, i_ns), (e_same, i_same) = out[0], out[-1]
+    assert i_ns["status"] == q.OK and i_same["status"] == q.OK
+    assert e_ns <= 1e-6 and e_same <= 1e-6, (e_ns, e_same)
+    assert 1 <= i_ns["iters_f64"] <= 2
+    assert i_ns["gemm_flops"] < i_same["gemm_flops"], (i_ns["gemm_flops"], i_same["gemm_flops"])
