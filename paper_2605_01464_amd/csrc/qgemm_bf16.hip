@@ -2,10 +2,10 @@
 // FP32 accumulation: the early, self-correcting iterations of the precision ladder.
 //
 // The operand planes stay FP32 in HBM; each workgroup rounds them to BF16 (round to nearest even)
-// while staging into LDS, so no BF16 copy of any matrix exists.  LDS holds A tiles as [plane][row][k]
-// and B tiles transposed as [plane][col][k], both k-contiguous, so that every lane reads its eight
-// consecutive k of a fragment with one 16-byte LDS load.  Lane layout (64 lanes, verified):
+// while staging into LDS, so no BF16 copy of any matrix exists.  Two forms: a single-buffered one
+// (small tiles) and a double-buffered one (below).  Fragment lane layout of the MFMA (64 lanes):
 //   A frag: row l%16, k = 8(l/16) .. 8(l/16)+7;  B frag: col l%16, same k;  D reg r: row 4(l/16)+r, col l%16.
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -26,6 +26,9 @@ __device__ __forceinline__ floatx4 mma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Single-buffered form.  LDS holds A tiles as [plane][row][k] and B tiles transposed as [plane][col][k],
+// both k-contiguous with 8 elements of row padding, so that every lane reads its eight consecutive k
+// of a fragment with one 16-byte LDS load.
 template <int BM, int BN, int WM, int WN>
 struct Bf16Cfg {
   static constexpr int BK = 32, BLK = 16, NR = 4;
@@ -214,6 +217,307 @@ __global__ void __launch_bounds__(64 * WM * WN) qgemm_bf16_kernel(GemmParams<flo
   store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
 }
 
+// ---------------------------------------------------------------------------------------------------
+// Double-buffered form.  Per K step (32) a workgroup fetches the FP32 A tile as 16-byte row chunks and
+// the FP32 B tile as 2 x 4 blocks (two 16-byte row loads, regrouped in registers to k-pairs of one
+// column), rounds to BF16 (packed converts) and writes the other LDS stage while the MFMAs read this
+// one: one barrier per K step.  The next stage's A tile is fetched during the first half of the MFMAs
+// and its B tile during the second half, so that only one of them is held in registers.
+//
+// LDS rows hold the 32 k of one row (A) or column (B) of one plane, 64 bytes, with the four 16-byte k
+// chunks of row r permuted by (r >> 1) & 3 so that the 8 lanes of one fragment read phase hit
+// distinct banks.  With 16-byte aligned operands (BUF) the loads are buffer loads over the four planes:
+// the per-tile part of each address is a lane offset and the per-step part (plane, k) a scalar
+// offset, so a K step spends no vector instructions on addresses.  Steps of partial tiles and the last
+// partial K step take a separate path: addresses clamped into the matrix (a row's ld extent is
+// readable), and what lies outside zeroed at the LDS store.  Accumulators go straight to the epilogue.
+template <int BM, int BN, int WM, int WN>
+struct Bf16DbCfg {
+  static constexpr int BK = 32;
+  static constexpr int NW = WM * WN, NT = 64 * NW;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int TM = WTM / 16, TN = WTN / 16;
+  static constexpr int JB = BN / 4;                // column blocks of a B tile
+  static constexpr int ACH = BM * BK / 4;          // 4-float chunks of one A plane tile
+  static constexpr int BBL = (BK / 2) * JB;        // 2 x 4 blocks of one B plane tile
+  static constexpr int NA = ACH / NT, NB = BBL / NT;
+  static constexpr int STAGE = 4 * (BM + BN) * BK;  // bf16 elements of one stage
+  static_assert(TM >= 2 && TN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile (two row halves)");
+  static_assert(ACH % NT == 0 && BBL % NT == 0 && NT % JB == 0, "whole chunks and blocks per thread");
+  static_assert(2 * STAGE * 2 <= 160 * 1024, "two stages fit the LDS");
+};
+
+// bf16 element offset of (LDS row r, 16-byte k chunk c) in the permuted layout
+__device__ __forceinline__ int db_off(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) << 3); }
+
+__device__ __forceinline__ floatx4 buf_load4(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+template <int BM, int BN, int WM, int WN, bool BUF>
+__device__ __forceinline__ void bf16_db_tile(const GemmParams<float>& P, int tm, int tn, __bf16* smem, double& s_d,
+                                             double& s_x) {
+  using C = Bf16DbCfg<BM, BN, WM, WN>;
+  constexpr int BK = C::BK, JB = C::JB;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w % WM, wn = w / WM;
+  const int lastk = (P.K - 1) & ~3, lastn = (P.N - 1) & ~3;
+  const bool full_mn = m0 + BM <= P.M && n0 + BN <= P.N;
+  // A chunks of this thread: rows tid / 8 + t NT / 8, k 4 (tid % 8) .. +3.  B blocks: columns
+  // 4 (tid % JB) .. +3, k rows 2 kb(t) and 2 kb(t) + 1 with kb(t) = tid / JB + t NT / JB.
+  const int kqa = tid & 7, jqb = tid % JB;
+  const int colb = min(n0 + 4 * jqb, lastn);
+  int rowa[C::NA];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t) rowa[t] = min(m0 + (tid + t * C::NT) / 8, P.M - 1);
+  auto kb = [&](int t) __attribute__((always_inline)) { return (tid + t * C::NT) / JB; };
+
+  // raw buffers over the four planes (extents below 2^31 bytes, checked by the launcher when BUF)
+  const __amdgpu_buffer_rsrc_t srcA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(P.A), (short)0, (int)((3 * P.psa + (int64_t)P.M * P.lda) * 4), 0x00020000);
+  const __amdgpu_buffer_rsrc_t srcB = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(P.B), (short)0, (int)((3 * P.psb + (int64_t)P.K * P.ldb) * 4), 0x00020000);
+  int offa[C::NA], offb[C::NB][2];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t) offa[t] = (int)(((int64_t)rowa[t] * P.lda + 4 * kqa) * 4);
+#pragma unroll
+  for (int t = 0; t < C::NB; ++t)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) offb[t][e] = (int)(((int64_t)(2 * kb(t) + e) * P.ldb + colb) * 4);
+
+  floatx4 acc[4][C::TM][C::TN];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) acc[p][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  floatx4 ra[4][C::NA], rb[4][C::NB][2];
+
+  // FAST: whole tile and whole K step (no clamping, no masking)
+  auto load_a = [&](int k0, auto fast) __attribute__((always_inline)) {
+    constexpr bool FAST = decltype(fast)::value;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NA; ++t) {
+        if constexpr (BUF && FAST) {
+          ra[q][t] = buf_load4(srcA, offa[t], (int)((q * P.psa + k0) * 4));
+        } else if constexpr (BUF) {
+          ra[q][t] = buf_load4(srcA, offa[t] + 4 * (min(k0 + 4 * kqa, lastk) - 4 * kqa), (int)(q * P.psa * 4));
+        } else {
+          const float* Ar = P.A + q * P.psa + (int64_t)rowa[t] * P.lda;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) ra[q][t][e] = gload(Ar, min(k0 + 4 * kqa + e, P.K - 1));
+        }
+      }
+  };
+  auto load_b = [&](int k0, auto fast) __attribute__((always_inline)) {
+    constexpr bool FAST = decltype(fast)::value;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NB; ++t)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int gk = min(k0 + 2 * kb(t) + e, P.K - 1);
+          if constexpr (BUF && FAST) {
+            rb[q][t][e] = buf_load4(srcB, offb[t][e], (int)((q * P.psb + (int64_t)k0 * P.ldb) * 4));
+          } else if constexpr (BUF) {
+            rb[q][t][e] = buf_load4(srcB, (int)(((int64_t)gk * P.ldb + colb) * 4), (int)(q * P.psb * 4));
+          } else {
+            const float* Bk = P.B + q * P.psb + (int64_t)gk * P.ldb;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rb[q][t][e][c] = gload(Bk, min(n0 + 4 * jqb + c, P.N - 1));
+          }
+        }
+  };
+  auto store_a = [&](__bf16* As, int k0, auto fast) __attribute__((always_inline)) {
+    constexpr bool FAST = decltype(fast)::value;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NA; ++t) {
+        const int i = (tid + t * C::NT) / 8;
+        floatx4 v = ra[q][t];
+        if constexpr (!FAST) {
+          const bool rok = m0 + i < P.M;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = (rok && k0 + 4 * kqa + e < P.K) ? v[e] : 0.f;
+        }
+        *reinterpret_cast<bf16x4*>(&As[db_off(q * BM + i, kqa >> 1) + (kqa & 1) * 4]) =
+            __builtin_convertvector(v, bf16x4);
+      }
+  };
+  auto store_b = [&](__bf16* As, int k0, auto fast) __attribute__((always_inline)) {
+    constexpr bool FAST = decltype(fast)::value;
+    __bf16* const Bs = As + 4 * BM * BK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NB; ++t) {
+        const int kk = 2 * kb(t);  // k within the step, even
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          floatx2 v = {rb[q][t][0][c], rb[q][t][1][c]};
+          if constexpr (!FAST) {
+            const bool cok = n0 + 4 * jqb + c < P.N;
+            v[0] = (cok && k0 + kk < P.K) ? v[0] : 0.f;
+            v[1] = (cok && k0 + kk + 1 < P.K) ? v[1] : 0.f;
+          }
+          *reinterpret_cast<bf16x2*>(&Bs[db_off(q * BN + 4 * jqb + c, kk >> 3) + (kk & 7)]) =
+              __builtin_convertvector(v, bf16x2);
+        }
+      }
+  };
+
+  const int fr = lane & 15, fc = lane >> 4;
+  bf16x8 b[C::TN][4];
+  auto frag_b = [&](const __bf16* As) __attribute__((always_inline)) {
+    const __bf16* const Bs = As + 4 * BM * BK;
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        b[j][q] = *reinterpret_cast<const bf16x8*>(&Bs[db_off(q * BN + wn * C::WTN + j * 16 + fr, fc)]);
+  };
+  // MFMAs of wave-tile rows i0 <= i < i1 (compile-time bounds after inlining)
+  auto compute = [&](const __bf16* As, int i0, int i1) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      bf16x8 a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        a[q] = *reinterpret_cast<const bf16x8*>(&As[db_off(q * BM + wm * C::WTM + i * 16 + fr, fc)]);
+      const bf16x8 na1 = neg_bf16x8(a[1]), na2 = neg_bf16x8(a[2]), na3 = neg_bf16x8(a[3]);
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        // Hamilton product: acc_p += sum_q sign(p, q) a_q b_{r(p, q)}, the four planes interleaved
+        acc[0][i][j] = mma_bf16(a[0], b[j][0], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(a[0], b[j][1], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(a[0], b[j][2], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(a[0], b[j][3], acc[3][i][j]);
+        acc[0][i][j] = mma_bf16(na1, b[j][1], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(a[1], b[j][0], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(na1, b[j][3], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(a[1], b[j][2], acc[3][i][j]);
+        acc[0][i][j] = mma_bf16(na2, b[j][2], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(a[2], b[j][3], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(a[2], b[j][0], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(na2, b[j][1], acc[3][i][j]);
+        acc[0][i][j] = mma_bf16(na3, b[j][3], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(na3, b[j][2], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(a[3], b[j][1], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(a[3], b[j][0], acc[3][i][j]);
+      }
+    }
+  };
+
+  constexpr int IH = C::TM / 2;
+  // The whole K loop, fast (whole tile, K a multiple of the step: no clamping, no masking) or not.
+  // The last step is peeled so that every loop step stages the next tile unconditionally.
+  auto run = [&](auto fast) __attribute__((always_inline)) {
+    const int nk = (P.K + BK - 1) / BK;
+    load_a(0, fast);
+    load_b(0, fast);
+    store_a(smem, 0, fast);
+    store_b(smem, 0, fast);
+    __syncthreads();
+    for (int kt = 0; kt + 1 < nk; ++kt) {
+      __bf16* const cur = smem + (kt & 1) * C::STAGE;
+      __bf16* const nxt = smem + ((kt + 1) & 1) * C::STAGE;
+      const int kn = (kt + 1) * BK;
+      frag_b(cur);
+      load_a(kn, fast);
+      compute(cur, 0, IH);
+      store_a(nxt, kn, fast);
+      load_b(kn, fast);
+      compute(cur, IH, C::TM);
+      store_b(nxt, kn, fast);
+      __syncthreads();
+    }
+    const __bf16* const last = smem + ((nk - 1) & 1) * C::STAGE;
+    frag_b(last);
+    compute(last, 0, C::TM);
+    __syncthreads();  // the next tile's first stage overwrites LDS
+  };
+  if (P.K > 0) {
+    if (full_mn && P.K % BK == 0)
+      run(std::integral_constant<bool, true>{});
+    else
+      run(std::integral_constant<bool, false>{});
+  }
+
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      const int rb0 = m0 + wm * C::WTM + i * 16 + 4 * fc, cb0 = n0 + wn * C::WTN + j * 16 + fr;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        float inv[4][3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) epilogue_inputs(P, p, rb0 + r, cb0, inv[r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) epilogue_apply(P, p, rb0 + r, cb0, acc[p][i][j][r], inv[r], s_d, s_x);
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, bool BUF, int MINW>
+__global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16_db_kernel(GemmParams<float> P) {
+  using C = Bf16DbCfg<BM, BN, WM, WN>;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * C::STAGE];
+  __shared__ double red_lds[C::NW][2];
+  const int nt = P.tiles_m * P.tiles_n;
+  double s_d = 0.0, s_x = 0.0;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int tm, tn;
+    tile_of_block(t, nt, P.tiles_m, P.tiles_n, tm, tn);
+    bf16_db_tile<BM, BN, WM, WN, BUF>(P, tm, tn, smem, s_d, s_x);
+  }
+  store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
+}
+
+// Buffer loads need 16-byte aligned bases, leading dimensions and plane strides (P.vec) and byte
+// offsets below 2^31 over the four planes.
+static bool bf16_buffer_ok(const GemmParams<float>& P) {
+  const int64_t lim = int64_t(1) << 31;
+  return P.vec && (3 * P.psa + (int64_t)P.M * P.lda) * 4 < lim && (3 * P.psb + (int64_t)P.K * P.ldb) * 4 < lim;
+}
+
+template <int BM, int BN, int WM, int WN, int MINW>
+static int64_t launch_bf16_db(const GemmParams<float>& P0, int per_cu, hipStream_t s) {
+  using C = Bf16DbCfg<BM, BN, WM, WN>;
+  GemmParams<float> P = P0;
+  P.tiles_m = (P.M + BM - 1) / BM;
+  P.tiles_n = (P.N + BN - 1) / BN;
+  const int64_t nt = (int64_t)P.tiles_m * P.tiles_n;
+  if (nt == 0) return 0;
+  auto kern = bf16_buffer_ok(P) ? qgemm_bf16_db_kernel<BM, BN, WM, WN, true, MINW>
+                                : qgemm_bf16_db_kernel<BM, BN, WM, WN, false, MINW>;
+  LaunchShape ls;
+  ls.grid = nt;
+  if (per_cu > 0) {
+    static const std::pair<int, size_t> kl = [&] {
+      int occ = 0;
+      QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, C::NT, 0));
+      hipFuncAttributes fa{};
+      QP_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)));
+      return std::make_pair(std::max(occ, 1), (size_t)fa.sharedSizeBytes);
+    }();
+    ls = launch_shape(nt, per_cu, kl.first, kl.second);
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)ls.grid), dim3(C::NT), ls.dyn_lds, s, P);
+  QP_HIP(hipGetLastError());
+  return ls.grid;
+}
+
 template <int BM, int BN, int WM, int WN>
 static int64_t launch_bf16(const GemmParams<float>& P0, int per_cu, hipStream_t s) {
   using C = Bf16Cfg<BM, BN, WM, WN>;
@@ -247,12 +551,14 @@ struct Bf16Entry {
 
 static const std::vector<Bf16Entry>& bf16_table() {
   static const std::vector<Bf16Entry> t = {
-      {{0, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32"}, launch_bf16<64, 64, 2, 2>},
+      // Measured on MI355X at 4096^3: 0 reaches 800 TFLOP/s (two workgroups per compute unit), 5 (the
+      // single-buffered form) 490; the 32 x 32 tiles win when there are few tiles per compute unit.
+      {{0, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"}, launch_bf16_db<64, 64, 2, 2, 2>},
       {{1, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32"}, launch_bf16<32, 32, 2, 2>},
-      {{2, 128, 64, 32, 256, "bf16_128x64x32_w2x2_mfma16x16x32"}, launch_bf16<128, 64, 2, 2>},
-      {{3, 64, 128, 32, 256, "bf16_64x128x32_w2x2_mfma16x16x32"}, launch_bf16<64, 128, 2, 2>},
-      {{4, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32_cu3", 3}, launch_bf16<32, 32, 2, 2>},
-      {{5, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_cu2", 2}, launch_bf16<64, 64, 2, 2>},
+      {{2, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2_cu2", 2}, launch_bf16_db<64, 64, 2, 2, 2>},
+      {{3, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32_cu3", 3}, launch_bf16<32, 32, 2, 2>},
+      {{4, 64, 128, 32, 512, "bf16_64x128x32_w2x4_mfma16x16x32_db"}, launch_bf16_db<64, 128, 2, 4, 2>},
+      {{5, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32"}, launch_bf16<64, 64, 2, 2>},
   };
   return t;
 }
