@@ -250,7 +250,7 @@ int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
   (void)K;
   const int64_t b64 = ((M + 63) / 64) * ((N + 63) / 64);
   if (p == P_F64) return b64 >= 1024 ? 4 : 1;
-  if (p == P_BF16) return b64 >= 256 ? 0 : 1;
+  if (p == P_BF16) return b64 >= 1024 ? 6 : b64 >= 256 ? 0 : 1;
   return b64 >= 1024 ? 5 : 6;
 }
 
@@ -289,7 +289,7 @@ static GemmParams<T> make_params(const QView& A, const QView& B, int64_t M, int6
   return P;
 }
 
-int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s);  // qgemm_bf16.hip
+int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s, GemmScratch& scratch);  // qgemm_bf16.hip
 int64_t bf16_blocks(int cfg, int64_t M, int64_t N);
 
 void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t K, const Epilogue& epi,
@@ -310,7 +310,7 @@ void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t
   } else if (p == P_F32) {
     launched = f32_table()[cfg].fn(make_params<float>(A, B, M, N, K, epi, partial), stream);
   } else {
-    launched = bf16_launch(make_params<float>(A, B, M, N, K, epi, partial), cfg, stream);
+    launched = bf16_launch(make_params<float>(A, B, M, N, K, epi, partial), cfg, stream, scratch);
   }
   if (epi.reduce) reduce_pairs(partial, launched, red, stream);
 }

@@ -36,6 +36,8 @@ struct Epilogue {
 struct GemmScratch {
   double* partial = nullptr;  // device, capacity doubles
   int64_t capacity = 0;
+  void* stage = nullptr;  // device, stage_bytes: BF16 operand copies of the staged BF16 products (grown on
+  size_t stage_bytes = 0;  // demand, outside graph capture; owned and freed by the context)
 };
 
 struct TileConfig {

@@ -5,6 +5,7 @@
 // while staging into LDS, so no BF16 copy of any matrix exists.  Two forms: a single-buffered one
 // (small tiles) and a double-buffered one (below).  Fragment lane layout of the MFMA (64 lanes):
 //   A frag: row l%16, k = 8(l/16) .. 8(l/16)+7;  B frag: col l%16, same k;  D reg r: row 4(l/16)+r, col l%16.
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -544,21 +545,357 @@ static int64_t launch_bf16(const GemmParams<float>& P0, int per_cu, hipStream_t 
   return ls.grid;
 }
 
+// ---------------------------------------------------------------------------------------------------
+// Staged form: the product first writes BF16 copies of its operands into the context's stage buffer,
+// A as [plane][Mp][Kp] and B transposed as [plane][Np][Kp] (both k-contiguous, rows of Kp = K rounded
+// up to 32, Mp and Np rounded up to the tile, zeros in the padding), then runs a kernel that reads
+// only those copies: no masks, no clamps, no conversion or transposition in the K loop, and half the
+// staging registers of the FP32-operand form, which leaves room for larger tiles.  The copies are
+// rounded to nearest even exactly as the other forms round while staging, and the MFMA sequence over
+// k is the same, so the three forms give identical products.
+template <int BM, int BN, int WM, int WN>
+struct Bf16SCfg {
+  static constexpr int BK = 32;
+  static constexpr int NW = WM * WN, NT = 64 * NW;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int TM = WTM / 16, TN = WTN / 16;
+  static constexpr int ACH = BM * 4, BCH = BN * 4;  // 16-byte chunks (8 k) of one plane tile
+  static constexpr int NA = ACH / NT, NB = BCH / NT;
+  static constexpr int STAGE = 4 * (BM + BN) * BK;  // bf16 elements of one LDS stage
+  static_assert(TM >= 2 && TN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile (two row halves)");
+  static_assert(ACH % NT == 0 && BCH % NT == 0 && NA >= 1 && NB >= 1, "whole chunks per thread");
+  static_assert(2 * STAGE * 2 <= 160 * 1024, "two stages fit the LDS");
+};
+
+// The BF16 copies of one product: planes of rows x kp elements (kp a multiple of 32).
+struct Bf16Stage {
+  const __bf16* a;  // [4][mp][kp]
+  const __bf16* b;  // [4][np][kp] (B transposed)
+  int mp, np, kp;
+};
+
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf16Stage& S, int tm, int tn,
+                                           __bf16* smem, double& s_d, double& s_x) {
+  using C = Bf16SCfg<BM, BN, WM, WN>;
+  constexpr int BK = C::BK;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w % WM, wn = w / WM;
+  // raw buffers over the four planes of each copy (extents below 2^31 bytes, checked by the launcher)
+  const __amdgpu_buffer_rsrc_t srcA = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<__bf16*>(S.a), (short)0, (int)((int64_t)4 * S.mp * S.kp * 2), 0x00020000);
+  const __amdgpu_buffer_rsrc_t srcB = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<__bf16*>(S.b), (short)0, (int)((int64_t)4 * S.np * S.kp * 2), 0x00020000);
+  const int psa = S.mp * S.kp * 2, psb = S.np * S.kp * 2;  // plane strides in bytes
+  // chunk c = tid + t NT of a plane tile: row c / 4, k 8 (c % 4) .. +7
+  int offa[C::NA], offb[C::NB];
+#pragma unroll
+  for (int t = 0; t < C::NA; ++t) {
+    const int c = tid + t * C::NT;
+    offa[t] = ((m0 + c / 4) * S.kp + 8 * (c % 4)) * 2;
+  }
+#pragma unroll
+  for (int t = 0; t < C::NB; ++t) {
+    const int c = tid + t * C::NT;
+    offb[t] = ((n0 + c / 4) * S.kp + 8 * (c % 4)) * 2;
+  }
+
+  floatx4 acc[4][C::TM][C::TN];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) acc[p][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  u32x4v ra[4][C::NA], rb[4][C::NB];
+  auto load_a = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NA; ++t)
+        ra[q][t] = __builtin_bit_cast(u32x4v, __builtin_amdgcn_raw_buffer_load_b128(srcA, offa[t], q * psa + 2 * k0, 0));
+  };
+  auto load_b = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NB; ++t)
+        rb[q][t] = __builtin_bit_cast(u32x4v, __builtin_amdgcn_raw_buffer_load_b128(srcB, offb[t], q * psb + 2 * k0, 0));
+  };
+  auto store_a = [&](__bf16* As) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NA; ++t) {
+        const int c = tid + t * C::NT;
+        *reinterpret_cast<u32x4v*>(&As[db_off(q * BM + c / 4, c % 4)]) = ra[q][t];
+      }
+  };
+  auto store_b = [&](__bf16* As) __attribute__((always_inline)) {
+    __bf16* const Bs = As + 4 * BM * BK;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < C::NB; ++t) {
+        const int c = tid + t * C::NT;
+        *reinterpret_cast<u32x4v*>(&Bs[db_off(q * BN + c / 4, c % 4)]) = rb[q][t];
+      }
+  };
+
+  const int fr = lane & 15, fc = lane >> 4;
+  bf16x8 b[C::TN][4];
+  auto frag_b = [&](const __bf16* As) __attribute__((always_inline)) {
+    const __bf16* const Bs = As + 4 * BM * BK;
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        b[j][q] = *reinterpret_cast<const bf16x8*>(&Bs[db_off(q * BN + wn * C::WTN + j * 16 + fr, fc)]);
+  };
+  auto compute = [&](const __bf16* As, int i0, int i1) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = i0; i < i1; ++i) {
+      bf16x8 a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        a[q] = *reinterpret_cast<const bf16x8*>(&As[db_off(q * BM + wm * C::WTM + i * 16 + fr, fc)]);
+      const bf16x8 na1 = neg_bf16x8(a[1]), na2 = neg_bf16x8(a[2]), na3 = neg_bf16x8(a[3]);
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        acc[0][i][j] = mma_bf16(a[0], b[j][0], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(a[0], b[j][1], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(a[0], b[j][2], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(a[0], b[j][3], acc[3][i][j]);
+        acc[0][i][j] = mma_bf16(na1, b[j][1], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(a[1], b[j][0], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(na1, b[j][3], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(a[1], b[j][2], acc[3][i][j]);
+        acc[0][i][j] = mma_bf16(na2, b[j][2], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(a[2], b[j][3], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(a[2], b[j][0], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(na2, b[j][1], acc[3][i][j]);
+        acc[0][i][j] = mma_bf16(na3, b[j][3], acc[0][i][j]);
+        acc[1][i][j] = mma_bf16(na3, b[j][2], acc[1][i][j]);
+        acc[2][i][j] = mma_bf16(a[3], b[j][1], acc[2][i][j]);
+        acc[3][i][j] = mma_bf16(a[3], b[j][0], acc[3][i][j]);
+      }
+    }
+  };
+
+  constexpr int IH = C::TM / 2;
+  const int nk = S.kp / BK;
+  if (nk > 0) {
+    load_a(0);
+    load_b(0);
+    store_a(smem);
+    store_b(smem);
+    __syncthreads();
+    for (int kt = 0; kt + 1 < nk; ++kt) {
+      __bf16* const cur = smem + (kt & 1) * C::STAGE;
+      __bf16* const nxt = smem + ((kt + 1) & 1) * C::STAGE;
+      const int kn = (kt + 1) * BK;
+      frag_b(cur);
+      load_a(kn);
+      compute(cur, 0, IH);
+      store_a(nxt);
+      load_b(kn);
+      compute(cur, IH, C::TM);
+      store_b(nxt);
+      __syncthreads();
+    }
+    const __bf16* const last = smem + ((nk - 1) & 1) * C::STAGE;
+    frag_b(last);
+    compute(last, 0, C::TM);
+    __syncthreads();  // the next tile's first stage overwrites LDS
+  }
+
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      const int rb0 = m0 + wm * C::WTM + i * 16 + 4 * fc, cb0 = n0 + wn * C::WTN + j * 16 + fr;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        float inv[4][3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) epilogue_inputs(P, p, rb0 + r, cb0, inv[r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) epilogue_apply(P, p, rb0 + r, cb0, acc[p][i][j][r], inv[r], s_d, s_x);
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, int MINW>
+__global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16s_kernel(GemmParams<float> P, Bf16Stage S) {
+  using C = Bf16SCfg<BM, BN, WM, WN>;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * C::STAGE];
+  __shared__ double red_lds[C::NW][2];
+  const int nt = P.tiles_m * P.tiles_n;
+  double s_d = 0.0, s_x = 0.0;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int tm, tn;
+    tile_of_block(t, nt, P.tiles_m, P.tiles_n, tm, tn);
+    bf16s_tile<BM, BN, WM, WN>(P, S, tm, tn, smem, s_d, s_x);
+  }
+  store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
+}
+
+// out[q][r][8c .. 8c+7] = bf16(A[q][r][8c ..]) inside the matrix, 0 in the padding (r < mp, 8c < kp).
+__global__ void __launch_bounds__(256) bf16_rows_kernel(const float* __restrict__ A, int64_t lda, int64_t psa, int M,
+                                                        int K, __bf16* __restrict__ out, int mp, int kp) {
+  const int64_t chunks = (int64_t)4 * mp * (kp / 8);
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * blockDim.x) {
+    const int kc = (int)(c % (kp / 8));
+    const int64_t qr = c / (kp / 8);
+    const int r = (int)(qr % mp), q = (int)(qr / mp);
+    floatx4 lo = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
+    if (r < M) {
+      const float* row = A + q * psa + (int64_t)r * lda;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 8 * kc + e;
+        lo[e] = k < K ? gload(row, k) : 0.f;
+        hi[e] = k + 4 < K ? gload(row, k + 4) : 0.f;
+      }
+    }
+    bf16x8 o;
+    const bf16x4 l = __builtin_convertvector(lo, bf16x4), h = __builtin_convertvector(hi, bf16x4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      o[e] = l[e];
+      o[e + 4] = h[e];
+    }
+    *reinterpret_cast<bf16x8*>(out + 8 * c) = o;
+  }
+}
+
+// out[q][n][k] = bf16(B[q][k][n]) inside the matrix, 0 in the padding (n < np, k < kp): one 32 (k) x 64 (n)
+// tile per workgroup through LDS, reads coalesced along n, writes 16 bytes (8 k) per lane.
+__global__ void __launch_bounds__(256) bf16_transpose_kernel(const float* __restrict__ B, int64_t ldb, int64_t psb,
+                                                             int K, int N, __bf16* __restrict__ out, int np, int kp) {
+  __shared__ float tile[32][65];
+  const int tk = kp / 32, tn = np / 64;
+  const int64_t t = blockIdx.x;
+  const int q = (int)(t / ((int64_t)tk * tn));
+  const int rest = (int)(t % ((int64_t)tk * tn));
+  const int k0 = (rest / tn) * 32, n0 = (rest % tn) * 64;
+  const int tid = threadIdx.x;
+  {
+    const int col = tid % 64, r0 = (tid / 64) * 8;
+    const int n = n0 + col;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + r0 + e;
+      tile[r0 + e][col] = (k < K && n < N) ? gload(B + q * psb, (int64_t)k * ldb + n) : 0.f;
+    }
+  }
+  __syncthreads();
+  const int nl = tid / 4, kc = (tid % 4) * 8;
+  floatx4 lo, hi;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    lo[e] = tile[kc + e][nl];
+    hi[e] = tile[kc + 4 + e][nl];
+  }
+  bf16x8 o;
+  const bf16x4 l = __builtin_convertvector(lo, bf16x4), h = __builtin_convertvector(hi, bf16x4);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    o[e] = l[e];
+    o[e + 4] = h[e];
+  }
+  *reinterpret_cast<bf16x8*>(out + ((int64_t)q * np + n0 + nl) * kp + k0 + kc) = o;
+}
+
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Stage bytes of a staged product (rows padded to 128 cover every staged tile shape).
+static int64_t stage_bytes(int64_t M, int64_t N, int64_t K) {
+  return 2 * 4 * (round_up(M, 128) + round_up(N, 128)) * round_up(std::max<int64_t>(K, 1), 32);
+}
+
+template <int BM, int BN, int WM, int WN, int MINW>
+static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipStream_t s, GemmScratch& sc) {
+  using C = Bf16SCfg<BM, BN, WM, WN>;
+  GemmParams<float> P = P0;
+  P.tiles_m = (P.M + BM - 1) / BM;
+  P.tiles_n = (P.N + BN - 1) / BN;
+  const int64_t nt = (int64_t)P.tiles_m * P.tiles_n;
+  if (nt == 0) return 0;
+  const int64_t mp = round_up(P.M, 128), np = round_up(P.N, 128), kp = round_up(P.K, 32);
+  if (4 * std::max(mp, np) * std::max<int64_t>(kp, 32) * 2 >= (int64_t(1) << 31))
+    throw Error(-1, "qgemm: BF16 operand copies exceed 2^31 bytes per operand");
+  const size_t need = (size_t)stage_bytes(P.M, P.N, P.K);
+  if (sc.stage_bytes < need) {
+    // grow the stage buffer (kernels of earlier products on the stream may still read it)
+    QP_HIP(hipStreamSynchronize(s));
+    if (sc.stage) QP_HIP(hipFree(sc.stage));
+    sc.stage = nullptr;
+    sc.stage_bytes = 0;
+    QP_HIP(hipMalloc(&sc.stage, need));
+    sc.stage_bytes = need;
+  }
+  __bf16* const a16 = static_cast<__bf16*>(sc.stage);
+  __bf16* const b16 = a16 + 4 * mp * kp;
+  if (kp > 0) {
+    const int64_t chunks = 4 * mp * (kp / 8);
+    const int64_t grid_r = std::min<int64_t>((chunks + 255) / 256, 65536);
+    hipLaunchKernelGGL(bf16_rows_kernel, dim3((unsigned)grid_r), dim3(256), 0, s, P.A, P.lda, P.psa, P.M, P.K, a16,
+                       (int)mp, (int)kp);
+    QP_HIP(hipGetLastError());
+    const int64_t grid_t = 4 * (kp / 32) * (np / 64);
+    hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)grid_t), dim3(256), 0, s, P.B, P.ldb, P.psb, P.K, P.N, b16,
+                       (int)np, (int)kp);
+    QP_HIP(hipGetLastError());
+  }
+  const Bf16Stage S{a16, b16, (int)mp, (int)np, (int)kp};
+  auto kern = qgemm_bf16s_kernel<BM, BN, WM, WN, MINW>;
+  LaunchShape ls;
+  ls.grid = nt;
+  if (per_cu > 0) {
+    static const std::pair<int, size_t> kl = [&] {
+      int occ = 0;
+      QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, C::NT, 0));
+      hipFuncAttributes fa{};
+      QP_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)));
+      return std::make_pair(std::max(occ, 1), (size_t)fa.sharedSizeBytes);
+    }();
+    ls = launch_shape(nt, per_cu, kl.first, kl.second);
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)ls.grid), dim3(C::NT), ls.dyn_lds, s, P, S);
+  QP_HIP(hipGetLastError());
+  return ls.grid;
+}
+
 struct Bf16Entry {
   TileConfig cfg;
-  int64_t (*fn)(const GemmParams<float>&, int, hipStream_t);
+  int64_t (*fn)(const GemmParams<float>&, int, hipStream_t, GemmScratch&);
 };
+
+// The forms that read the FP32 operands directly leave the stage buffer alone.
+template <int64_t (*F)(const GemmParams<float>&, int, hipStream_t)>
+static int64_t direct(const GemmParams<float>& P, int per_cu, hipStream_t s, GemmScratch&) {
+  return F(P, per_cu, s);
+}
 
 static const std::vector<Bf16Entry>& bf16_table() {
   static const std::vector<Bf16Entry> t = {
-      // Measured on MI355X at 4096^3: 0 reaches 800 TFLOP/s (two workgroups per compute unit), 5 (the
-      // single-buffered form) 490; the 32 x 32 tiles win when there are few tiles per compute unit.
-      {{0, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"}, launch_bf16_db<64, 64, 2, 2, 2>},
-      {{1, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32"}, launch_bf16<32, 32, 2, 2>},
-      {{2, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2_cu2", 2}, launch_bf16_db<64, 64, 2, 2, 2>},
-      {{3, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32_cu3", 3}, launch_bf16<32, 32, 2, 2>},
-      {{4, 64, 128, 32, 512, "bf16_64x128x32_w2x4_mfma16x16x32_db"}, launch_bf16_db<64, 128, 2, 4, 2>},
-      {{5, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32"}, launch_bf16<64, 64, 2, 2>},
+      // Measured on MI355X at 4096^3 (2048^3): 6 reaches 1000 (920) TFLOP/s including its operand copies,
+      // 0 790 (850), 5 (the single-buffered form) 490; below about 4 tiles of 64 x 64 per compute unit
+      // the copies cost more than they save, and below 1 the 32 x 32 tiles win.  Tiles of 128 (staged)
+      // measured 320-360 TFLOP/s: their LDS stages leave one workgroup per compute unit.
+      {{0, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"}, direct<launch_bf16_db<64, 64, 2, 2, 2>>},
+      {{1, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32"}, direct<launch_bf16<32, 32, 2, 2>>},
+      {{2, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2_cu2", 2}, direct<launch_bf16_db<64, 64, 2, 2, 2>>},
+      {{3, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32_cu3", 3}, direct<launch_bf16<32, 32, 2, 2>>},
+      {{4, 64, 128, 32, 512, "bf16_64x128x32_w2x4_mfma16x16x32_db"}, direct<launch_bf16_db<64, 128, 2, 4, 2>>},
+      {{5, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32"}, direct<launch_bf16<64, 64, 2, 2>>},
+      {{6, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_staged"}, launch_bf16_staged<64, 64, 2, 2, 2>},
+      {{7, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_staged_cu2", 2}, launch_bf16_staged<64, 64, 2, 2, 2>},
   };
   return t;
 }
@@ -570,9 +907,9 @@ const std::vector<TileConfig>& bf16_configs() {
   return v;
 }
 
-int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s) {
+int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s, GemmScratch& scratch) {
   const auto& e = bf16_table().at(cfg);
-  return e.fn(P, e.cfg.per_cu, s);
+  return e.fn(P, e.cfg.per_cu, s, scratch);
 }
 
 int64_t bf16_blocks(int cfg, int64_t M, int64_t N) {

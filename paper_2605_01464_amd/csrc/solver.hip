@@ -100,6 +100,7 @@ Ctx::~Ctx() {
   delete batched;
   ws.release();
   if (scratch.partial) (void)hipFree(scratch.partial);
+  if (scratch.stage) (void)hipFree(scratch.stage);
   if (dsc) (void)hipFree(dsc);
   if (hsc) (void)hipHostFree(hsc);
 }

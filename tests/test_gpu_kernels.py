@@ -172,6 +172,32 @@ def test_round_bf16_helper():
     assert v[0] == 1.0 and v[1] == 1.0 + 2 ** -6  # ties go to the even mantissa
 
 
+def _bf16_cfgs(q, tag):
+    gp = q.GEMM_PREC["bf16"]
+    return [c for c in range(q.qpinv_num_tile_configs(gp)) if tag in q.qpinv_tile_config_name(gp, c)]
+
+
+def test_qgemm_bf16_staged_equals_direct_and_regrows_its_stage(qctx):
+    """The staged form (BF16 copies of the operands, zero-padded to whole tiles and K steps) computes the
+    same MFMA sequence over k as the forms that round while staging: identical outputs, epilogue included.
+    Products of growing and shrinking size reuse and regrow the context's stage buffer."""
+    import paper_2605_01464_amd as q
+
+    staged, direct = _bf16_cfgs(q, "_staged"), _bf16_cfgs(q, "_db")
+    assert staged and direct
+    for seed, (M_, N_, K_) in enumerate([(130, 250, 70), (1, 1, 1), (700, 520, 333), (257, 129, 300), (64, 64, 32)]):
+        A = rng_planes(80 + seed, M_, K_, "f32")
+        B = rng_planes(90 + seed, K_, N_, "f32")
+        C0 = rng_planes(100 + seed, M_, N_, "f32")
+        outs = {}
+        for cfg in staged + direct:
+            Cd = to_dev(C0, "f32")
+            q.qgemm(qctx, to_dev(A, "f32"), to_dev(B, "f32"), Cd, 0.5, -1.25, 1.0, gemm_prec="bf16", cfg=cfg)
+            outs[cfg] = to_np(Cd)
+        for cfg in staged:
+            assert np.array_equal(outs[cfg], outs[direct[0]]), (M_, N_, K_, cfg)
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_qgemm_bf16_every_config(qctx, shape):
     """BF16-operand product = exact product of the BF16-rounded FP32 inputs up to FP32 accumulation."""
