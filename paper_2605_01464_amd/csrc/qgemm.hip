@@ -250,7 +250,7 @@ int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
   (void)K;
   const int64_t b64 = ((M + 63) / 64) * ((N + 63) / 64);
   if (p == P_F64) return b64 >= 1024 ? 4 : 1;
-  if (p == P_BF16) return b64 >= 1024 ? 6 : b64 >= 256 ? 0 : 1;
+  if (p == P_BF16) return b64 >= 1024 ? 8 : b64 >= 256 ? 0 : 1;
   return b64 >= 1024 ? 5 : 6;
 }
 

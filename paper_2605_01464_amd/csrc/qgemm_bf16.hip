@@ -560,10 +560,9 @@ struct Bf16SCfg {
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int TM = WTM / 16, TN = WTN / 16;
   static constexpr int ACH = BM * 4, BCH = BN * 4;  // 16-byte chunks (8 k) of one plane tile
-  static constexpr int NA = ACH / NT, NB = BCH / NT;
+  static constexpr int NA = (ACH + NT - 1) / NT, NB = (BCH + NT - 1) / NT;
   static constexpr int STAGE = 4 * (BM + BN) * BK;  // bf16 elements of one LDS stage
   static_assert(TM >= 2 && TN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile (two row halves)");
-  static_assert(ACH % NT == 0 && BCH % NT == 0 && NA >= 1 && NB >= 1, "whole chunks per thread");
   static_assert(2 * STAGE * 2 <= 160 * 1024, "two stages fit the LDS");
 };
 
@@ -594,12 +593,12 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
   int offa[C::NA], offb[C::NB];
 #pragma unroll
   for (int t = 0; t < C::NA; ++t) {
-    const int c = tid + t * C::NT;
+    const int c = min(tid + t * C::NT, C::ACH - 1);
     offa[t] = ((m0 + c / 4) * S.kp + 8 * (c % 4)) * 2;
   }
 #pragma unroll
   for (int t = 0; t < C::NB; ++t) {
-    const int c = tid + t * C::NT;
+    const int c = min(tid + t * C::NT, C::BCH - 1);
     offb[t] = ((n0 + c / 4) * S.kp + 8 * (c % 4)) * 2;
   }
 
@@ -632,7 +631,7 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
 #pragma unroll
       for (int t = 0; t < C::NA; ++t) {
         const int c = tid + t * C::NT;
-        *reinterpret_cast<u32x4v*>(&As[db_off(q * BM + c / 4, c % 4)]) = ra[q][t];
+        if (C::ACH % C::NT == 0 || c < C::ACH) *reinterpret_cast<u32x4v*>(&As[db_off(q * BM + c / 4, c % 4)]) = ra[q][t];
       }
   };
   auto store_b = [&](__bf16* As) __attribute__((always_inline)) {
@@ -642,7 +641,7 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
 #pragma unroll
       for (int t = 0; t < C::NB; ++t) {
         const int c = tid + t * C::NT;
-        *reinterpret_cast<u32x4v*>(&Bs[db_off(q * BN + c / 4, c % 4)]) = rb[q][t];
+        if (C::BCH % C::NT == 0 || c < C::BCH) *reinterpret_cast<u32x4v*>(&Bs[db_off(q * BN + c / 4, c % 4)]) = rb[q][t];
       }
   };
 
@@ -884,10 +883,10 @@ static int64_t direct(const GemmParams<float>& P, int per_cu, hipStream_t s, Gem
 
 static const std::vector<Bf16Entry>& bf16_table() {
   static const std::vector<Bf16Entry> t = {
-      // Measured on MI355X at 4096^3 (2048^3): 6 reaches 1000 (920) TFLOP/s including its operand copies,
-      // 0 790 (850), 5 (the single-buffered form) 490; below about 4 tiles of 64 x 64 per compute unit
-      // the copies cost more than they save, and below 1 the 32 x 32 tiles win.  Tiles of 128 (staged)
-      // measured 320-360 TFLOP/s: their LDS stages leave one workgroup per compute unit.
+      // Measured on MI355X at 4096^3 (2048^3): 8 reaches 1060 (910) TFLOP/s including its operand copies,
+      // 6 960-1000 (900-920), 0 790 (850), 5 (the single-buffered form) 490; below about 4 tiles of
+      // 64 x 64 per compute unit the copies cost more than they save, and below 1 the 32 x 32 tiles win.
+      // Tiles of 128 (staged) measured 320-360 TFLOP/s: their LDS stages leave one workgroup per CU.
       {{0, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"}, direct<launch_bf16_db<64, 64, 2, 2, 2>>},
       {{1, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32"}, direct<launch_bf16<32, 32, 2, 2>>},
       {{2, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2_cu2", 2}, direct<launch_bf16_db<64, 64, 2, 2, 2>>},
@@ -896,6 +895,7 @@ static const std::vector<Bf16Entry>& bf16_table() {
       {{5, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32"}, direct<launch_bf16<64, 64, 2, 2>>},
       {{6, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_staged"}, launch_bf16_staged<64, 64, 2, 2, 2>},
       {{7, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_staged_cu2", 2}, launch_bf16_staged<64, 64, 2, 2, 2>},
+      {{8, 64, 64, 32, 512, "bf16_64x64x32_w2x4_mfma16x16x32_staged"}, launch_bf16_staged<64, 64, 2, 4, 4>},
   };
   return t;
 }
