@@ -218,7 +218,13 @@ int qpinv_residuals(qpinv_ctx* ctx, const qpinv_qmat* A, const qpinv_qmat* X, do
 /* Quaternion product (Section 2, Hamilton product): C = alpha A B + beta C + gamma I, with
  * A (M x K), B (K x N), C (M x N) of one storage dtype (F64 for GEMM_F64, F32 otherwise) and I the
  * quaternion identity (ones on the diagonal of the real plane).  C must not alias A or B.
- * Errors: EINVAL, EHIP. */
+ * GEMM_BF16 rounds the FP32 operands to BF16 (nearest even) and accumulates in FP32.  Its large
+ * products (1024 or more 64 x 64 output tiles, or the "_staged" configurations) first copy the
+ * operands into a BF16 stage buffer that the context owns: 2 * 4 * (Mp + Np) * Kp bytes, Mp and Np
+ * the row counts of A and of B^T rounded up to 128, Kp = K rounded up to 32.  The buffer grows on
+ * demand (the stream is synchronised first) and is freed by qpinv_finalize; products on one context
+ * share it, so they must not run concurrently on different streams.
+ * Errors: EINVAL, EHIP, ENOMEM (stage buffer). */
 int qpinv_qgemm(qpinv_ctx* ctx, int gemm_prec, const qpinv_qmat* A, const qpinv_qmat* B, qpinv_qmat* C,
                 double alpha, double beta, double gamma, void* hip_stream);
 

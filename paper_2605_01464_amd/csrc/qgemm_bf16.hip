@@ -6,6 +6,7 @@
 // (small tiles) and a double-buffered one (below).  Fragment lane layout of the MFMA (64 lanes):
 //   A frag: row l%16, k = 8(l/16) .. 8(l/16)+7;  B frag: col l%16, same k;  D reg r: row 4(l/16)+r, col l%16.
 #include <algorithm>
+#include <string>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -835,7 +836,11 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
     if (sc.stage) QP_HIP(hipFree(sc.stage));
     sc.stage = nullptr;
     sc.stage_bytes = 0;
-    QP_HIP(hipMalloc(&sc.stage, need));
+    if (hipMalloc(&sc.stage, need) != hipSuccess || !sc.stage) {
+      (void)hipGetLastError();
+      sc.stage = nullptr;
+      throw Error(-6, "qgemm: allocation of the BF16 stage buffer (" + std::to_string(need) + " bytes) failed");
+    }
     sc.stage_bytes = need;
   }
   __bf16* const a16 = static_cast<__bf16*>(sc.stage);
