@@ -127,7 +127,7 @@ def qmat(t) -> QMat:
     if not t.is_cuda:
         raise ValueError("quaternion matrices must live in GPU memory")
     rows, cols = int(t.shape[1]), int(t.shape[2])
-    if cols > 1 and t.stride(2) != 1:
+    if cols > 1 and rows > 0 and t.stride(2) != 1:  # (an empty tensor's strides are arbitrary)
         raise ValueError("columns must have unit stride")
     ld = int(t.stride(1)) if rows > 1 else max(cols, 1)
     ps = int(t.stride(0))

@@ -745,8 +745,9 @@ __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16s_kernel(GemmPar
 }
 
 // out[q][r][8c .. 8c+7] = bf16(A[q][r][8c ..]) inside the matrix, 0 in the padding (r < mp, 8c < kp).
+// vec: 16-byte aligned base, lda and psa.
 __global__ void __launch_bounds__(256) bf16_rows_kernel(const float* __restrict__ A, int64_t lda, int64_t psa, int M,
-                                                        int K, __bf16* __restrict__ out, int mp, int kp) {
+                                                        int K, __bf16* __restrict__ out, int mp, int kp, int vec) {
   const int64_t chunks = (int64_t)4 * mp * (kp / 8);
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * blockDim.x) {
     const int kc = (int)(c % (kp / 8));
@@ -755,11 +756,16 @@ __global__ void __launch_bounds__(256) bf16_rows_kernel(const float* __restrict_
     floatx4 lo = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
     if (r < M) {
       const float* row = A + q * psa + (int64_t)r * lda;
+      if (vec && 8 * kc + 8 <= K) {  // whole chunk: two 16-byte loads
+        lo = gload(reinterpret_cast<const floatx4*>(row + 8 * kc), 0);
+        hi = gload(reinterpret_cast<const floatx4*>(row + 8 * kc + 4), 0);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k = 8 * kc + e;
-        lo[e] = k < K ? gload(row, k) : 0.f;
-        hi[e] = k + 4 < K ? gload(row, k + 4) : 0.f;
+        for (int e = 0; e < 4; ++e) {
+          const int k = 8 * kc + e;
+          lo[e] = k < K ? gload(row, k) : 0.f;
+          hi[e] = k + 4 < K ? gload(row, k + 4) : 0.f;
+        }
       }
     }
     bf16x8 o;
@@ -848,8 +854,9 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
   if (kp > 0) {
     const int64_t chunks = 4 * mp * (kp / 8);
     const int64_t grid_r = std::min<int64_t>((chunks + 255) / 256, 65536);
+    const int vec_a = (reinterpret_cast<uintptr_t>(P.A) & 15) == 0 && P.lda % 4 == 0 && P.psa % 4 == 0;
     hipLaunchKernelGGL(bf16_rows_kernel, dim3((unsigned)grid_r), dim3(256), 0, s, P.A, P.lda, P.psa, P.M, P.K, a16,
-                       (int)mp, (int)kp);
+                       (int)mp, (int)kp, vec_a);
     QP_HIP(hipGetLastError());
     const int64_t grid_t = 4 * (kp / 32) * (np / 64);
     hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)grid_t), dim3(256), 0, s, P.B, P.ldb, P.psb, P.K, P.N, b16,

@@ -185,7 +185,8 @@ def test_qgemm_bf16_staged_equals_direct_and_regrows_its_stage(qctx):
 
     staged, direct = _bf16_cfgs(q, "_staged"), _bf16_cfgs(q, "_db")
     assert staged and direct
-    for seed, (M_, N_, K_) in enumerate([(130, 250, 70), (1, 1, 1), (700, 520, 333), (257, 129, 300), (64, 64, 32)]):
+    for seed, (M_, N_, K_) in enumerate([(130, 250, 70), (1, 1, 1), (700, 520, 333), (257, 129, 300), (64, 64, 32),
+                                         (96, 40, 0)]):
         A = rng_planes(80 + seed, M_, K_, "f32")
         B = rng_planes(90 + seed, K_, N_, "f32")
         C0 = rng_planes(100 + seed, M_, N_, "f32")
