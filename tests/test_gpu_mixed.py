@@ -104,6 +104,39 @@ def test_full_size_mixed_sampled_rows(qctx):
     assert info["iters_bf16"] >= 1 and 1 <= info["iters_f64"] <= 2
 
 
+def test_ragged_tall_mixed_ladder_with_staged_bf16_products(qctx):
+    """2100 x 2050, condition 1e2: the BF16 products of this size (1089 output tiles of 64 x 64, K = 2100)
+    take the staged form with padded operand copies; sampled rows of X A - I (the left residual, I_n since
+    A has full column rank) must be at FP64 level after the finish."""
+    import torch
+    import paper_2605_01464_amd as q
+
+    m, n = 2100, 2050
+    s = qsynth.geometric(n, 1.0, 1e-2)
+    s = s * (2.0 * np.sqrt(m * n) / np.sqrt(np.sum(s * s)))
+    A = qsynth.round_f32(qsynth.structured_spectral((230, 231), m, n, s))
+    qctx.set("gemm_timing", 1)
+    try:
+        q.qpinv_gemm_stats(qctx.handle)  # reset
+        X, info = q.solve(qctx, to_dev(A, "f32"), "qhpi19", scaling="power", tol=1e-6, stop="guarded",
+                          precision="mixed", out_dtype=torch.float64)
+        st, rows_used = q.qpinv_gemm_stats(qctx.handle)
+    finally:
+        qctx.set("gemm_timing", 0)
+    gp = q.GEMM_PREC["bf16"]
+    assert st == q.OK
+    bf16_names = {q.qpinv_tile_config_name(gp, r["cfg"]) for r in rows_used if r["prec"] == gp}
+    assert any("_staged" in nm for nm in bf16_names), bf16_names
+    assert info["iters_bf16"] >= 1 and 1 <= info["iters_f64"] <= 2, info
+    Xh = to_np(X)
+    rows = np.random.default_rng(7).choice(n, 16, replace=False)
+    XAr = Q.qmul(Xh[:, rows, :], A)
+    I = np.zeros_like(XAr)
+    I[0, np.arange(16), rows] = 1.0
+    res = np.linalg.norm(XAr - I) / np.sqrt(16)
+    assert res * (s[0] / s[-1]) <= 1e-6, (res, info)
+
+
 @pytest.mark.parametrize("precision", ["mixed", "f32_f64finish"])
 def test_newton_schulz_finish_vs_same_method(qctx, sq512, precision):
     """The default FP64 finish (Newton-Schulz, 2 products per update) reaches the 1e-6 target like a finish
