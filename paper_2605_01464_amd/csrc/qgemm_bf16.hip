@@ -554,16 +554,39 @@ static int64_t launch_bf16(const GemmParams<float>& P0, int per_cu, hipStream_t 
 // staging registers of the FP32-operand form, which leaves room for larger tiles.  The copies are
 // rounded to nearest even exactly as the other forms round while staging, and the MFMA sequence over
 // k is the same, so the three forms give identical products.
-template <int BM, int BN, int WM, int WN>
+// BF16 MFMA shapes of the staged form.  Fragments are 8 consecutive k of one row (A) or column (B) per
+// lane, i.e. one 16-byte LDS chunk; chunk(l, h) names the chunk (of the 4 in a 32-k row) that lane l
+// reads for k sub-step h.  Output register r of lane l holds element (crow(l, r), ccol(l)) of the block.
+struct BfM16 {  // v_mfma_f32_16x16x32_bf16: one 32-k sub-step per K step
+  using Acc = floatx4;
+  static constexpr int BLK = 16, KSUB = 1, NR = 4;
+  __device__ static int fr(int l) { return l & 15; }
+  __device__ static int chunk(int l, int) { return l >> 4; }
+  __device__ static int crow(int l, int r) { return ((l >> 4) << 2) + r; }
+  __device__ static int ccol(int l) { return l & 15; }
+  __device__ static Acc mma(bf16x8 a, bf16x8 b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+struct BfM32 {  // v_mfma_f32_32x32x16_bf16: two 16-k sub-steps per K step
+  using Acc = floatx16;
+  static constexpr int BLK = 32, KSUB = 2, NR = 16;
+  __device__ static int fr(int l) { return l & 31; }
+  __device__ static int chunk(int l, int h) { return 2 * h + (l >> 5); }
+  __device__ static int crow(int l, int r) { return ((r >> 2) << 3) + ((l >> 5) << 2) + (r & 3); }
+  __device__ static int ccol(int l) { return l & 31; }
+  __device__ static Acc mma(bf16x8 a, bf16x8 b, Acc c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+
+template <int BM, int BN, int WM, int WN, class MB = BfM16>
 struct Bf16SCfg {
   static constexpr int BK = 32;
   static constexpr int NW = WM * WN, NT = 64 * NW;
   static constexpr int WTM = BM / WM, WTN = BN / WN;
-  static constexpr int TM = WTM / 16, TN = WTN / 16;
+  static constexpr int TM = WTM / MB::BLK, TN = WTN / MB::BLK;
+  static constexpr int ITEMS = TM * MB::KSUB;  // (row block, k sub-step) pairs of one K step
   static constexpr int ACH = BM * 4, BCH = BN * 4;  // 16-byte chunks (8 k) of one plane tile
   static constexpr int NA = (ACH + NT - 1) / NT, NB = (BCH + NT - 1) / NT;
   static constexpr int STAGE = 4 * (BM + BN) * BK;  // bf16 elements of one LDS stage
-  static_assert(TM >= 2 && TN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile (two row halves)");
+  static_assert(ITEMS >= 2 && TN >= 1 && WTM % MB::BLK == 0 && WTN % MB::BLK == 0, "wave tile (two halves)");
   static_assert(2 * STAGE * 2 <= 160 * 1024, "two stages fit the LDS");
 };
 
@@ -576,10 +599,11 @@ struct Bf16Stage {
 
 typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, class MB>
 __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf16Stage& S, int tm, int tn,
                                            __bf16* smem, double& s_d, double& s_x) {
-  using C = Bf16SCfg<BM, BN, WM, WN>;
+  using C = Bf16SCfg<BM, BN, WM, WN, MB>;
+  using Acc = typename MB::Acc;
   constexpr int BK = C::BK;
   const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -603,13 +627,13 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
     offb[t] = ((n0 + c / 4) * S.kp + 8 * (c % 4)) * 2;
   }
 
-  floatx4 acc[4][C::TM][C::TN];
+  Acc acc[4][C::TM][C::TN];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-      for (int j = 0; j < C::TN; ++j) acc[p][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < C::TN; ++j) acc[p][i][j] = Acc{};
 
   u32x4v ra[4][C::NA], rb[4][C::NB];
   auto load_a = [&](int k0) __attribute__((always_inline)) {
@@ -646,47 +670,53 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
       }
   };
 
-  const int fr = lane & 15, fc = lane >> 4;
-  bf16x8 b[C::TN][4];
+  const int fr = MB::fr(lane);
+  bf16x8 b[C::TN][MB::KSUB][4];
   auto frag_b = [&](const __bf16* As) __attribute__((always_inline)) {
     const __bf16* const Bs = As + 4 * BM * BK;
 #pragma unroll
     for (int j = 0; j < C::TN; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        b[j][q] = *reinterpret_cast<const bf16x8*>(&Bs[db_off(q * BN + wn * C::WTN + j * 16 + fr, fc)]);
-  };
-  auto compute = [&](const __bf16* As, int i0, int i1) __attribute__((always_inline)) {
+      for (int h = 0; h < MB::KSUB; ++h)
 #pragma unroll
-    for (int i = i0; i < i1; ++i) {
+        for (int q = 0; q < 4; ++q)
+          b[j][h][q] = *reinterpret_cast<const bf16x8*>(
+              &Bs[db_off(q * BN + wn * C::WTN + j * MB::BLK + fr, MB::chunk(lane, h))]);
+  };
+  // MFMAs of the (row block, k sub-step) items it0 <= it < it1 (compile-time bounds after inlining)
+  auto compute = [&](const __bf16* As, int it0, int it1) __attribute__((always_inline)) {
+#pragma unroll
+    for (int it = it0; it < it1; ++it) {
+      const int i = it / MB::KSUB, h = it % MB::KSUB;
       bf16x8 a[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        a[q] = *reinterpret_cast<const bf16x8*>(&As[db_off(q * BM + wm * C::WTM + i * 16 + fr, fc)]);
+        a[q] = *reinterpret_cast<const bf16x8*>(&As[db_off(q * BM + wm * C::WTM + i * MB::BLK + fr, MB::chunk(lane, h))]);
       const bf16x8 na1 = neg_bf16x8(a[1]), na2 = neg_bf16x8(a[2]), na3 = neg_bf16x8(a[3]);
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
-        acc[0][i][j] = mma_bf16(a[0], b[j][0], acc[0][i][j]);
-        acc[1][i][j] = mma_bf16(a[0], b[j][1], acc[1][i][j]);
-        acc[2][i][j] = mma_bf16(a[0], b[j][2], acc[2][i][j]);
-        acc[3][i][j] = mma_bf16(a[0], b[j][3], acc[3][i][j]);
-        acc[0][i][j] = mma_bf16(na1, b[j][1], acc[0][i][j]);
-        acc[1][i][j] = mma_bf16(a[1], b[j][0], acc[1][i][j]);
-        acc[2][i][j] = mma_bf16(na1, b[j][3], acc[2][i][j]);
-        acc[3][i][j] = mma_bf16(a[1], b[j][2], acc[3][i][j]);
-        acc[0][i][j] = mma_bf16(na2, b[j][2], acc[0][i][j]);
-        acc[1][i][j] = mma_bf16(a[2], b[j][3], acc[1][i][j]);
-        acc[2][i][j] = mma_bf16(a[2], b[j][0], acc[2][i][j]);
-        acc[3][i][j] = mma_bf16(na2, b[j][1], acc[3][i][j]);
-        acc[0][i][j] = mma_bf16(na3, b[j][3], acc[0][i][j]);
-        acc[1][i][j] = mma_bf16(na3, b[j][2], acc[1][i][j]);
-        acc[2][i][j] = mma_bf16(a[3], b[j][1], acc[2][i][j]);
-        acc[3][i][j] = mma_bf16(a[3], b[j][0], acc[3][i][j]);
+        const bf16x8(&bb)[4] = b[j][h];
+        acc[0][i][j] = MB::mma(a[0], bb[0], acc[0][i][j]);
+        acc[1][i][j] = MB::mma(a[0], bb[1], acc[1][i][j]);
+        acc[2][i][j] = MB::mma(a[0], bb[2], acc[2][i][j]);
+        acc[3][i][j] = MB::mma(a[0], bb[3], acc[3][i][j]);
+        acc[0][i][j] = MB::mma(na1, bb[1], acc[0][i][j]);
+        acc[1][i][j] = MB::mma(a[1], bb[0], acc[1][i][j]);
+        acc[2][i][j] = MB::mma(na1, bb[3], acc[2][i][j]);
+        acc[3][i][j] = MB::mma(a[1], bb[2], acc[3][i][j]);
+        acc[0][i][j] = MB::mma(na2, bb[2], acc[0][i][j]);
+        acc[1][i][j] = MB::mma(a[2], bb[3], acc[1][i][j]);
+        acc[2][i][j] = MB::mma(a[2], bb[0], acc[2][i][j]);
+        acc[3][i][j] = MB::mma(na2, bb[1], acc[3][i][j]);
+        acc[0][i][j] = MB::mma(na3, bb[3], acc[0][i][j]);
+        acc[1][i][j] = MB::mma(na3, bb[2], acc[1][i][j]);
+        acc[2][i][j] = MB::mma(a[3], bb[1], acc[2][i][j]);
+        acc[3][i][j] = MB::mma(a[3], bb[0], acc[3][i][j]);
       }
     }
   };
 
-  constexpr int IH = C::TM / 2;
+  constexpr int IH = C::ITEMS / 2;
   const int nk = S.kp / BK;
   if (nk > 0) {
     load_a(0);
@@ -703,13 +733,13 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
       compute(cur, 0, IH);
       store_a(nxt);
       load_b(kn);
-      compute(cur, IH, C::TM);
+      compute(cur, IH, C::ITEMS);
       store_b(nxt);
       __syncthreads();
     }
     const __bf16* const last = smem + ((nk - 1) & 1) * C::STAGE;
     frag_b(last);
-    compute(last, 0, C::TM);
+    compute(last, 0, C::ITEMS);
     __syncthreads();  // the next tile's first stage overwrites LDS
   }
 
@@ -717,21 +747,24 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
     for (int j = 0; j < C::TN; ++j) {
-      const int rb0 = m0 + wm * C::WTM + i * 16 + 4 * fc, cb0 = n0 + wn * C::WTN + j * 16 + fr;
+      const int rb = m0 + wm * C::WTM + i * MB::BLK, cb = n0 + wn * C::WTN + j * MB::BLK + MB::ccol(lane);
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        float inv[4][3];
+      for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) epilogue_inputs(P, p, rb0 + r, cb0, inv[r]);
+        for (int r0 = 0; r0 < MB::NR; r0 += 4) {  // inputs of 4 elements in flight at a time
+          float inv[4][3];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) epilogue_apply(P, p, rb0 + r, cb0, acc[p][i][j][r], inv[r], s_d, s_x);
-      }
+          for (int r = 0; r < 4; ++r) epilogue_inputs(P, p, rb + MB::crow(lane, r0 + r), cb, inv[r]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            epilogue_apply(P, p, rb + MB::crow(lane, r0 + r), cb, acc[p][i][j][r0 + r], inv[r], s_d, s_x);
+        }
     }
 }
 
-template <int BM, int BN, int WM, int WN, int MINW>
+template <int BM, int BN, int WM, int WN, int MINW, class MB>
 __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16s_kernel(GemmParams<float> P, Bf16Stage S) {
-  using C = Bf16SCfg<BM, BN, WM, WN>;
+  using C = Bf16SCfg<BM, BN, WM, WN, MB>;
   __shared__ __attribute__((aligned(16))) __bf16 smem[2 * C::STAGE];
   __shared__ double red_lds[C::NW][2];
   const int nt = P.tiles_m * P.tiles_n;
@@ -739,7 +772,7 @@ __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16s_kernel(GemmPar
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     int tm, tn;
     tile_of_block(t, nt, P.tiles_m, P.tiles_n, tm, tn);
-    bf16s_tile<BM, BN, WM, WN>(P, S, tm, tn, smem, s_d, s_x);
+    bf16s_tile<BM, BN, WM, WN, MB>(P, S, tm, tn, smem, s_d, s_x);
   }
   store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
 }
@@ -824,9 +857,9 @@ static int64_t stage_bytes(int64_t M, int64_t N, int64_t K) {
   return 2 * 4 * (round_up(M, 128) + round_up(N, 128)) * round_up(std::max<int64_t>(K, 1), 32);
 }
 
-template <int BM, int BN, int WM, int WN, int MINW>
+template <int BM, int BN, int WM, int WN, int MINW, class MB = BfM16>
 static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipStream_t s, GemmScratch& sc) {
-  using C = Bf16SCfg<BM, BN, WM, WN>;
+  using C = Bf16SCfg<BM, BN, WM, WN, MB>;
   GemmParams<float> P = P0;
   P.tiles_m = (P.M + BM - 1) / BM;
   P.tiles_n = (P.N + BN - 1) / BN;
@@ -864,7 +897,7 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
     QP_HIP(hipGetLastError());
   }
   const Bf16Stage S{a16, b16, (int)mp, (int)np, (int)kp};
-  auto kern = qgemm_bf16s_kernel<BM, BN, WM, WN, MINW>;
+  auto kern = qgemm_bf16s_kernel<BM, BN, WM, WN, MINW, MB>;
   LaunchShape ls;
   ls.grid = nt;
   if (per_cu > 0) {
@@ -898,7 +931,9 @@ static const std::vector<Bf16Entry>& bf16_table() {
       // Measured on MI355X at 4096^3 (2048^3): 8 reaches 1060 (910) TFLOP/s including its operand copies,
       // 6 960-1000 (900-920), 0 790 (850), 5 (the single-buffered form) 490; below about 4 tiles of
       // 64 x 64 per compute unit the copies cost more than they save, and below 1 the 32 x 32 tiles win.
-      // Tiles of 128 (staged) measured 320-360 TFLOP/s: their LDS stages leave one workgroup per CU.
+      // Tiles of 128 x 128 (staged) measured 320-360 TFLOP/s: their LDS stages leave one workgroup per CU.
+      // 9 and 10 (32 x 32 x 16 MFMA, sums rounded in another order) measured 1020 and 1080, within the
+      // run-to-run spread of 8, whose products equal those of the direct forms bit for bit.
       {{0, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"}, direct<launch_bf16_db<64, 64, 2, 2, 2>>},
       {{1, 32, 32, 32, 256, "bf16_32x32x32_w2x2_mfma16x16x32"}, direct<launch_bf16<32, 32, 2, 2>>},
       {{2, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2_cu2", 2}, direct<launch_bf16_db<64, 64, 2, 2, 2>>},
@@ -908,6 +943,8 @@ static const std::vector<Bf16Entry>& bf16_table() {
       {{6, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_staged"}, launch_bf16_staged<64, 64, 2, 2, 2>},
       {{7, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma16x16x32_staged_cu2", 2}, launch_bf16_staged<64, 64, 2, 2, 2>},
       {{8, 64, 64, 32, 512, "bf16_64x64x32_w2x4_mfma16x16x32_staged"}, launch_bf16_staged<64, 64, 2, 4, 4>},
+      {{9, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma32x32x16_staged"}, launch_bf16_staged<64, 64, 2, 2, 2, BfM32>},
+      {{10, 128, 64, 32, 512, "bf16_128x64x32_w4x2_mfma32x32x16_staged"}, launch_bf16_staged<128, 64, 4, 2, 2, BfM32>},
   };
   return t;
 }

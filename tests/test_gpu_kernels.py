@@ -178,12 +178,16 @@ def _bf16_cfgs(q, tag):
 
 
 def test_qgemm_bf16_staged_equals_direct_and_regrows_its_stage(qctx):
-    """The staged form (BF16 copies of the operands, zero-padded to whole tiles and K steps) computes the
-    same MFMA sequence over k as the forms that round while staging: identical outputs, epilogue included.
+    """The staged form (BF16 copies of the operands, zero-padded to whole tiles and K steps) with the
+    16 x 16 x 32 MFMA computes the same MFMA sequence over k as the forms that round while staging:
+    identical outputs, epilogue included.
     Products of growing and shrinking size reuse and regrow the context's stage buffer."""
     import paper_2605_01464_amd as q
 
-    staged, direct = _bf16_cfgs(q, "_staged"), _bf16_cfgs(q, "_db")
+    # (the 32 x 32 x 16 MFMA splits each 32-k step in two: its sums round differently, and the
+    # every-configuration test bounds it instead)
+    staged = [c for c in _bf16_cfgs(q, "_staged") if c in _bf16_cfgs(q, "mfma16x16x32")]
+    direct = _bf16_cfgs(q, "_db")
     assert staged and direct
     for seed, (M_, N_, K_) in enumerate([(130, 250, 70), (1, 1, 1), (700, 520, 333), (257, 129, 300), (64, 64, 32),
                                          (96, 40, 0)]):
