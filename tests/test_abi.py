@@ -66,6 +66,20 @@ def test_batched_configuration_table_without_gpu():
     assert all(nm.startswith(("batched_f32_", "batched_sync_f32_")) for nm in names)
 
 
+def test_bf16_product_configuration_table_without_gpu():
+    """The BF16 product forms the library picks without tuning sit where it expects them: index 8, the
+    staged 64 x 64 tile with 8 waves (1024 or more 64 x 64 output tiles); 0, the direct double-buffered
+    64 x 64 tile (256 to 1023); 1, the single-buffered 32 x 32 tile (fewer)."""
+    import paper_2605_01464_amd as q
+
+    gp = q.GEMM_PREC["bf16"]
+    names = [q.qpinv_tile_config_name(gp, c) for c in range(q.qpinv_num_tile_configs(gp))]
+    assert names[8] == "bf16_64x64x32_w2x4_mfma16x16x32_staged"
+    assert names[0] == "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"
+    assert names[1] == "bf16_32x32x32_w2x2_mfma16x16x32"
+    assert len(set(names)) == len(names) and all(nm.startswith("bf16_") for nm in names)
+
+
 # ------------------------------------------------------------------ stop-rule controller (host logic)
 def test_controller_dx_abs_and_rel():
     import paper_2605_01464_amd as q
