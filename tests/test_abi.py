@@ -66,7 +66,7 @@ def test_batched_configuration_table_without_gpu():
     assert all(nm.startswith(("batched_f32_", "batched_sync_f32_")) for nm in names)
 
 
-def test_bf16_product_configuration_table_without_gpu():
+def test_product_configuration_tables_without_gpu():
     """The BF16 product forms the library picks without tuning sit where it expects them: index 8, the
     staged 64 x 64 tile with 8 waves (1024 or more 64 x 64 output tiles); 0, the direct double-buffered
     64 x 64 tile (256 to 1023); 1, the single-buffered 32 x 32 tile (fewer)."""
@@ -78,6 +78,11 @@ def test_bf16_product_configuration_table_without_gpu():
     assert names[0] == "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"
     assert names[1] == "bf16_32x32x32_w2x2_mfma16x16x32"
     assert len(set(names)) == len(names) and all(nm.startswith("bf16_") for nm in names)
+    # FP32 / FP64: 5 / 4 (64 x 64 double-buffered tiles) from 1024 tiles of 64 x 64, 6 / 1 below
+    f32 = [q.qpinv_tile_config_name(q.GEMM_PREC["f32"], c) for c in (5, 6)]
+    f64 = [q.qpinv_tile_config_name(q.GEMM_PREC["f64"], c) for c in (4, 1)]
+    assert f32 == ["f32_64x64x16_w2x2_mfma32_db", "f32_32x32x16_w2x2_mfma16_db"]
+    assert f64 == ["f64_64x64x8_w4x4_mfma16_db", "f64_32x32x16_w2x2_mfma16"]
 
 
 # ------------------------------------------------------------------ stop-rule controller (host logic)
