@@ -100,6 +100,32 @@ def measured_traffic(config_name):
     return None
 
 
+def ladder_breakdown(q, ctx, torch, A, kw):
+    """One more (untimed) solve with every product bracketed by HIP events on its stream: product time
+    and rate per precision (BF16 including its operand copies); the rest of the solve is norms, power
+    steps, stop rules and copies between precisions."""
+    ctx.set("gemm_timing", 1)
+    q.qpinv_gemm_stats(ctx.handle)  # reset
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    q.solve(ctx, A, **kw)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t
+    _, rows = q.qpinv_gemm_stats(ctx.handle)
+    ctx.set("gemm_timing", 0)
+    names = {q.GEMM_PREC[k]: k for k in ("f64", "f32", "bf16")}
+    byp = {}
+    for r in rows:
+        e = byp.setdefault(names[r["prec"]], {"launches": 0, "ms": 0.0, "flops": 0.0})
+        e["launches"] += r["launches"]
+        e["ms"] += r["ms"]
+        e["flops"] += r["flops"]
+    for e in byp.values():
+        e["tflops"] = e["flops"] / (e["ms"] * 1e-3) / 1e12 if e["ms"] > 0 else None
+    return {"products_by_precision": byp, "one_solve_ms_with_events": 1e3 * t_one,
+            "non_product_ms": 1e3 * t_one - sum(e["ms"] for e in byp.values())}
+
+
 def section_lorenz(q, ctx, torch):
     import qsynth
 
@@ -388,6 +414,8 @@ def main() -> int:
                 res[f"{label}:{method}"] = {"pinv_per_s": 1.0 / dt, "ms": 1e3 * dt, "iters_bf16": inf3["iters_bf16"],
                                             "iters_f32": inf3["iters_f32"], "iters_f64": inf3["iters_f64"],
                                             "E_rel_fp64": Er}
+                if label.startswith("mixed"):
+                    res[f"{label}:{method}"].update(ladder_breakdown(q, ctx, torch, Ain, kw))
         ctx.set("f64_refined", 1)
         ctx.set("finish_method", 0)
         out["mixed_vs_plain"] = {"workload": "4096x4096 quaternion, cond 1e3, geometric spectrum, unit-variance "
