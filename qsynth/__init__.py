@@ -60,6 +60,14 @@ def gaussian(seed: int, m: int, n: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((4, m, n))
 
 
+def low_rank_gaussian(seed: int, m: int, n: int, r: int) -> np.ndarray:
+    """(4,m,n) planes of G H, G (m x r) and H (r x n) with components iid N(0,1) (streams seed, seed + 1):
+    rank r almost surely.  The product is formed through the complex adjoint (a homomorphism)."""
+    G = gaussian(seed, m, r)
+    H = gaussian(seed + 1, r, n)
+    return _from_cplx(_to_cplx(G) @ _to_cplx(H))
+
+
 def stiefel(seed: int, m: int, r: int) -> np.ndarray:
     """m x r quaternion matrix with orthonormal columns (U^H U = I_r): polar factor of a Gaussian."""
     if r > m:
