@@ -442,6 +442,23 @@ def spectral_e1_rel(s, alpha, method, order, count) -> np.ndarray:
     return np.sqrt(np.sum((s * rho) ** 2, axis=1) / np.sum(s * s))
 
 
+def spectral_dx_iterations(s, alpha, method, order, tol, max_iter=500) -> int:
+    """Smallest j >= 1 with ||X_j - X_{j-1}||_F < tol in exact arithmetic (the stopping test of
+    Algorithms 1-3), max_iter + 1 if never.  X_j - X_{j-1} = V diag((rho^{(j-1)} - rho^{(j)}) / s) U^H
+    and V, U have orthonormal columns, so its Frobenius norm is that of the diagonal."""
+    s = np.asarray(s, dtype=np.float64)
+    g = scalar_residual_map(method, order)
+    rho = 1.0 - alpha * s ** 2
+    for j in range(1, max_iter + 1):
+        rn = g(rho)
+        if not np.all(np.isfinite(rn)) or np.max(np.abs(rn)) > 1e30:
+            return max_iter + 1
+        if math.sqrt(np.sum(((rho - rn) / s) ** 2)) < tol:
+            return j
+        rho = rn
+    return max_iter + 1
+
+
 def spectral_iterations(s, alpha, method, order, tol, max_iter=500) -> int:
     """Smallest j >= 1 with E1_rel(X_j) <= tol in exact arithmetic (max_iter + 1 if never)."""
     s = np.asarray(s, dtype=np.float64)

@@ -265,6 +265,24 @@ def test_spectral_iteration_count_matches_run():
         assert r.iters == J, (method, r.iters, J)
 
 
+def test_spectral_dx_iteration_count_matches_run():
+    """The exact-arithmetic count under the paper's absolute stopping test against the step-by-step
+    oracle run with that test, several scalings, on a tall (left residual, I_n) and a wide (right
+    residual, I_m) matrix of full rank.  (Where the residual keeps the eigenvalue 1 on a null space -- the
+    larger side, or any side of a rank-deficient matrix -- the update multiplies rounding there by the
+    order p every step, so a tight absolute test may never be met: not a model case.)"""
+    s = qsynth.geometric(15, 3.0, 3e-2)
+    for (m, n, side) in [(20, 15, "left"), (15, 20, "right")]:
+        inst = qsynth.small_spectral_instance(62, m, n, s)
+        for method, order in [("ns", None), ("qsai", None), ("qhpi19", None), ("qrapid", 5), ("hpi", 3)]:
+            for mu in (1.0, 0.6, 1.7):
+                alpha = mu / s[0] ** 2
+                J = M.spectral_dx_iterations(s, alpha, method, order, 1e-9)
+                r = M.solve(inst["A"], method, order, alpha=alpha, tol=1e-9, stop="dx_abs", side=side)
+                assert r.iters == J, (m, n, method, mu, r.iters, J)
+                assert r.dx[-1] < 1e-9 <= (r.dx[-2] if len(r.dx) > 1 else np.inf)
+
+
 # ------------------------------------------------------------------ Proposition 3.1 and Theorem 1
 @pytest.mark.parametrize("method,order", [("ns", None), ("qsai", None), ("qhpi19", None), ("qrapid", 2)])
 def test_proposition_invariants(method, order):
