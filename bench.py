@@ -141,7 +141,8 @@ PAPER_TABLES = [
      {"qsai": (1.844, 7), "qrapid": (4.089, 5), "qhpi19": (1.752, 6), "ns": (7.126, 60)}),
     ("1000x1000 rank-deficient (rank 500)", 1000, 1000, "rank500",
      {"qsai": (8.789, 10), "qrapid": (16.78, 6), "qhpi19": (8.570, 8), "ns": (32.73, 73)}),
-    ("800x800 Gaussian (Example 3)", 800, 800, "gaussian", {"qhpi19": (6.188, 8), "qsai": (6.594, 10)}),
+    ("800x800 Gaussian (Example 3)", 800, 800, "gaussian",
+     {"qhpi19": (6.188, 8), "qsai": (6.594, 10), "hpi:19": (13.87, 8), "hpi:10": (11.05, 10)}),
 ]
 
 
@@ -149,7 +150,8 @@ def section_paper_tables(q, ctx, torch, reps=3):
     """FP64 solves with the paper's stopping test ||X_{j+1} - X_j||_F < 1e-10 and alpha = 1/||A||_F^2
     (Tables 1-2; Example 3: 1/sigma_1^2 by power iteration, the paper's alpha being 1/sigma_1^2 of its
     own matrix); QRAPID with N = 5.  Inputs: planes iid N(0,1); the rank-deficient matrix is the product
-    of 1000 x 500 and 500 x 1000 Gaussian matrices (the paper does not give its construction)."""
+    of 1000 x 500 and 500 x 1000 Gaussian matrices (the paper does not give its construction).  Example 3
+    also times the unfactorized order-19 and order-10 iterations ("hpi:19", "hpi:10")."""
     import qsynth
 
     out = {"settings": "FP64 on the GPU; stop ||X_{j+1}-X_j||_F < 1e-10, max 500 updates; alpha = 1/||A||_F^2 "
@@ -159,8 +161,10 @@ def section_paper_tables(q, ctx, torch, reps=3):
         A = qsynth.gaussian(9000 + wi, m, n) if kind == "gaussian" else qsynth.low_rank_gaussian(9000 + wi, m, n, 500)
         Ad = torch.from_numpy(A).cuda()
         scaling = "power" if "Example 3" in name else "frob"
-        for method, (t_paper, it_paper) in methods.items():
-            kw = dict(method=method, order=5 if method == "qrapid" else None, scaling=scaling, tol=1e-10,
+        for key, (t_paper, it_paper) in methods.items():
+            # "hpi:p": the unfactorized hyperpower iteration of order p (Horner, p products per update)
+            method, order = (key.split(":")[0], int(key.split(":")[1])) if ":" in key else (key, None)
+            kw = dict(method=method, order=5 if method == "qrapid" else order, scaling=scaling, tol=1e-10,
                       max_iter=500, stop="dx_abs", precision="f64")
             X, info = q.solve(ctx, Ad, **kw)  # warm-up (and tile tuning)
             torch.cuda.synchronize()
@@ -172,7 +176,7 @@ def section_paper_tables(q, ctx, torch, reps=3):
                 ts.append(time.perf_counter() - t)
             dt = float(np.median(ts))
             Ea, Er = q.residuals(ctx, Ad, X)
-            out["results"][f"{name}:{method}"] = {
+            out["results"][f"{name}:{key}"] = {
                 "ms": 1e3 * dt, "pinv_per_s": 1.0 / dt, "iters": info["iters"], "E1_abs": Ea[0], "E1_rel": Er[0],
                 "status": info["status"], "paper_s": t_paper, "paper_iters": it_paper, "speedup_vs_paper": t_paper / dt}
         del Ad
