@@ -180,6 +180,25 @@ def section_paper_tables(q, ctx, torch, reps=3):
                 "ms": 1e3 * dt, "pinv_per_s": 1.0 / dt, "iters": info["iters"], "E1_abs": Ea[0], "E1_rel": Er[0],
                 "status": info["status"], "paper_s": t_paper, "paper_iters": it_paper, "speedup_vs_paper": t_paper / dt}
         del Ad
+    # growth with n (the paper's scalability figure plots CPU time and E1..E4 against n without printing
+    # the values): square Gaussian stand-ins, same settings, one timed solve after a warm-up
+    sweep = {}
+    for n in (500, 1000, 2000, 3000):
+        Ad = torch.from_numpy(qsynth.gaussian(9200 + n, n, n)).cuda()
+        for method in ("qhpi19", "qsai"):
+            kw = dict(method=method, scaling="frob", tol=1e-10, max_iter=500, stop="dx_abs", precision="f64")
+            q.solve(ctx, Ad, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            X, info = q.solve(ctx, Ad, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            Ea, Er = q.residuals(ctx, Ad, X)
+            flops = 7 * 32.0 * n ** 3 * info["iters"] if method == "qhpi19" else None
+            sweep[f"{n}:{method}"] = {"ms": 1e3 * dt, "iters": info["iters"], "E_rel": Er,
+                                      "tflops": flops / dt / 1e12 if flops else None}
+        del Ad
+    out["growth_with_n"] = sweep
     return out
 
 
