@@ -159,6 +159,24 @@ def test_qgemm_square_relative_error_le_1e6(qctx, n):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_qgemm_bf16_full_size_sampled_rows(qctx, n):
+    """Square BF16-operand product at the ladder's sizes in the configuration the library picks there
+    (the staged form): relative Frobenius error vs the exact product of the BF16-rounded inputs, on 24
+    sampled rows, within FP32 accumulation (<= 1e-6)."""
+    import torch
+    import paper_2605_01464_amd as q
+
+    g = torch.Generator(device="cuda").manual_seed(410)
+    A = torch.randn((4, n, n), device="cuda", generator=g)
+    B = torch.randn((4, n, n), device="cuda", generator=g)
+    C = q.qgemm(qctx, A, B, gemm_prec="bf16")
+    rows = np.random.default_rng(n + 1).choice(n, 24, replace=False)
+    ref = Q.qmul(round_bf16(A[:, rows, :].cpu().numpy()), round_bf16(B.cpu().numpy()))
+    err = np.linalg.norm(C[:, rows, :].double().cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-6, err
+
+
 def round_bf16(x):
     """Round float32 values to the nearest bfloat16 (ties to even), returned as float64."""
     u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
