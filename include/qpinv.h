@@ -221,7 +221,8 @@ int qpinv_residuals(qpinv_ctx* ctx, const qpinv_qmat* A, const qpinv_qmat* X, do
  * GEMM_BF16 rounds the FP32 operands to BF16 (nearest even) and accumulates in FP32.  Its large
  * products (1024 or more 64 x 64 output tiles, or the "_staged" configurations) first copy the
  * operands into a BF16 stage buffer that the context owns: 2 * 4 * (Mp + Np) * Kp bytes, Mp and Np
- * the row counts of A and of B^T rounded up to 128, Kp = K rounded up to 32.  The buffer grows on
+ * the row counts of A and of B^T rounded up to 128, Kp = K rounded up to 32 (a product whose copy of one
+ * operand would reach 2^31 bytes takes the direct form instead, with no copies).  The buffer grows on
  * demand (the stream is synchronised first) and is freed by qpinv_finalize; products on one context
  * share it, so they must not run concurrently on different streams.
  * Errors: EINVAL, EHIP, ENOMEM (stage buffer). */

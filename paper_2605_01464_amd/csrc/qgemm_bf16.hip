@@ -866,8 +866,10 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
   const int64_t nt = (int64_t)P.tiles_m * P.tiles_n;
   if (nt == 0) return 0;
   const int64_t mp = round_up(P.M, 128), np = round_up(P.N, 128), kp = round_up(P.K, 32);
+  // copies beyond the 32-bit offsets of the buffer loads (about 16k x 16k): the direct form, which rounds
+  // while staging and takes any size, computes the same products
   if (4 * std::max(mp, np) * std::max<int64_t>(kp, 32) * 2 >= (int64_t(1) << 31))
-    throw Error(-1, "qgemm: BF16 operand copies exceed 2^31 bytes per operand");
+    return launch_bf16_db<64, 64, 2, 2, 2>(P0, 0, s);
   const size_t need = (size_t)stage_bytes(P.M, P.N, P.K);
   if (sc.stage_bytes < need) {
     // grow the stage buffer (kernels of earlier products on the stream may still read it)

@@ -177,6 +177,28 @@ def test_qgemm_bf16_full_size_sampled_rows(qctx, n):
     assert err <= 1e-6, err
 
 
+def test_qgemm_bf16_beyond_the_staged_copy_limit(qctx):
+    """A 16512 x 256 x 16384 BF16 product: 1032 output tiles of 64 x 64 select the staged form, whose copy
+    of A would reach 2^31 bytes; the library computes it with the direct form instead (sampled rows
+    against the exact product of the rounded inputs, within the random-walk scale u32 sqrt(4K) of FP32
+    accumulation over 4K = 65536 terms)."""
+    import torch
+    import paper_2605_01464_amd as q
+
+    M_, N_, K_ = 16512, 256, 16384
+    assert 4 * M_ * K_ * 2 >= 2 ** 31 and ((M_ + 63) // 64) * ((N_ + 63) // 64) >= 1024
+    g = torch.Generator(device="cuda").manual_seed(420)
+    A = torch.randn((4, M_, K_), device="cuda", generator=g)
+    B = torch.randn((4, K_, N_), device="cuda", generator=g)
+    C = q.qgemm(qctx, A, B, gemm_prec="bf16")
+    rows = np.random.default_rng(7).choice(M_, 8, replace=False)
+    ref = Q.qmul(round_bf16(A[:, rows, :].cpu().numpy()), round_bf16(B.cpu().numpy()))
+    err = np.linalg.norm(C[:, rows, :].double().cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 2.0 ** -24 * np.sqrt(4 * K_), err
+    del A, B, C
+    torch.cuda.empty_cache()
+
+
 def round_bf16(x):
     """Round float32 values to the nearest bfloat16 (ties to even), returned as float64."""
     u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
