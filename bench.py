@@ -314,7 +314,7 @@ def main() -> int:
                     help="skip the FP64 solves of the paper's own table workloads")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU (the library has no multi-GPU path); --gpus must be 1"}))
         return 2
 
     import torch
