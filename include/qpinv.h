@@ -147,7 +147,9 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
  * threshold, default 1e-2), mixed_rnorm_steps,
  * max_bf16_iters, gemm_timing (0/1), gemm_cfg_f64 / gemm_cfg_f32 / gemm_cfg_bf16 (tile configuration
  * index used for every product of that precision, -1 = tuned or heuristic choice), batched_cfg
- * (configuration of qpinv_solve_batched, -1 = tuned or default), verbose (0/1).
+ * (configuration of qpinv_solve_batched, -1 = tuned or default), batched_dynamic (phase-synchronous
+ * batched form: 1 (default) workgroups claim work items from a counter, 0 workgroup g takes items
+ * g, g + G, ...; the results are the same), verbose (0/1).
  * Errors: EINVAL for an unknown key or out-of-range value. */
 int qpinv_set_option(qpinv_ctx* ctx, const char* key, double value);
 

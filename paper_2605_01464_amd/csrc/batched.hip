@@ -810,6 +810,9 @@ struct SParams {
   Coef k;
   unsigned long long* trace;  // optional: workgroup 0 stamps wall_clock64() after every grid barrier
   int trace_cap;
+  unsigned int* qctr;  // per phase of the launch: the next work item (zeroed before the launch)
+  int qctr_cap;        // phases with a counter; later phases (and dyn == 0) deal items g, g + G, ...
+  int dyn;
 };
 
 constexpr int SYNC_MAX = 2048;   // matrices per launch (the per-phase tile prefix lives in LDS)
@@ -1122,6 +1125,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
   __shared__ int pref[SYNC_MAX + 1];
   __shared__ int s_mn[SYNC_MAX];  // m | n << 16 per matrix
   __shared__ int s_total;
+  __shared__ int s_item;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const unsigned int G = gridDim.x;
@@ -1245,7 +1249,28 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
       __syncthreads();
       const int total = s_total;
       if (ph == 1 && total == 0) return;  // nothing active: every workgroup sees the same states
-      for (int item = blockIdx.x; item < total; item += G) {
+      // Work items of this phase.  Dynamic: a workgroup takes the next unclaimed item from the phase's
+      // counter (asking for the following one as it starts an item, so the atomic's latency hides
+      // behind the tile), which balances items of different K; static: items g, g + G, ...  Either way
+      // every item is computed once, by code that does not depend on which workgroup runs it.
+      const int seq = it * (np + 1) + (ph - 1);
+      const bool dyn = P.dyn != 0 && seq < P.qctr_cap;
+      unsigned int pre = 0u;  // thread 0: the item claimed for after the current one
+      auto first_item = [&]() -> int {
+        if (!dyn) return (int)blockIdx.x;
+        if (tid == 0) s_item = (int)__hip_atomic_fetch_add(&P.qctr[seq], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        return s_item;
+      };
+      auto next_item = [&](int item) -> int {
+        if (!dyn) return item + (int)G;
+        __syncthreads();  // every thread has read s_item
+        if (tid == 0) s_item = (int)pre;
+        __syncthreads();
+        return s_item;
+      };
+      for (int item = first_item(); item < total; item = next_item(item)) {
+        if (dyn && tid == 0) pre = __hip_atomic_fetch_add(&P.qctr[seq], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // matrix of this item: last b with pref[b] <= item
         int lo = 0, hi = P.count;
         while (hi - lo > 1) {
@@ -1548,9 +1573,10 @@ __global__ void zero_int_kernel(int* p) {
 }
 
 // timeout flag, barrier words and a status sentinel for every matrix (overwritten when it retires)
-__global__ void sync_reset_kernel(unsigned int* bar, BInfo* info, int count) {
+__global__ void sync_reset_kernel(unsigned int* bar, BInfo* info, int count, unsigned int* qctr, int qcap) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < 4) bar[i] = 0u;
+  for (int k = i; k < qcap; k += gridDim.x * blockDim.x) qctr[k] = 0u;
   for (int b = i; b < count; b += gridDim.x * blockDim.x) {
     info[b].iters = 0;
     info[b].returned = 0;
@@ -1612,6 +1638,9 @@ static void build_sync(BatchedState& st, const BKey& key, int64_t pool_cap, int6
   BInfo* d_info = static_cast<BInfo*>(dev_alloc(st, sizeof(BInfo) * count));
   LState* d_st = static_cast<LState*>(dev_alloc(st, sizeof(LState) * count));
   unsigned int* d_bar = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * 4));
+  // one item counter per phase: (max_iter + 2) passes of at most 32 phases
+  const int qcap = (key.max_iter + 2) * 32;
+  unsigned int* d_qctr = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * (size_t)qcap));
   double* d_alpha = static_cast<double*>(dev_alloc(st, sizeof(double) * count));
   float* pool = static_cast<float*>(dev_alloc(st, sizeof(float) * (size_t)pool_cap));
   double* partial = static_cast<double*>(dev_alloc(st, sizeof(double) * (size_t)part_cap));
@@ -1640,12 +1669,16 @@ static void build_sync(BatchedState& st, const BKey& key, int64_t pool_cap, int6
   P.k = make_coef();
   P.trace = trace;
   P.trace_cap = kTraceCap;
+  P.qctr = d_qctr;
+  P.qctr_cap = qcap;
+  P.dyn = key.dyn;
 
   hipStream_t s = st.stream;
   QP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   QP_HIP(hipMemcpyAsync(d_desc, st.h_desc, sizeof(BDesc) * count, hipMemcpyHostToDevice, s));
   QP_HIP(hipMemcpyAsync(d_alpha, st.h_alpha, sizeof(double) * count, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(sync_reset_kernel, dim3((count + 255) / 256 + 1), dim3(256), 0, s, d_bar, d_info, count);
+  hipLaunchKernelGGL(sync_reset_kernel, dim3((count + 255) / 256 + 1), dim3(256), 0, s, d_bar, d_info, count, d_qctr,
+                     qcap);
   ent.sfn(P, st.grid, s);
   QP_HIP(hipMemcpyAsync(st.h_info, d_info, sizeof(BInfo) * count, hipMemcpyDeviceToHost, s));
   QP_HIP(hipMemcpyAsync(st.h_order, d_bar, sizeof(unsigned int) * 4, hipMemcpyDeviceToHost, s));

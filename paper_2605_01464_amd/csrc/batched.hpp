@@ -30,12 +30,13 @@ struct BInfo {
 // Everything the captured graph bakes in.
 struct BKey {
   int count = 0, D = 0, cfg = 0, method = 0, stop = 0, max_iter = 0, scaling = 0, power_steps = 0;
+  int dyn = 1;  // phase-synchronous form: workgroups take work items from a counter (0: items g, g + G, ...)
   double tol = 0.0;
   unsigned long long seed = 0;
   bool operator==(const BKey& o) const {
     return count == o.count && D == o.D && cfg == o.cfg && method == o.method && stop == o.stop &&
-           max_iter == o.max_iter && scaling == o.scaling && power_steps == o.power_steps && tol == o.tol &&
-           seed == o.seed;
+           max_iter == o.max_iter && scaling == o.scaling && power_steps == o.power_steps && dyn == o.dyn &&
+           tol == o.tol && seed == o.seed;
   }
 };
 

@@ -96,6 +96,9 @@ void set_option(qp::Ctx& c, const std::string& key, double v) {
   } else if (key == "batched_cfg") {
     need(v == -1 || (v >= 0 && v < (double)qp::batched_num_configs() && v == (int)v));
     c.opt.batched_cfg = (int)v;
+  } else if (key == "batched_dynamic") {
+    need(v == 0 || v == 1);
+    c.opt.batched_dynamic = (int)v;
   } else if (key == "verbose") {
     c.opt.verbose = v != 0;
   } else {

@@ -1252,6 +1252,7 @@ int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A,
   key.scaling = scaling == QPINV_ALPHA_GIVEN ? 2 : 0;
   key.power_steps = c.opt.power_steps;
   key.seed = c.opt.power_seed;
+  key.dyn = c.opt.batched_dynamic;
   if (!c.batched) c.batched = new BatchedState();
   std::vector<BInfo> out;
   // tile configuration: tuned per batch signature (size histogram) when autotuning is on

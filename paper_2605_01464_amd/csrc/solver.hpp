@@ -39,6 +39,7 @@ struct Options {
   int gemm_timing = 0;
   int force_cfg[3] = {-1, -1, -1};  // per product precision: tile configuration for every product, -1 = choose
   int batched_cfg = -1;             // batched kernel configuration, -1 = tuned or default
+  int batched_dynamic = 1;          // phase-synchronous batched form: dynamic (1) or static (0) item dealing
 };
 
 struct MlpState;      // scaling network (mlp.hip)
