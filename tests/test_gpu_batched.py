@@ -147,3 +147,27 @@ def test_sync_equals_queue_bitwise(qctx, small_batch, batched_form):
     Xs_queue, _ = q.solve_batched(qctx, As, "qhpi19", **kw)
     for a, b in zip(Xs_sync, Xs_queue):
         assert torch.equal(a, b)
+
+
+def test_sync_item_dealing_does_not_change_results(qctx, small_batch, batched_form):
+    """Work items claimed from the phase counter (default) or dealt g, g + G, ...: every tile is computed by
+    the same code on the same operands and the per-matrix sums run in tile order, so the converged
+    iterates, iteration counts and statuses agree bit for bit."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    if batched_form == "queue":
+        pytest.skip("item dealing exists in the phase-synchronous forms only")
+    As = [to_dev(A, "f32") for A in small_batch]
+    try:
+        out = {}
+        for dyn in (1, 0):
+            qctx.set("batched_dynamic", dyn)
+            Xs, infos = q.solve_batched(qctx, As, "qhpi19", tol=1e-6, stop="guarded")
+            out[dyn] = (Xs, [(i["iters"], i["status"]) for i in infos])
+    finally:
+        qctx.set("batched_dynamic", 1)
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
