@@ -597,8 +597,6 @@ struct Bf16Stage {
   int mp, np, kp;
 };
 
-typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
-
 template <int BM, int BN, int WM, int WN, class MB>
 __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf16Stage& S, int tm, int tn,
                                            __bf16* smem, double& s_d, double& s_x) {
@@ -635,20 +633,20 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) acc[p][i][j] = Acc{};
 
-  u32x4v ra[4][C::NA], rb[4][C::NB];
+  u32x4 ra[4][C::NA], rb[4][C::NB];
   auto load_a = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int t = 0; t < C::NA; ++t)
-        ra[q][t] = __builtin_bit_cast(u32x4v, __builtin_amdgcn_raw_buffer_load_b128(srcA, offa[t], q * psa + 2 * k0, 0));
+        ra[q][t] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(srcA, offa[t], q * psa + 2 * k0, 0));
   };
   auto load_b = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int t = 0; t < C::NB; ++t)
-        rb[q][t] = __builtin_bit_cast(u32x4v, __builtin_amdgcn_raw_buffer_load_b128(srcB, offb[t], q * psb + 2 * k0, 0));
+        rb[q][t] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(srcB, offb[t], q * psb + 2 * k0, 0));
   };
   auto store_a = [&](__bf16* As) __attribute__((always_inline)) {
 #pragma unroll
@@ -656,7 +654,7 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
 #pragma unroll
       for (int t = 0; t < C::NA; ++t) {
         const int c = tid + t * C::NT;
-        if (C::ACH % C::NT == 0 || c < C::ACH) *reinterpret_cast<u32x4v*>(&As[db_off(q * BM + c / 4, c % 4)]) = ra[q][t];
+        if (C::ACH % C::NT == 0 || c < C::ACH) *reinterpret_cast<u32x4*>(&As[db_off(q * BM + c / 4, c % 4)]) = ra[q][t];
       }
   };
   auto store_b = [&](__bf16* As) __attribute__((always_inline)) {
@@ -666,7 +664,7 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
 #pragma unroll
       for (int t = 0; t < C::NB; ++t) {
         const int c = tid + t * C::NT;
-        if (C::BCH % C::NT == 0 || c < C::BCH) *reinterpret_cast<u32x4v*>(&Bs[db_off(q * BN + c / 4, c % 4)]) = rb[q][t];
+        if (C::BCH % C::NT == 0 || c < C::BCH) *reinterpret_cast<u32x4*>(&Bs[db_off(q * BN + c / 4, c % 4)]) = rb[q][t];
       }
   };
 
