@@ -394,6 +394,28 @@ def main() -> int:
         "input_generation_s": t_gen,
     }
 
+    XL = None
+    if not args.no_learned:
+        # the learned initial scaling on the same workload, reported beside the plain method's value
+        from paper_2605_01464_amd import learned as L
+
+        L.load(ctx)
+        XL = torch.empty_like(X)
+        lkw = dict(solve_kw, scaling="learned", X=XL)
+        q.solve(ctx, A, **lkw)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            _, linfo = q.solve(ctx, A, **lkw)
+        torch.cuda.synchronize()
+        dtl = (time.perf_counter() - t) / args.steps
+        _, er_plain = q.residuals(ctx, A, X)
+        _, er_learned = q.residuals(ctx, A, XL)
+        out["learned_alpha_same_workload"] = {
+            "pinv_per_s": 1.0 / dtl, "iters": linfo["iters"], "mu": linfo["mu_used"],
+            "fallback_used": linfo["fallback_used"], "plain_pinv_per_s": value, "plain_iters": info["iters"],
+            "E_rel_plain": er_plain, "E_rel_learned": er_learned}
+
     if not args.no_gemm:
         # standalone quaternion products: square sizes and the solver's own shapes, per precision
         out["qgemm_square"] = {}
@@ -602,6 +624,10 @@ def main() -> int:
         Xd = X.detach().cpu().double().numpy()
         Xc = Q.pinv_from_factors(inst["U"], inst["s"], inst["V"])
         out["rel_err_vs_rank1024_pinv"] = float(np.linalg.norm(Xd - Xc) / np.linalg.norm(Xc))
+        if XL is not None:
+            XLd = XL.detach().cpu().double().numpy()
+            out["learned_alpha_same_workload"]["rel_err_vs_rank1024_pinv"] = float(
+                np.linalg.norm(XLd - Xc) / np.linalg.norm(Xc))
         if mixed_inst is not None:
             # sampled rows of the default ladder's QHPI19 result (the mixed section's last) vs the exact inverse of
             # the FP32 input: relative residual of rows of A X - I, times the condition number
