@@ -518,6 +518,23 @@ def main() -> int:
                     res[f"{label}:{method}"].update(ladder_breakdown(q, ctx, torch, Ain, kw))
         ctx.set("f64_refined", 1)
         ctx.set("finish_method", 0)
+        if XL is not None:
+            # the ladder started from the learned scaling (the network was loaded with the headline's comparison)
+            X3L = torch.empty_like(X3)
+            kw = dict(method="qhpi19", order=None, scaling="learned", tol=1e-6, max_iter=100, stop="guarded",
+                      precision="mixed", X=X3L)
+            q.solve(ctx, A3, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.mixed_steps):
+                _, inf3 = q.solve(ctx, A3, **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / args.mixed_steps
+            Ea, Er = q.residuals(ctx, A3, X3L)
+            res["mixed_bf16_f32_f64_learned:qhpi19"] = {
+                "pinv_per_s": 1.0 / dt, "ms": 1e3 * dt, "iters_bf16": inf3["iters_bf16"], "iters_f32": inf3["iters_f32"],
+                "iters_f64": inf3["iters_f64"], "mu": inf3["mu_used"], "E_rel_fp64": Er}
+            del X3L
         out["mixed_vs_plain"] = {"workload": "4096x4096 quaternion, cond 1e3, geometric spectrum, unit-variance "
                                              "components (FP32 input), guarded stop tol 1e-6",
                                  "input_generation_s": t_g, "results": res}
