@@ -811,9 +811,11 @@ __global__ void __launch_bounds__(256) bf16_rows_kernel(const float* __restrict_
 }
 
 // out[q][n][k] = bf16(B[q][k][n]) inside the matrix, 0 in the padding (n < np, k < kp): one 32 (k) x 64 (n)
-// tile per workgroup through LDS, reads coalesced along n, writes 16 bytes (8 k) per lane.
+// tile per workgroup through LDS, reads along n (16 bytes a lane when vec: 16-byte aligned base, ldb and
+// psb), writes 16 bytes (8 k) per lane.
 __global__ void __launch_bounds__(256) bf16_transpose_kernel(const float* __restrict__ B, int64_t ldb, int64_t psb,
-                                                             int K, int N, __bf16* __restrict__ out, int np, int kp) {
+                                                             int K, int N, __bf16* __restrict__ out, int np, int kp,
+                                                             int vec) {
   __shared__ float tile[32][65];
   const int tk = kp / 32, tn = np / 64;
   const int64_t t = blockIdx.x;
@@ -822,12 +824,23 @@ __global__ void __launch_bounds__(256) bf16_transpose_kernel(const float* __rest
   const int k0 = (rest / tn) * 32, n0 = (rest % tn) * 64;
   const int tid = threadIdx.x;
   {
-    const int col = tid % 64, r0 = (tid / 64) * 8;
-    const int n = n0 + col;
+    // thread: columns n0 + 4 c .. +3 of rows k0 + r and k0 + r + 16
+    const int c = tid % 16, r = tid / 16, n = n0 + 4 * c;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + r0 + e;
-      tile[r0 + e][col] = (k < K && n < N) ? gload(B + q * psb, (int64_t)k * ldb + n) : 0.f;
+    for (int h = 0; h < 2; ++h) {
+      const int kr = r + 16 * h, k = k0 + kr;
+      floatx4 v = {0.f, 0.f, 0.f, 0.f};
+      if (k < K) {
+        const float* row = B + q * psb + (int64_t)k * ldb;
+        if (vec && n + 4 <= N) {
+          v = gload(reinterpret_cast<const floatx4*>(row + n), 0);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = n + e < N ? gload(row, n + e) : 0.f;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tile[kr][4 * c + e] = v[e];
     }
   }
   __syncthreads();
@@ -892,8 +905,9 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
                        (int)mp, (int)kp, vec_a);
     QP_HIP(hipGetLastError());
     const int64_t grid_t = 4 * (kp / 32) * (np / 64);
+    const int vec_b = (reinterpret_cast<uintptr_t>(P.B) & 15) == 0 && P.ldb % 4 == 0 && P.psb % 4 == 0;
     hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)grid_t), dim3(256), 0, s, P.B, P.ldb, P.psb, P.K, P.N, b16,
-                       (int)np, (int)kp);
+                       (int)np, (int)kp, vec_b);
     QP_HIP(hipGetLastError());
   }
   const Bf16Stage S{a16, b16, (int)mp, (int)np, (int)kp};
