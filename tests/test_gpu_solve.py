@@ -109,6 +109,30 @@ def test_small_workload_power_alpha(qctx):
     assert rel_fro(to_np(X), ro.X) <= 1e-12
 
 
+@pytest.mark.parametrize("dtype,shape", [("f64", (64, 48)), ("f32", (150, 97)), ("f64", (3, 3))])
+def test_frobenius_scaling_matches_oracle(qctx, example1, dtype, shape):
+    """Section 4's alpha = 1/||A||_F^2 (scaling FROB): the GPU's alpha_used equals the oracle's on the values the
+    GPU holds (FP32 inputs widened exactly), and the solve from it follows the oracle run from the same alpha."""
+    import paper_2605_01464_amd as q
+
+    if shape == (3, 3):
+        A = example1[0]
+    else:
+        A = np.random.default_rng(18).standard_normal((4,) + shape)
+    if dtype == "f32":
+        A = qsynth.round_f32(A)
+    a_ref = M.alpha_frobenius(A)
+    if shape == (3, 3):
+        assert a_ref == pytest.approx(1.0 / 532.0, rel=1e-15)
+    X, info = q.solve(qctx, to_dev(A, dtype), "qhpi19", scaling="frob", tol=1e-12 if dtype == "f64" else 1e-6,
+                      stop="e1_rel" if dtype == "f64" else "guarded", precision=dtype, max_iter=100)
+    assert info["alpha_used"] == pytest.approx(a_ref, rel=1e-13)
+    if dtype == "f64":
+        ro = M.solve(A, "qhpi19", alpha=a_ref, tol=1e-12, stop="e1_rel", side="left" if shape[0] > shape[1] else "right")
+        assert info["iters"] == ro.iters
+        assert rel_fro(to_np(X), ro.X) <= 1e-12
+
+
 def test_worked_example_on_gpu(qctx, example1):
     """Section 4, Example 1 through the GPU path: printed pseudoinverse and iteration counts."""
     import paper_2605_01464_amd as q

@@ -360,3 +360,97 @@ def test_guarded_stop_fp64_converges_by_tolerance():
     r = M.solve(A, "qhpi19", alpha=M.alpha_sigma(A), tol=1e-12, stop="guarded", side="left")
     assert r.reason in ("tol", "rise")
     assert Q.fro(r.X - Q.pinv_full_column_rank(A)) <= 1e-10 * Q.fro(r.X)
+
+
+# ------------------------------------------------------------------ norms, alpha_F and E1-E4 at hand-computed values
+def _qrow(entries):
+    """1 x n quaternion row vector from (s, x, y, z) tuples."""
+    return np.array(entries, dtype=float).T.reshape(4, 1, len(entries))
+
+
+def test_norm1_norminf_on_row_and_column_vectors():
+    """Section 2's induced norms on a vector: for a 1 x n row the column sums are the entry moduli, so
+    ||a||_1 = max_j |a_j| and ||a||_inf = sum_j |a_j|; transposed for an n x 1 column.  Entries chosen with
+    integer moduli: |1+2i+2j+4k| = 5, |2+3i+6j| = 7, |1+4i+8j| = 9."""
+    a = _qrow([(1, 2, 2, 4), (2, 3, 6, 0), (1, 4, 8, 0)])
+    assert Q.norm1(a) == pytest.approx(9.0, rel=1e-15)
+    assert Q.norminf(a) == pytest.approx(21.0, rel=1e-15)
+    col = np.ascontiguousarray(np.transpose(a, (0, 2, 1)))
+    assert Q.norm1(col) == pytest.approx(21.0, rel=1e-15)
+    assert Q.norminf(col) == pytest.approx(9.0, rel=1e-15)
+
+
+def test_norms_of_example1(example1):
+    """Example 1's matrix: row 2 is twice row 1, entry moduli squared are 74, 39, 114 / 7, 20, 34 /
+    28, 80, 136 (summed by hand from the printed entries), so the largest column sum is sqrt(114) + 3 sqrt(34)
+    (column 3) and the largest row sum 2 (sqrt(7) + sqrt(20) + sqrt(34)) (row 3)."""
+    A, _, _, _ = example1
+    assert Q.norm1(A) == pytest.approx(math.sqrt(114) + 3 * math.sqrt(34), rel=1e-14)
+    assert Q.norminf(A) == pytest.approx(2 * (math.sqrt(7) + math.sqrt(20) + math.sqrt(34)), rel=1e-14)
+    assert Q.fro(A) ** 2 == pytest.approx(532.0, rel=1e-15)
+
+
+def test_alpha_frobenius_example1(example1):
+    """Section 4's scaling 1/||A||_F^2 on Example 1: the squared components sum to 227 + 61 + 244 = 532
+    by rows (by hand), and ||A||_F^2 is also the sum of the squared singular values."""
+    A, _, _, _ = example1
+    assert M.alpha_frobenius(A) == pytest.approx(1.0 / 532.0, rel=1e-15)
+    assert M.alpha_frobenius(A) == pytest.approx(1.0 / float(np.sum(Q.singular_values(A) ** 2)), rel=1e-12)
+    # the two scalings differ on this rank-2 matrix (sigma_1^2 < ||A||_F^2)
+    assert M.alpha_frobenius(A) < M.alpha_sigma(A)
+
+
+def test_residuals_at_zero_iterate():
+    """X = 0: A X A - A = -A, X A X - X = 0 and A X, X A are zero (Hermitian)."""
+    A = rand_q(100, 5, 3)
+    r = M.residuals(A, np.zeros((4, 3, 5)))
+    E1, E2, E3, E4 = r["E"]
+    assert E1 == pytest.approx(Q.fro(A), rel=1e-15)
+    assert (E2, E3, E4) == (0.0, 0.0, 0.0)
+    assert r["E_rel"][0] == pytest.approx(1.0, rel=1e-15)
+
+
+def test_residuals_hand_computed_real_case():
+    """A = diag(1, 2), X = e_1 e_2^T (real): AX = [[0,1],[0,0]], XA = [[0,2],[0,0]], AXA = [[0,2],[0,0]],
+    XAX = 0, so E1 = ||[[-1,2],[0,-2]]|| = 3, E2 = ||X|| = 1, E3 = sqrt 2, E4 = 2 sqrt 2; relative forms
+    divide by ||A|| = sqrt 5, ||X|| = 1, ||AX|| = 1 and ||XA|| = 2.  E3 != E4 separates the two Hermitian
+    residuals."""
+    A = np.zeros((4, 2, 2))
+    A[0] = np.diag([1.0, 2.0])
+    X = np.zeros((4, 2, 2))
+    X[0, 0, 1] = 1.0
+    r = M.residuals(A, X)
+    np.testing.assert_allclose(r["E"], [3.0, 1.0, math.sqrt(2), 2 * math.sqrt(2)], rtol=1e-15)
+    np.testing.assert_allclose(r["E_rel"], [3.0 / math.sqrt(5), 1.0, math.sqrt(2), math.sqrt(2)], rtol=1e-15)
+
+
+def test_residuals_identity_operator():
+    """A = I_2 and the quaternion X = B = [[1+i, 2j], [3, k]] (by hand, with ij = k, jk = i):
+    B^H - B = [[-2i, 3-2j], [-3-2j, -2k]] so E3 = E4 = sqrt 34; B - I = [[i, 2j], [3, -1+k]] so E1 = 4;
+    B^2 = [[2i+6j, 2i+2j+2k], [3+3i+3k, -1+6j]], B^2 - B = [[-1+i+6j, 2i+2k], [3i+3k, -1+6j-k]] so
+    E2 = sqrt 102."""
+    B = np.zeros((4, 2, 2))
+    B[:, 0, 0] = (1, 1, 0, 0)
+    B[:, 0, 1] = (0, 0, 2, 0)
+    B[:, 1, 0] = (3, 0, 0, 0)
+    B[:, 1, 1] = (0, 0, 0, 1)
+    r = M.residuals(Q.qeye(2), B)
+    np.testing.assert_allclose(r["E"], [4.0, math.sqrt(102), math.sqrt(34), math.sqrt(34)], rtol=1e-15)
+
+
+def test_residuals_spectral_iterate():
+    """A = U diag(s) V^H (5 x 4, rank 3) and X = V diag(x) U^H with x not 1/s: AXA = U diag(s^2 x) V^H and
+    XAX = V diag(x^2 s) U^H, so E1 = ||s^2 x - s||_2, E2 = ||x^2 s - x||_2, and AX = U diag(sx) U^H,
+    XA = V diag(sx) V^H are Hermitian (E3 = E4 = 0)."""
+    s = np.array([2.0, 1.0, 0.5])
+    x = np.array([0.3, 0.8, 1.5])
+    inst = qsynth.small_spectral_instance(101, 5, 4, s)
+    X = Q.pinv_from_factors(inst["U"], 1.0 / x, inst["V"])   # V diag(x) U^H
+    r = M.residuals(inst["A"], X)
+    E1, E2, E3, E4 = r["E"]
+    assert E1 == pytest.approx(float(np.linalg.norm(s * s * x - s)), rel=1e-12)
+    assert E2 == pytest.approx(float(np.linalg.norm(x * x * s - x)), rel=1e-12)
+    assert E3 <= 1e-14 and E4 <= 1e-14
+    nr = r["E_rel"]
+    assert nr[0] == pytest.approx(E1 / float(np.linalg.norm(s)), rel=1e-12)
+    assert nr[1] == pytest.approx(E2 / float(np.linalg.norm(x)), rel=1e-12)
