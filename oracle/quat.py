@@ -118,6 +118,16 @@ def pinv_full_row_rank(A: np.ndarray) -> np.ndarray:
     return from_cadj(np.linalg.solve(G, C).conj().T)
 
 
+def inverse_square(A: np.ndarray) -> np.ndarray:
+    """A^{-1} for a nonsingular square A, which is then its Moore-Penrose inverse (Section 2): the complex adjoint
+    of the inverse is the inverse of the complex adjoint (a homomorphism), solved from A^C Z = I by LU.  Its
+    relative error is about kappa(A) u, against kappa(A)^2 u for the normal equations of the full-rank form."""
+    if A.shape[1] != A.shape[2]:
+        raise ValueError("inverse_square: A must be square")
+    C = cadj(A)
+    return from_cadj(np.linalg.solve(C, np.eye(C.shape[0], dtype=C.dtype)))
+
+
 def pinv_from_factors(U: np.ndarray, s: np.ndarray, V: np.ndarray) -> np.ndarray:
     """For A = U diag(s) V^H with orthonormal U, V and s > 0: A^dagger = V diag(1/s) U^H (Section 2)."""
     Vs = V / s[None, None, :]

@@ -83,25 +83,40 @@ def test_bf16_phase_alone_stalls(qctx, sq512):
     assert rel_fro(to_np(X), ref) > 1e-3
 
 
-def test_full_size_mixed_sampled_rows(qctx):
-    """4096 x 4096, condition 1e3: rows i of A X - I computed on the host for sampled i must be at FP64
-    level after the FP64 finish (relative error <= kappa * residual)."""
+@pytest.fixture(scope="module")
+def c3_full():
+    """The 4096 x 4096 condition-1e3 workload and the oracle's inverse of its FP32-rounded values (the
+    Moore-Penrose inverse of a nonsingular square matrix, solved through the complex adjoint in FP64; its own
+    error is about kappa u64 = 1e-13, far below the 1e-6 bound)."""
+    import sys
+
+    inst = qsynth.c3_instance()
+    print("c3_full: oracle inverse at 4096^2", flush=True, file=sys.stderr)
+    inst["ref"] = Q.inverse_square(inst["A"])
+    return inst
+
+
+@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("qrapid", 5)])
+@pytest.mark.parametrize("precision", ["mixed", "f32_f64finish", "f64"])
+def test_full_size_parity_vs_oracle(qctx, c3_full, method, order, precision):
+    """4096 x 4096, condition 1e3: the returned X of the ladder, of FP32 with an FP64 finish and of all-FP64
+    against the oracle's pseudoinverse of the identical FP32-rounded input, relative Frobenius error <= 1e-6 (the
+    workload's target); the FP64 forms end at the oracle's own accuracy, well below it."""
     import torch
     import paper_2605_01464_amd as q
 
-    inst = qsynth.c3_instance()
-    A = inst["A"]
-    X, info = q.solve(qctx, to_dev(A, "f32"), "qhpi19", scaling="power", tol=1e-6, stop="guarded",
-                      precision="mixed", out_dtype=torch.float64)
-    Xh = to_np(X)
-    rows = np.random.default_rng(5).choice(A.shape[1], 16, replace=False)
-    AXr = Q.qmul(A[:, rows, :], Xh)
-    I = np.zeros_like(AXr)
-    I[0, np.arange(16), rows] = 1.0
-    res = np.linalg.norm(AXr - I) / np.sqrt(16)
-    s = inst["s"]
-    assert res * (s[0] / s[-1]) <= 1e-6, (res, info)
-    assert info["iters_bf16"] >= 1 and 1 <= info["iters_f64"] <= 2
+    A = c3_full["A"]
+    X, info = q.solve(qctx, to_dev(A, "f64" if precision == "f64" else "f32"), method, order, scaling="power",
+                      tol=1e-6, stop="guarded", precision=precision, out_dtype=torch.float64)
+    err = rel_fro(to_np(X), c3_full["ref"])
+    assert info["status"] == q.OK, info
+    assert err <= 1e-6, (err, info)
+    if precision == "mixed":
+        assert info["iters_bf16"] >= 1 and info["iters_f32"] >= 1 and 1 <= info["iters_f64"] <= 2, info
+    elif precision == "f32_f64finish":
+        assert info["iters_bf16"] == 0 and info["iters_f32"] >= 1 and 1 <= info["iters_f64"] <= 2, info
+    else:
+        assert info["iters_f64"] == info["iters"], info
 
 
 def test_ragged_tall_mixed_ladder_with_staged_bf16_products(qctx):

@@ -132,6 +132,24 @@ def test_pinv_closed_forms():
     np.testing.assert_allclose(Q.pinv_svd(B), Q.pinv_full_row_rank(B), atol=1e-12)
 
 
+def test_inverse_square():
+    """A^{-1} of a nonsingular square quaternion matrix: both products with A are the identity, it equals the
+    SVD pseudoinverse, and on a constructed U diag(s) V^H it is V diag(1/s) U^H."""
+    A = rand_q(22, 7, 7)
+    X = Q.inverse_square(A)
+    np.testing.assert_allclose(Q.qmul(A, X), Q.qeye(7), atol=1e-12)
+    np.testing.assert_allclose(Q.qmul(X, A), Q.qeye(7), atol=1e-12)
+    np.testing.assert_allclose(X, Q.pinv_svd(A), atol=1e-12)
+    inst = qsynth.small_spectral_instance(23, 6, 6, [4.0, 2.0, 1.0, 0.5, 0.25, 0.125])
+    np.testing.assert_allclose(Q.inverse_square(inst["A"]), Q.pinv_from_factors(inst["U"], inst["s"], inst["V"]),
+                               atol=1e-12)
+    # a 1 x 1 quaternion: q^{-1} = conj(q) / |q|^2
+    qv = np.array([1.0, 2.0, 2.0, 4.0]).reshape(4, 1, 1)
+    np.testing.assert_allclose(Q.inverse_square(qv)[:, 0, 0], np.array([1.0, -2.0, -2.0, -4.0]) / 25.0, rtol=1e-15)
+    with pytest.raises(ValueError):
+        Q.inverse_square(rand_q(24, 3, 4))
+
+
 def test_pinv_unitary_is_adjoint():
     U = qsynth.stiefel(30, 8, 8)
     np.testing.assert_allclose(Q.qmul(Q.qH(U), U), Q.qeye(8), atol=1e-12)
