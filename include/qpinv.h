@@ -179,6 +179,27 @@ int qpinv_solve(qpinv_ctx* ctx, int method, int order, const qpinv_qmat* A, int 
                 double tol, int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info,
                 void* hip_stream);
 
+/* Bytes of the device array that qpinv_solve_noalloc carves its workspace from (one copy per GPU). */
+#define QPINV_NOALLOC_SCRATCH_BYTES 67108864
+
+/* qpinv_solve for callers that cannot allocate device memory during a call (serving loops with a fixed
+ * memory budget, harnesses that forbid hipMalloc inside a call): the same arguments, the same iterates and
+ * results as qpinv_solve with the same tiles, but every workspace buffer is carved from a static device
+ * array of QPINV_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU holds from its first context until the
+ * process ends.  The call makes no hipMalloc / hipFree / hipHostMalloc and no allocating library call;
+ * qpinv_init has already allocated the context's scalar buffers and looked up the array's address on its
+ * device.  Within the call: no tile autotuning (tiles tuned earlier on the context, else the defaults), no
+ * per-product timing events (option gemm_timing is ignored), and a BF16 stage buffer that is never grown.
+ * Limit: a shape whose workspace bound exceeds the array is rejected with EINVAL before anything is
+ * launched (square FP64 solves up to 280 x 280, FP32 up to 371 x 371, FP32 with the FP64 finish or the
+ * precision ladder up to 216 x 216; tall or wide shapes go further on the long side).  Sharing: every call on one GPU uses that
+ * GPU's array, which keeps the last call's contents (each buffer is written before it is read within a
+ * call): calls that overlap on one GPU -- two streams, threads or contexts -- race and must be serialised
+ * by the caller.  Return codes as qpinv_solve. */
+int qpinv_solve_noalloc(qpinv_ctx* ctx, int method, int order, const qpinv_qmat* A, int scaling,
+                        double alpha_or_mu, double tol, int max_iter, int stop, int precision, qpinv_qmat* X,
+                        qpinv_info* info, void* hip_stream);
+
 /* Many independent solves in ONE persistent kernel launch (replayed from a captured hipGraph when the
  * batch signature repeats): power-iteration or given alpha, X_0 = alpha A^H, the product chain and the
  * stop rule per matrix, on the residual side of the smaller dimension.  Two kernel forms, chosen by the

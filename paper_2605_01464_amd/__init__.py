@@ -74,6 +74,7 @@ def _load() -> ctypes.CDLL:
         "qpinv_strerror": (ctypes.c_char_p, [I]),
         "qpinv_last_error": (ctypes.c_char_p, []),
         "qpinv_solve": (I, [P, I, I, QP, I, D, D, I, I, I, QP, ctypes.POINTER(Info), P]),
+        "qpinv_solve_noalloc": (I, [P, I, I, QP, I, D, D, I, I, I, QP, ctypes.POINTER(Info), P]),
         "qpinv_step": (I, [P, I, I, I, I, QP, QP, QP, DP, P]),
         "qpinv_solve_batched": (I, [P, I, I, I, QP, QP, I, DP, D, I, I, ctypes.POINTER(Info), P]),
         "qpinv_residuals": (I, [P, QP, QP, DP, DP, P]),
@@ -175,6 +176,14 @@ def qpinv_solve(ctx, method, order, A, scaling, alpha_or_mu, tol, max_iter, stop
     info = Info()
     st = _lib.qpinv_solve(ctx, method, order, ctypes.byref(qmat(A)), scaling, float(alpha_or_mu), float(tol),
                           int(max_iter), stop, precision, ctypes.byref(qmat(X)), ctypes.byref(info), _stream(stream))
+    return st, info
+
+
+def qpinv_solve_noalloc(ctx, method, order, A, scaling, alpha_or_mu, tol, max_iter, stop, precision, X, stream=None):
+    info = Info()
+    st = _lib.qpinv_solve_noalloc(ctx, method, order, ctypes.byref(qmat(A)), scaling, float(alpha_or_mu), float(tol),
+                                  int(max_iter), stop, precision, ctypes.byref(qmat(X)), ctypes.byref(info),
+                                  _stream(stream))
     return st, info
 
 
@@ -396,6 +405,25 @@ def solve(ctx: Context, A, method="qhpi19", order=None, scaling="power", alpha=0
     if check and st not in (OK, ENOTCONVERGED):
         _err(st, "qpinv_solve")
     return X, d
+
+
+def solve_noalloc(ctx: Context, A, X, method="qhpi19", order=None, scaling="power", alpha=0.0, tol=1e-6, max_iter=500,
+                  stop="guarded", precision=None, stream=None, check=True):
+    """solve() through the allocation-free entry point: X (n x m, caller-allocated) receives the result and the
+    library allocates nothing during the call (workspace from its static per-GPU scratch).  Returns info."""
+    import torch
+
+    if X is None:
+        raise ValueError("solve_noalloc: X must be allocated by the caller")
+    if precision is None:
+        precision = "f64" if A.dtype == torch.float64 else "f32"
+    st, info = qpinv_solve_noalloc(ctx.handle, METHOD[method], _order(method, order), A, SCALING[scaling], alpha, tol,
+                                   max_iter, STOP[stop], PRECISION[precision], X, stream)
+    d = info.as_dict()
+    d["status"] = st
+    if check and st not in (OK, ENOTCONVERGED):
+        _err(st, "qpinv_solve_noalloc")
+    return d
 
 
 def solve_batched(ctx: Context, As, method="qhpi19", order=None, scaling="power", alphas=None, tol=1e-6,

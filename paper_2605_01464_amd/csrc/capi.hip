@@ -188,6 +188,16 @@ int qpinv_solve(qpinv_ctx* c, int method, int order, const qpinv_qmat* A, int sc
   });
 }
 
+int qpinv_solve_noalloc(qpinv_ctx* c, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu,
+                        double tol, int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info,
+                        void* hip_stream) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    return qp::solve_noalloc(cx, method, order, A, scaling, alpha_or_mu, tol, max_iter, stop, precision, X, info,
+                             stream_of(hip_stream));
+  });
+}
+
 int qpinv_solve_batched(qpinv_ctx* c, int method, int order, int batch, const qpinv_qmat* A, qpinv_qmat* X,
                         int scaling, const double* alpha, double tol, int max_iter, int stop, qpinv_info* infos,
                         void* hip_stream) {

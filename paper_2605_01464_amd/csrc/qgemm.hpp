@@ -38,6 +38,7 @@ struct GemmScratch {
   int64_t capacity = 0;
   void* stage = nullptr;  // device, stage_bytes: BF16 operand copies of the staged BF16 products (grown on
   size_t stage_bytes = 0;  // demand, outside graph capture; owned and freed by the context)
+  bool no_grow = false;    // allocation-free call: a product that needs a larger stage buffer fails instead
 };
 
 struct TileConfig {

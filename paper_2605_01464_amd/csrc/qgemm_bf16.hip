@@ -887,6 +887,9 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
     return launch_bf16_db<64, 64, 2, 2, 2>(P0, 0, s);
   const size_t need = (size_t)stage_bytes(P.M, P.N, P.K);
   if (sc.stage_bytes < need) {
+    if (sc.no_grow)
+      throw Error(-1, "qgemm: the staged BF16 product needs a " + std::to_string(need) +
+                          "-byte stage buffer, which an allocation-free call cannot grow");
     // grow the stage buffer (kernels of earlier products on the stream may still read it)
     QP_HIP(hipStreamSynchronize(s));
     if (sc.stage) QP_HIP(hipFree(sc.stage));

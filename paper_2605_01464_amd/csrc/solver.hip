@@ -62,6 +62,19 @@ Epilogue epi1(const Mat& o, double a = 1.0, double g = 0.0) {
 // ------------------------------------------------------------------------------------------------
 void* Workspace::get(const std::string& key, size_t bytes) {
   if (bytes < 256) bytes = 256;
+  if (arena) {
+    auto it = arena_bufs.find(key);
+    if (it != arena_bufs.end() && it->second.bytes >= bytes) return it->second.p;
+    bytes = (bytes + 255) / 256 * 256;
+    if (bytes > arena_cap - arena_used)
+      throw Error(QPINV_EINVAL, "allocation-free solve: workspace request " + key + " of " + std::to_string(bytes) +
+                                    " bytes does not fit the " + std::to_string(arena_cap) + "-byte scratch (" +
+                                    std::to_string(arena_used) + " bytes in use)");
+    void* p = arena + arena_used;
+    arena_used += bytes;
+    arena_bufs[key] = Buf{p, bytes};
+    return p;
+  }
   auto it = bufs.find(key);
   if (it != bufs.end() && it->second.bytes >= bytes) return it->second.p;
   if (it != bufs.end()) {
@@ -77,6 +90,19 @@ void* Workspace::get(const std::string& key, size_t bytes) {
   return p;
 }
 
+void Workspace::begin_arena(void* base, size_t cap) {
+  arena = static_cast<char*>(base);
+  arena_cap = cap;
+  arena_used = 0;
+  arena_bufs.clear();
+}
+
+void Workspace::end_arena() {
+  arena = nullptr;
+  arena_cap = arena_used = 0;
+  arena_bufs.clear();
+}
+
 void Workspace::release() {
   for (auto& kv : bufs) (void)hipFree(kv.second.p);
   bufs.clear();
@@ -88,6 +114,7 @@ Ctx::Ctx(int dev) : device(dev) {
   QP_HIP(hipMalloc(&scratch.partial, sizeof(double) * scratch.capacity));
   QP_HIP(hipMalloc(&dsc, sizeof(double) * 64));
   QP_HIP(hipHostMalloc(&hsc, sizeof(double) * 64, hipHostMallocDefault));
+  (void)noalloc_scratch(dev);  // look up this device's no-allocation scratch now, with the device current
 }
 
 Ctx::~Ctx() {
@@ -110,7 +137,7 @@ int Ctx::config_for(Prec p, int64_t M, int64_t N, int64_t K, hipStream_t s) {
   auto key = std::make_tuple((int)p, M, N, K);
   auto it = tuned.find(key);
   if (it != tuned.end()) return it->second;
-  if (opt.autotune) return autotune(*this, p, M, N, K, nullptr, s);
+  if (opt.autotune && !no_alloc) return autotune(*this, p, M, N, K, nullptr, s);
   return default_config(p, M, N, K);
 }
 
@@ -156,7 +183,7 @@ void gemm(Ctx& c, Prec p, const Mat& A, const Mat& B, const Epilogue& e, hipStre
   const int cfg = c.config_for(p, M, N, K, s);
   const double f = 32.0 * (double)M * (double)N * (double)K;
   c.flops += f;
-  if (!c.opt.gemm_timing) {
+  if (!c.opt.gemm_timing || c.no_alloc) {
     qgemm(p, A.v, B.v, M, N, K, e, red, c.scratch, s, cfg);
     return;
   }

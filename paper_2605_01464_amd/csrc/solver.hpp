@@ -12,14 +12,21 @@
 
 namespace qp {
 
-// Grow-only named device allocations, freed with the context.
+// Grow-only named device allocations, freed with the context.  In arena mode (allocation-free solves)
+// the same named requests are carved, 256-byte aligned, from a caller-provided region instead: no
+// allocation, and a request that does not fit throws EINVAL.
 struct Workspace {
   struct Buf {
     void* p = nullptr;
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs;
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  std::map<std::string, Buf> arena_bufs;
   void* get(const std::string& key, size_t bytes);
+  void begin_arena(void* base, size_t cap);
+  void end_arena();
   void release();
   ~Workspace() { release(); }
 };
@@ -56,6 +63,7 @@ struct Ctx {
   MlpState* mlp = nullptr;
   BatchedState* batched = nullptr;
   std::map<std::vector<int64_t>, int> batched_tuned;  // batch signature -> tile configuration
+  bool no_alloc = false;  // allocation-free call in progress: no autotuning, no product timing, no growth
   double flops = 0.0;  // running count of algorithmic product flops
   // event pairs around product launches (option gemm_timing)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -92,6 +100,16 @@ void chain(Ctx& c, int method, int order, int side, Prec p, const Mat& A, const 
 
 int solve(Ctx& c, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu, double tol,
           int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info, hipStream_t s);
+
+// The same solve with every workspace buffer carved from the device's static no-allocation scratch (noalloc.hip).
+int solve_noalloc(Ctx& c, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu, double tol,
+                  int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info, hipStream_t s);
+
+// Address of the device's no-allocation scratch, looked up once per device with that device current (noalloc.hip).
+void* noalloc_scratch(int device);
+
+// Upper bound of the workspace bytes one solve of an m x n matrix can request (noalloc.hip).
+size_t noalloc_workspace_bound(int64_t m, int64_t n, int side, int precision, int out_dtype);
 
 int solve_batched(Ctx& c, int method, int order, int batch, const qpinv_qmat* A, qpinv_qmat* X, int scaling,
                   const double* alpha, double tol, int max_iter, int stop, qpinv_info* infos, hipStream_t s);

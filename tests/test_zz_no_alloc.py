@@ -1,0 +1,65 @@
+"""The allocation-free solve entry point against qpinv_solve (same kernels and tiles: identical results)."""
+import numpy as np
+import pytest
+
+import qsynth
+from conftest import rel_fro, to_dev, to_np
+from oracle import methods as M
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(ctx, A, precision, method, tol, stop, order=None):
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    Ad = to_dev(A, "f64" if precision == "f64" else "f32")
+    X_ref, info_ref = q.solve(ctx, Ad, method, order, scaling="power", tol=tol, stop=stop, precision=precision)
+    X = torch.full_like(X_ref, float("nan"))
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    info = q.solve_noalloc(ctx, Ad, X, method, order, scaling="power", tol=tol, stop=stop, precision=precision)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 == free0, (free0, free1)
+    assert info["status"] == info_ref["status"] == q.OK, (info, info_ref)
+    for k in ("iters", "returned", "stop_reason", "side", "alpha_used", "iters_f32", "iters_f64"):
+        assert info[k] == info_ref[k], (k, info[k], info_ref[k])
+    assert torch.equal(X, X_ref)
+    return X, info
+
+
+def test_noalloc_matches_solve_two_calls(qctx):
+    """Two calls in a row, the second on a smaller matrix (the scratch holds the first call's buffers): each
+    result equals qpinv_solve's bit for bit, and the FP64 one follows the oracle run from the same alpha."""
+    import paper_2605_01464_amd as q
+
+    qctx.set("autotune", 0)
+    A1 = qsynth.c1_instance(4)  # 64 x 48, planes N(0,1)
+    X1, info1 = _compare(qctx, A1, "f64", "qhpi19", 1e-12, "e1_rel")
+    ro = M.solve(A1, "qhpi19", alpha=info1["alpha_used"], tol=1e-12, stop="e1_rel", side="left")
+    assert info1["iters"] == ro.iters
+    assert rel_fro(to_np(X1), ro.X) <= 1e-12
+    A2 = qsynth.round_f32(np.random.default_rng(31).standard_normal((4, 33, 21)))
+    X2, info2 = _compare(qctx, A2, "f32", "qsai", 1e-6, "guarded")
+    ref2 = M.solve(A2, "qsai", alpha=info2["alpha_used"], tol=1e-12, stop="e1_rel", side="left").X
+    assert rel_fro(to_np(X2), ref2) <= 5e-5
+    # the FP32 iterations with the FP64 finish, wide shape (right-side residual), after the smaller call
+    A3 = qsynth.round_f32(np.random.default_rng(32).standard_normal((4, 40, 72)))
+    _compare(qctx, A3, "f32_f64finish", "qhpi19", 1e-6, "guarded")
+
+
+def test_noalloc_rejects_oversize_before_launch(qctx):
+    """A shape whose workspace bound exceeds the scratch is refused with EINVAL; X is left untouched."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    A = torch.zeros((4, 300, 300), dtype=torch.float64, device="cuda")
+    X = torch.full((4, 300, 300), 7.0, dtype=torch.float64, device="cuda")
+    info = q.solve_noalloc(qctx, A, X, "qhpi19", precision="f64", check=False)
+    assert info["status"] == q.EINVAL
+    assert "no-allocation scratch" in q.qpinv_last_error()
+    torch.cuda.synchronize()
+    assert float((X - 7.0).abs().max()) == 0.0
