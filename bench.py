@@ -310,8 +310,20 @@ def section_c2(q, ctx, torch, steps=5, warmup=2):
     for meth in ("qhpi19", "ns", "qsai", "qrapid"):
         kw = dict(method=meth, scaling="power", tol=1e-6, max_iter=200, stop="guarded", precision="f32", X=X)
         el, info, _ = timed_solves(q, ctx, torch, A, kw, steps, warmup)
+        _, Er = q.residuals(ctx, A, X)
         res[meth] = {"pinv_per_s": steps / el, "iters": info["iters"], "returned": info["returned"],
-                     "reason": info["reason"], "gemm_tflop": info["gemm_flops"] / 1e12}
+                     "reason": info["reason"], "gemm_tflop": info["gemm_flops"] / 1e12, "E_rel_fp64": Er}
+    # FP32 QHPI19, FP64 Newton-Schulz finish, then no projection / X A X / (X A)^H X (A X)^H (option penrose_finish)
+    X64 = torch.empty((4, A.shape[2], A.shape[1]), dtype=torch.float64, device="cuda")
+    for mode, label in ((0, "f32_f64finish"), (1, "f32_f64finish_xax"), (2, "f32_f64finish_projection")):
+        ctx.set("penrose_finish", mode)
+        kw = dict(method="qhpi19", scaling="power", tol=1e-6, max_iter=200, stop="guarded", precision="f32_f64finish",
+                  X=X64)
+        el, info, _ = timed_solves(q, ctx, torch, A, kw, steps, warmup)
+        _, Er = q.residuals(ctx, A, X64)
+        res[label] = {"pinv_per_s": steps / el, "iters_f32": info["iters_f32"], "iters_f64": info["iters_f64"],
+                      "E_rel_fp64": Er}
+    ctx.set("penrose_finish", 0)
     return {"section": "c2_2048x1536_rank1024", "results": res}
 
 

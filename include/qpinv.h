@@ -149,7 +149,17 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
  * index used for every product of that precision, -1 = tuned or heuristic choice), batched_cfg
  * (configuration of qpinv_solve_batched, -1 = tuned or default), batched_dynamic (phase-synchronous
  * batched form: 1 (default) workgroups claim work items from a counter, 0 workgroup g takes items
- * g, g + G, ...; the results are the same), verbose (0/1).
+ * g, g + G, ...; the results are the same), verbose (0/1), penrose_finish (projection of the returned
+ * iterate in FP64, Section 2's Penrose conditions: 0 (default) none; 1 X <- X A X (condition (b)) after the
+ * last update; 2 X <- (X A)^H X (A X)^H, which A^dagger leaves unchanged by conditions (b)-(d) and whose
+ * rows lie in range(A^H) and columns in range(A), the invariants of every exact iterate (Proposition 3.1):
+ * it removes the rounding that lower precisions leave outside them -- on a numerically rank-deficient A
+ * that is what limits an FP32 solve, since the update multiplies it by its order in the near-null
+ * directions.  It amplifies, to first order, what error the range directions still carry, so it is placed
+ * before the last FP64 update: the FP64 finish then runs max(2, f64_finish_iters) updates (no early stop)
+ * with the projection before the last; an F64 solve is projected after its last update and takes one
+ * more FP64 Newton-Schulz update; F32 solves refuse it (EINVAL).  2 FP64 products for 1, 4 products and
+ * 2 adjoints for 2).
  * Errors: EINVAL for an unknown key or out-of-range value. */
 int qpinv_set_option(qpinv_ctx* ctx, const char* key, double value);
 

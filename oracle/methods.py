@@ -317,6 +317,13 @@ def residuals(A, X) -> dict:
     }
 
 
+def penrose_projection(A, X) -> np.ndarray:
+    """(X A)^H X (A X)^H (Section 2): A^dagger is a fixed point, since (b)-(d) give (XA)^H X (AX)^H = XAXAX = X.
+    Its rows lie in range(A^H) and its columns in range(A), the invariants every exact iterate keeps
+    (Proposition 3.1)."""
+    return qmul(qmul(qH(qmul(X, A)), X), qH(qmul(A, X)))
+
+
 def e1_rel(A, X) -> float:
     return fro(qmul(qmul(A, X), A) - A) / fro(A)
 

@@ -74,7 +74,7 @@ void* noalloc_scratch(int device) {
 // chain's 8 side-by-side buffers, 2 saved residuals, 4 iterates, 3 iterate-shaped temporaries, the
 // residual-based and E1 outputs, E1's side product and a converted copy of A; the FP64 candidate check
 // (iterate, X A, output, FP64 A); the refined FP64 finish (8 FP32 and 2 FP64 side-by-side, 2 FP32
-// iterate-shaped); the zero result; the norm and power-iteration work vectors.
+// iterate-shaped); the Penrose projection; the zero result; the norm and power-iteration work vectors.
 size_t noalloc_workspace_bound(int64_t m, int64_t n, int side, int precision, int out_dtype) {
   if (side == QPINV_SIDE_AUTO) side = (m > n) ? QPINV_SIDE_LEFT : QPINV_SIDE_RIGHT;
   const int64_t sd = side == QPINV_SIDE_LEFT ? n : m;
@@ -88,6 +88,8 @@ size_t noalloc_workspace_bound(int64_t m, int64_t n, int side, int precision, in
   }
   b += 2 * mat_bytes(n, m, QPINV_F64) + mat_bytes(n, n, QPINV_F64) + mat_bytes(m, n, QPINV_F64);
   if (finish) b += 8 * mat_bytes(sd, sd, QPINV_F32) + 2 * mat_bytes(sd, sd, QPINV_F64) + 2 * mat_bytes(n, m, QPINV_F32);
+  // the Penrose projection (FP64 copy, X A, A X, their adjoints, the first product, output, the update after it)
+  b += 4 * mat_bytes(n, m, QPINV_F64) + 2 * mat_bytes(n, n, QPINV_F64) + 2 * mat_bytes(m, m, QPINV_F64);
   b += mat_bytes(n, m, out_dtype);
   b += align256(8 * (size_t)std::max(norms_work_doubles(m, n), norms_work_doubles(n, m)));
   b += align256(8 * (size_t)std::max(power_work_doubles(m, n), power_work_doubles(sd, sd)));

@@ -816,6 +816,31 @@ double e1_sq(Ctx& c, Prec p, const Mat& A, const Mat& X, hipStream_t s) {
   return c.hsc[0];
 }
 
+// Projection of an FP64 iterate X (n x m) toward A^dagger with the Penrose conditions (Section 2), into O.
+//   mode 1: O = X A X (condition (b); a fixed point of every {2}-inverse of A).
+//   mode 2: O = (X A)^H X (A X)^H, which equals X for A^dagger by conditions (b)-(d).  Its rows lie in
+//           range(A^H) and its columns in range(A), the invariants every exact iterate keeps (Proposition 3.1):
+//           it removes what rounding put outside them.  Near-null directions of a numerically rank-deficient
+//           A take rounding that the update multiplies by its order, and the blocks of X that map them to
+//           range directions are fixed points of the update and of X A X; this projection removes both.
+void penrose_project(Ctx& c, int mode, const Mat& A64, const Mat& X64, const Mat& O, hipStream_t s) {
+  const int64_t m = A64.rows, n = A64.cols;
+  Mat XA = ws_mat(c, "pf_xa", n, n, QPINV_F64);
+  gemm(c, P_F64, X64, A64, epi1(XA), s);
+  if (mode == 1) {
+    gemm(c, P_F64, XA, X64, epi1(O), s);
+    return;
+  }
+  Mat AX = ws_mat(c, "pf_ax", m, m, QPINV_F64);
+  gemm(c, P_F64, A64, X64, epi1(AX), s);
+  Mat H1 = ws_mat(c, "pf_h1", n, n, QPINV_F64), H2 = ws_mat(c, "pf_h2", m, m, QPINV_F64);
+  Mat P1 = ws_mat(c, "pf_p1", n, m, QPINV_F64);
+  x0_into(XA, 1.0, H1, s);
+  x0_into(AX, 1.0, H2, s);
+  gemm(c, P_F64, H1, X64, epi1(P1), s);
+  gemm(c, P_F64, P1, H2, epi1(O), s);
+}
+
 struct IterSet {
   Mat b[4];
 };
@@ -837,6 +862,8 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
   if (precision < QPINV_PREC_F64 || precision > QPINV_PREC_MIXED) throw Error(QPINV_EINVAL, "bad precision");
   if (scaling < QPINV_ALPHA_POWER || scaling > QPINV_X0_GIVEN) throw Error(QPINV_EINVAL, "bad scaling");
   if (scaling == QPINV_ALPHA_GIVEN && !(am > 0.0)) throw Error(QPINV_EINVAL, "ALPHA_GIVEN needs alpha > 0");
+  if (c.opt.penrose_finish == 2 && precision == QPINV_PREC_F32)
+    throw Error(QPINV_EINVAL, "penrose_finish = 2 needs FP64 updates (precision F64, F32_F64FINISH or MIXED)");
 
   qpinv_info inf;
   std::memset(&inf, 0, sizeof(inf));
@@ -1111,6 +1138,25 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     if (has_finish && ph == phases.size() - 1) {
       const double d = xn > 0 ? d_abs / xn : 0.0;
       const int fin_it = inf.iters_f64;
+      if (c.opt.penrose_finish == 2) {
+        // fixed schedule: the projection comes before the last update, which removes the first-order error
+        // the projection leaves in the range directions; the updates before it converge the iterate (the
+        // projection cubes whatever is not yet converged)
+        const int total = std::max(2, c.opt.f64_finish_iters);
+        if (fin_it >= total) {
+          inf.stop_reason = QPINV_REASON_TOL;
+          returned_buf = nxt;
+          returned_j = j;
+          done = true;
+        } else if (fin_it == total - 1) {
+          Mat O = ws_mat(c, "pf_out", n, m, QPINV_F64);
+          penrose_project(c, 2, A_of(QPINV_F64), S->b[nxt], O, s);
+          convert_mat(O, S->b[nxt], s);
+        }
+        d_prev_finish = d;
+        cur = nxt;
+        continue;
+      }
       // in the asymptotic regime the next change is about d^p: once that is below tol the FP64 iterate
       // just computed is converged and a confirming step is not needed.  Not for order 2: the error of a
       // Newton-Schulz update is E A E, whose relative size carries a condition-number factor that d^2
@@ -1223,7 +1269,30 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
 
   inf.iters = inf.iters_bf16 + inf.iters_f32 + inf.iters_f64;
   inf.returned = returned_j;
-  convert_mat(S->b[returned_buf], Xout, s);
+  Mat Xret = S->b[returned_buf];
+  if (c.opt.penrose_finish && status != QPINV_EDIVERGED && !(c.opt.penrose_finish == 2 && has_finish)) {
+    // X A X after the last update (any precision), or for FP64 solves the projection followed by one FP64
+    // Newton-Schulz update (the same order as inside the finish)
+    Mat X64 = Xret;
+    if (X64.dtype != QPINV_F64) {
+      Mat t = ws_mat(c, "pf_x", n, m, QPINV_F64);
+      convert_mat(X64, t, s);
+      X64 = t;
+    }
+    Mat O = ws_mat(c, "pf_out", n, m, QPINV_F64);
+    const Mat A64 = A_of(QPINV_F64);
+    penrose_project(c, c.opt.penrose_finish, A64, X64, O, s);
+    if (c.opt.penrose_finish == 2) {
+      Mat N = ws_mat(c, "pf_ns", n, m, QPINV_F64);
+      chain(c, QPINV_NS, 2, side, P_F64, A64, O, N, nullptr, s);
+      ++inf.iters_f64;
+      ++inf.iters;
+      ++inf.returned;
+      O = N;
+    }
+    Xret = O;
+  }
+  convert_mat(Xret, Xout, s);
   QP_HIP(hipStreamSynchronize(s));
   return finish(status);
 }

@@ -39,6 +39,7 @@ struct Options {
   int f64_finish_iters = 2;
   int f64_refined = 1;  // 1: FP64 finish updates with FP64 residual and sum, FP32 polynomial (NS, HPI, QSAI, QHPI19)
   int finish_method = QPINV_NS;  // method of the FP64 finish updates (-1: the solve's own method)
+  int penrose_finish = 0;        // FP64 projection of the returned iterate: 0 none, 1 X A X, 2 (X A)^H X (A X)^H
   double mixed_switch = 1e-2;
   int mixed_rnorm_steps = 6;
   int max_bf16_iters = 8;

@@ -202,3 +202,79 @@ def test_degenerate_shapes(qctx, method):
         A = torch.zeros((4,) + shape, dtype=torch.float64, device="cuda")
         X, info = q.solve(qctx, A, method, precision="f64")
         assert tuple(X.shape) == (4, shape[1], shape[0]) and info["status"] == q.OK
+
+
+# ------------------------------------------------------------------ Penrose projection of the result
+@pytest.fixture(scope="module")
+def rank_def():
+    """150 x 110 of rank 60 (s geometric 1 .. 1e-3), rounded to FP32: numerically rank deficient."""
+    inst = qsynth.small_spectral_instance(120, 150, 110, qsynth.geometric(60, 1.0, 1e-3))
+    inst["A"] = qsynth.round_f32(inst["A"])
+    return inst
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_penrose_finish_fp64(qctx, rank_def, mode):
+    """FP64 solve with the guarded stop, then X A X (mode 1) or the projection (X A)^H X (A X)^H and one
+    Newton-Schulz update (mode 2): the oracle's returned iterate with the same steps."""
+    import paper_2605_01464_amd as q
+
+    A = rank_def["A"]
+    alpha = M.alpha_sigma(A)
+    ro = M.solve(A, "qhpi19", alpha=alpha, tol=1e-15, stop="guarded", side="left", max_iter=80)
+    try:
+        qctx.set("penrose_finish", mode)
+        X, info = q.solve(qctx, to_dev(A, "f64"), "qhpi19", scaling="given", alpha=alpha, tol=1e-15, stop="guarded",
+                          precision="f64", max_iter=80)
+    finally:
+        qctx.set("penrose_finish", 0)
+    if mode == 1:
+        ref = Q.qmul(Q.qmul(ro.X, A), ro.X)
+        assert info["iters"] == ro.iters and info["returned"] == ro.returned
+    else:
+        ref = M.step(A, M.penrose_projection(A, ro.X), "ns", 2, "left")
+        assert info["iters"] == ro.iters + 1 and info["returned"] == ro.returned + 1
+    assert rel_fro(to_np(X), ref) <= 1e-8
+    truth = Q.pinv_from_factors(rank_def["U"], rank_def["s"], rank_def["V"])
+    print(f"mode {mode}: vs oracle {rel_fro(to_np(X), ref):.2e}, vs rank-60 pinv {rel_fro(to_np(X), truth):.2e}")
+
+
+def test_penrose_finish_in_fp64_finish(qctx, rank_def):
+    """FP32 QHPI19 with the FP64 finish and the projection before its last update: the oracle's schedule from
+    the FP32 phase's exit iterate, and closer to the rank-60 pseudoinverse than the finish without it."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    A = rank_def["A"]
+    truth = Q.pinv_from_factors(rank_def["U"], rank_def["s"], rank_def["V"])
+    out = {}
+    for mode in (0, 2):
+        try:
+            qctx.set("penrose_finish", mode)
+            X, info = q.solve(qctx, to_dev(A, "f32"), "qhpi19", scaling="power", tol=1e-6, stop="guarded",
+                              precision="f32_f64finish", out_dtype=torch.float64)
+        finally:
+            qctx.set("penrose_finish", 0)
+        out[mode] = (to_np(X), info)
+    X2, info = out[2]
+    assert info["status"] == q.OK and info["iters_f64"] == 2, info
+    j_star = info["returned"] - info["iters_f64"]
+    Xo = M.x0(A, info["alpha_used"])
+    for _ in range(j_star):
+        Xo = M.step(A, Xo, "qhpi19", 19, "left")
+    Xo = M.step(A, Xo, "ns", 2, "left")
+    Xo = M.step(A, M.penrose_projection(A, Xo), "ns", 2, "left")
+    assert rel_fro(X2, Xo) <= 1e-4
+    assert rel_fro(X2, truth) < rel_fro(out[0][0], truth)
+
+
+def test_penrose_projection_needs_fp64_updates(qctx, rank_def):
+    import paper_2605_01464_amd as q
+
+    try:
+        qctx.set("penrose_finish", 2)
+        _, info = q.solve(qctx, to_dev(rank_def["A"], "f32"), "qhpi19", precision="f32", check=False)
+    finally:
+        qctx.set("penrose_finish", 0)
+    assert info["status"] == q.EINVAL

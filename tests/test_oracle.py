@@ -472,3 +472,33 @@ def test_residuals_spectral_iterate():
     nr = r["E_rel"]
     assert nr[0] == pytest.approx(E1 / float(np.linalg.norm(s)), rel=1e-12)
     assert nr[1] == pytest.approx(E2 / float(np.linalg.norm(x)), rel=1e-12)
+
+
+def test_penrose_projection():
+    """(X A)^H X (A X)^H: A^dagger is a fixed point; on X = A^dagger + E with E supported on the blocks outside
+    range(A^H) x range(A) (rows in the null space of A, or columns in the null space of A^H), it returns A^dagger
+    up to second order in E, while X A X keeps the mixed blocks (every {2}-inverse is its fixed point)."""
+    inst = qsynth.small_spectral_instance(102, 9, 7, [2.0, 1.0, 0.5, 0.25])   # rank 4
+    A, U, s, V = inst["A"], inst["U"], inst["s"], inst["V"]
+    Ad = Q.pinv_from_factors(U, s, V)
+    np.testing.assert_allclose(M.penrose_projection(A, Ad), Ad, atol=1e-12)
+    # null-space bases: complements of V (7 x 4 -> 3 more columns) and U (9 x 4 -> 5 more)
+    full_V = qsynth.stiefel(103, 7, 7)
+    PV = Q.qmul(V, Q.qH(V))
+    Vn = full_V - Q.qmul(PV, full_V)                       # columns in null(A)
+    PU = Q.qmul(U, Q.qH(U))
+    full_U = qsynth.stiefel(104, 9, 9)
+    Un = full_U - Q.qmul(PU, full_U)                       # columns in null(A^H)
+    eps = 1e-6
+    E_nr = eps * Q.qmul(Q.qmul(Vn, rand_q(105, 7, 4)), Q.qH(U))      # rows outside range(A^H), columns in range(A)
+    E_rn = eps * Q.qmul(Q.qmul(V, rand_q(106, 4, 9)), Q.qH(Un))      # rows in range(A^H), columns outside range(A)
+    X = Ad + E_nr + E_rn
+    P = M.penrose_projection(A, X)
+    assert Q.fro(P - Ad) <= 1e3 * eps ** 2 * Q.fro(Ad)
+    XAX = Q.qmul(Q.qmul(X, A), X)
+    assert Q.fro(XAX - Ad) >= 0.5 * Q.fro(E_nr + E_rn)
+    # the projection of anything has rows in range(A^H) and columns in range(A)
+    Y = rand_q(107, 7, 9)
+    PY = M.penrose_projection(A, Y)
+    np.testing.assert_allclose(Q.qmul(PV, PY), PY, atol=1e-10 * Q.fro(PY))
+    np.testing.assert_allclose(Q.qmul(PY, PU), PY, atol=1e-10 * Q.fro(PY))
