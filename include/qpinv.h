@@ -69,10 +69,12 @@ typedef enum {
   QPINV_ALPHA_FROB = 1,    /* alpha = 1 / ||A||_F^2 (Section 4 experimental setup) */
   QPINV_ALPHA_GIVEN = 2,   /* alpha = alpha_or_mu (e.g. 1/sigma_max(A^C)^2 of Algorithms 1-3) */
   QPINV_ALPHA_LEARNED = 3, /* mu predicted by the scaling network (qpinv_mlp_*), clamped to
-                              [sigma1_est^2 / min(||A||_F^2, ||A||_1 ||A||_inf), 1.9]; when mu > 1 the
-                              first residual's 2-norm is estimated (3 power steps) and a value above
-                              1 + 1e-3 restarts with mu = 1 (POWER), as does divergence; POWER when
-                              no network is loaded */
+                              [sigma1_est^2 / min(||A||_F^2, ||A||_1 ||A||_inf), 1.9] (the lower end is
+                              certified, the upper is not: sigma1_est^2 <= sigma_1^2); the solve restarts
+                              with mu = 1 (POWER) when it diverges or reaches max_iter, and, for stop
+                              rules other than E1_REL (whose test certifies the result), when mu > 1
+                              and the first residual's 2-norm estimate (3 power steps) exceeds
+                              1 + 1e-3; POWER when no network is loaded */
   QPINV_X0_GIVEN = 4       /* X holds X_0 on entry (warm start / resume) */
 } qpinv_scaling;
 
@@ -313,9 +315,10 @@ int qpinv_features(qpinv_ctx* ctx, const qpinv_qmat* A, int power_steps, double 
  * matrix, given as rows of 7 doubles (sigma1_est^2, previous estimate, ||A||_F, ||A||_1, ||A||_inf,
  * rows, cols) -- the order qpinv_features reports them in, with the previous estimate moved second.
  * ALPHA_LEARNED solves use it once a network is loaded (trained or set); the predicted mu is clamped
- * into [sigma1_est^2 / min(||A||_F^2, ||A||_1 ||A||_inf), 1.9] (Theorem 1's interval as far as cheap
- * bounds certify it), and the classical alpha = 1/sigma1_est^2 replaces it when ||I - X_0 A||_2 > 1 or
- * the iteration diverges.  All arrays below are DEVICE arrays unless marked host. */
+ * into [sigma1_est^2 / min(||A||_F^2, ||A||_1 ||A||_inf), 1.9] (only the lower end is certified inside
+ * Theorem 1's interval), and the classical alpha = 1/sigma1_est^2 replaces it when the iteration diverges
+ * or reaches max_iter, or (stop rules other than E1_REL) when ||I - X_0 A||_2 is estimated above 1.
+ * All arrays below are DEVICE arrays unless marked host. */
 
 /* (Re)initialise the network weights (Xavier-uniform, SplitMix64 stream `seed`) and the optimiser. */
 int qpinv_mlp_init(qpinv_ctx* ctx, uint64_t seed);

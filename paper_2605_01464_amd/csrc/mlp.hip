@@ -188,26 +188,27 @@ __global__ void __launch_bounds__(1024) train_kernel(float* __restrict__ P, floa
 }
 
 // y = log mu for `count` raw feature rows; mu = exp(y)
-__global__ void __launch_bounds__(256) predict_kernel(const float* __restrict__ P, const float* __restrict__ norm,
-                                                      const double* __restrict__ raw, int count, double* __restrict__ mu) {
-  const int b = blockIdx.x * 256 + threadIdx.x;
+// Inference, one 64-lane wave per sample: lane k forms hidden unit k of each layer (its sums run over the
+// layer's inputs in index order), and the output is the wave's sum of tanh(layer 2) * w3 plus the bias.
+// A single solve thus waits for two short layers of parallel loads instead of one thread's 4.7k.
+__global__ void __launch_bounds__(64) predict_kernel(const float* __restrict__ P, const float* __restrict__ norm,
+                                                     const double* __restrict__ raw, int count, double* __restrict__ mu) {
+  static_assert(MH == 64, "one lane per hidden unit");
+  const int b = blockIdx.x, k = threadIdx.x;
   if (b >= count) return;
+  __shared__ float h1s[MH];
   float f[MF];
   transform_raw(raw + 7 * (int64_t)b, f);
-  for (int k = 0; k < MF; ++k) f[k] = (f[k] - norm[k]) / norm[MF + k];
-  float h1[MH];
-  for (int k = 0; k < MH; ++k) {
-    float a = P[OB1 + k];
-    for (int q = 0; q < MF; ++q) a += f[q] * P[OW1 + q * MH + k];
-    h1[k] = tanhf(a);
-  }
-  float y = P[OB3];
-  for (int j = 0; j < MH; ++j) {
-    float a = P[OB2 + j];
-    for (int k = 0; k < MH; ++k) a += h1[k] * P[OW2 + k * MH + j];
-    y += tanhf(a) * P[OW3 + j];
-  }
-  mu[b] = exp((double)y);
+  for (int q = 0; q < MF; ++q) f[q] = (f[q] - norm[q]) / norm[MF + q];
+  float a = P[OB1 + k];
+  for (int q = 0; q < MF; ++q) a += f[q] * P[OW1 + q * MH + k];
+  h1s[k] = tanhf(a);
+  __syncthreads();
+  float a2 = P[OB2 + k];
+  for (int q = 0; q < MH; ++q) a2 += h1s[q] * P[OW2 + q * MH + k];
+  float t = tanhf(a2) * P[OW3 + k];
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+  if (k == 0) mu[b] = exp((double)(P[OB3] + t));
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -399,7 +400,7 @@ double mlp_train_step(Ctx& c, const double* raw, const double* target, const int
 void mlp_predict(Ctx& c, const double* raw, int count, double* mu, hipStream_t st) {
   MlpState& s = state(c);
   if (count <= 0) return;
-  hipLaunchKernelGGL(predict_kernel, dim3((count + 255) / 256), dim3(256), 0, st, s.p, s.norm, raw, count, mu);
+  hipLaunchKernelGGL(predict_kernel, dim3(count), dim3(64), 0, st, s.p, s.norm, raw, count, mu);
   QP_HIP(hipGetLastError());
 }
 

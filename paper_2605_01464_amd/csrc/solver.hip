@@ -942,8 +942,9 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
         mlp_predict(c, raw, 1, c.dsc + 56, s);
         to_host(c, c.dsc + 56, 1, s);
         double mul = c.hsc[0];
-        // clamp into (0, 2/sigma_1^2) as far as cheap bounds allow: sigma_1 <= U = min(||A||_F,
-        // sqrt(||A||_1 ||A||_inf)) gives mu >= s1sq / U^2; above, mu <= 1.9
+        // clamp: sigma_1 <= U = min(||A||_F, sqrt(||A||_1 ||A||_inf)) makes mu >= s1sq / U^2 a certified
+        // lower end (alpha >= 1/U^2 > 0); the upper end 1.9 is not certified (sigma1_est^2 underestimates
+        // sigma_1^2), which the residual guard and the restart on divergence or max_iter cover
         const double U2 = std::min(nh[0], nh[1] * nh[2]);
         const double lo = inf.sigma1_sq_est / U2, hi = 1.9;
         if (!std::isfinite(mul) || mul < lo || mul > hi) {
@@ -1016,8 +1017,36 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     return -1;
   };
 
+  // the learned alpha failed (divergence, no convergence within max_iter, or an estimated ||R_0||_2 above 1):
+  // start over from the classical alpha
+  auto restart_classical = [&]() {
+    learned = false;
+    inf.fallback_used = 1;
+    alpha = alpha_classical;
+    inf.alpha_used = alpha;
+    inf.mu_used = 1.0;
+    dt = store_of(phases[0]);
+    ph = 0;
+    S = &set_of(dt);
+    cur = 0;
+    x0_into(A_of(dt), alpha, S->b[cur], s);
+    j = 0;
+    inf.iters_bf16 = inf.iters_f32 = inf.iters_f64 = 0;
+    ctl = StopController(stop, tol);
+    xnorm_hist.assign(1, 0.0);
+    best_pair[0] = best_pair[1] = -1;
+    best_j = -1;
+    rsave_j[0] = rsave_j[1] = -1;
+    rprev = -1.0;
+    d_prev_finish = -1.0;
+  };
+
   while (!done) {
     const Prec p = phases[ph];
+    if (j >= max_iter && learned) {
+      restart_classical();
+      continue;
+    }
     if (j >= max_iter) {
       status = QPINV_ENOTCONVERGED;
       inf.stop_reason = QPINV_REASON_MAX_ITER;
@@ -1030,8 +1059,10 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     Mat R;
     const bool main_phase = p != P_BF16 && !(has_finish && ph == phases.size() - 1);
     const bool keep_R = main_phase && stop == STOP_GUARDED;
-    // the classical alpha (mu = 1) carries no more risk than the default; only a larger learned mu is checked
-    const bool guard_R = learned && j == 0 && inf.mu_used > 1.0;
+    // the classical alpha (mu = 1) carries no more risk than the default; only a larger learned mu is checked,
+    // and not under the E1 stop rule: ||A X A - A||_F <= tol ||A||_F certifies the result whatever alpha it
+    // started from, and an inadmissible alpha never gets there (divergence or max_iter restart it)
+    const bool guard_R = learned && j == 0 && inf.mu_used > 1.0 && stop != STOP_E1_REL;
     const bool want_R = (p == P_BF16) || keep_R || guard_R;
     const bool in_finish = has_finish && ph == phases.size() - 1;
     const int it_method = in_finish ? fin_method : method, it_order = in_finish ? fin_order : order;
@@ -1045,12 +1076,7 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
       // has exactly these eigenvalues (and 1 on the null space), so ||R_0||_2 > 1 means divergence
       const double r0 = std::sqrt(std::max(0.0, power_host(c, R, 3, s)));
       if (r0 > 1.0 + 1e-3) {
-        learned = false;
-        inf.fallback_used = 1;
-        alpha = alpha_classical;
-        inf.alpha_used = alpha;
-        inf.mu_used = 1.0;
-        x0_into(A_of(dt), alpha, S->b[cur], s);
+        restart_classical();
         continue;
       }
     }
@@ -1081,26 +1107,7 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
 
     const bool diverged = !std::isfinite(d_abs) || !std::isfinite(xn) || xn * normA > 1e20;
     if (diverged && learned) {
-      // the learned alpha failed: start over from the classical alpha
-      learned = false;
-      inf.fallback_used = 1;
-      alpha = alpha_classical;
-      inf.alpha_used = alpha;
-      inf.mu_used = 1.0;
-      dt = store_of(phases[0]);
-      ph = 0;
-      S = &set_of(dt);
-      cur = 0;
-      x0_into(A_of(dt), alpha, S->b[cur], s);
-      j = 0;
-      inf.iters_bf16 = inf.iters_f32 = inf.iters_f64 = 0;
-      ctl = StopController(stop, tol);
-      xnorm_hist.assign(1, 0.0);
-      best_pair[0] = best_pair[1] = -1;
-      best_j = -1;
-      rsave_j[0] = rsave_j[1] = -1;
-      rprev = -1.0;
-      d_prev_finish = -1.0;
+      restart_classical();
       continue;
     }
     if (diverged) {

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import qsynth
-from conftest import to_dev
+from conftest import rel_fro, to_dev, to_np
 from oracle import methods as M
 from oracle import mlp as OM
 
@@ -125,17 +125,49 @@ def test_labels_match_spectral_model(qctx, method, order):
 
 
 def test_label_counts_equal_gpu_fp64_solves(qctx):
-    """The spectral iteration count is what an FP64 QHPI19 solve with that alpha actually takes (+-1)."""
+    """The spectral iteration count behind the labels is what an FP64 QHPI19 solve with that alpha actually
+    takes (+-1): 12 matrices of 256..512 (4 per spectrum family) at three points of the label grid."""
     import paper_2605_01464_amd as q
 
-    for seed in (11, 12, 13):
-        d = qsynth.c5_sample(seed, shape=(140, 100))
+    seen = {f: 0 for f in qsynth.C5_FAMILIES}
+    seed = 70_000
+    while min(seen.values()) < 4:
+        d = qsynth.c5_sample(seed, size_range=(256, 512))
+        seed += 1
+        if seen[d["family"]] >= 4:
+            continue
+        seen[d["family"]] += 1
         s = d["s"]
-        alpha = 1.3 / s[0] ** 2
-        J = M.spectral_iterations(s, alpha, "qhpi19", 19, 1e-10)
-        _, info = q.solve(qctx, to_dev(d["A"], "f64"), "qhpi19", scaling="given", alpha=alpha, tol=1e-10,
-                          stop="e1_rel", precision="f64", max_iter=60)
-        assert abs(info["iters"] - J) <= 1, (seed, info["iters"], J)
+        Ad = to_dev(d["A"], "f64")
+        for mu in (0.6, 1.0, 1.6):
+            alpha = mu / s[0] ** 2
+            J = M.spectral_iterations(s, alpha, "qhpi19", 19, 1e-10)
+            _, info = q.solve(qctx, Ad, "qhpi19", scaling="given", alpha=alpha, tol=1e-10, stop="e1_rel",
+                              precision="f64", max_iter=60)
+            assert abs(info["iters"] - J) <= 1, (seed, d["family"], mu, info["iters"], J)
+
+
+@pytest.mark.parametrize("seed", [2_000_000, 2_000_001, 2_000_008])  # geometric, clustered, low rank + noise
+def test_eval_size_parity_vs_oracle(qctx, seed):
+    """Held-out 1024 x 768 evaluation matrices, FP64 QHPI19 to ||AXA - A||_F / ||A||_F <= 1e-10 from the shipped
+    network's alpha and from the classical alpha: each X against the oracle's solve from the same alpha, same
+    stop rule and side, <= 1e-9, with the same update count."""
+    import sys
+
+    import paper_2605_01464_amd as q
+    from paper_2605_01464_amd import learned as L
+
+    d = qsynth.c5_sample(seed, shape=(1024, 768))
+    L.load(qctx)
+    Ad = to_dev(d["A"], "f64")
+    for scaling in ("learned", "power"):
+        X, info = q.solve(qctx, Ad, "qhpi19", scaling=scaling, tol=1e-10, stop="e1_rel", precision="f64", max_iter=60)
+        assert info["status"] == q.OK and info["reason"] == "tol", info
+        print(f"{d['family']} {scaling}: mu {info['mu_used']:.3f}, {info['iters']} updates; oracle", file=sys.stderr,
+              flush=True)
+        ro = M.solve(d["A"], "qhpi19", alpha=info["alpha_used"], tol=1e-10, stop="e1_rel", side="left", max_iter=60)
+        assert info["iters"] == ro.iters, (info["iters"], ro.iters)
+        assert rel_fro(to_np(X), ro.X) <= 1e-9
 
 
 def test_trained_network_gain(qctx):
@@ -155,9 +187,28 @@ def test_trained_network_gain(qctx):
     assert res["best"]["mean_iters"] <= res["learned"]["mean_iters"] + 1.0
 
 
-def test_learned_guard_falls_back(qctx):
+def test_shipped_network_pays_at_eval_size(qctx):
+    """The shipped network (trained on 20k matrices of 64..512) on the first 64 held-out 1024 x 768 evaluation
+    matrices, FP64 QHPI19 to E1_rel <= 1e-10, arms interleaved per matrix: fewer updates on average than the
+    classical alpha = 1/sigma1_est^2, and less wall time per solve (features, network and updates included)."""
+    import paper_2605_01464_amd as q
+    from paper_2605_01464_amd import learned as L
+
+    L.load(qctx)
+    ev = L.build_set(qctx, range(2_000_000, 2_000_064), shape=(1024, 768), keep=True)
+    L.evaluate(qctx, ev["mats"][:4], ev)  # warm-up
+    res, _ = L.evaluate(qctx, ev["mats"], ev)
+    print({k: res[k] for k in ("learned", "classical", "best")})
+    assert res["learned_fallbacks"] == 0
+    assert res["learned"]["mean_iters"] < res["classical"]["mean_iters"]
+    assert res["learned"]["mean_ms"] < res["classical"]["mean_ms"]
+
+
+@pytest.mark.parametrize("stop", ["e1_rel", "guarded"])
+def test_learned_guard_falls_back(qctx, stop):
     """A network that always answers mu = 1.9 on a matrix whose power estimate is low enough that
-    1.9 / sigma1_est^2 > 2 / sigma_1^2: the ||I - X_0 A||_2 > 1 guard restarts with the classical alpha."""
+    1.9 / sigma1_est^2 > 2 / sigma_1^2: under the E1 stop the divergence restarts the solve from the classical
+    alpha, under the guarded stop the ||I - X_0 A||_2 > 1 estimate does before the first update."""
     import paper_2605_01464_amd as q
 
     theta = np.zeros(OM.NPARAM, dtype=np.float32)
@@ -169,10 +220,31 @@ def test_learned_guard_falls_back(qctx):
     inst = qsynth.small_spectral_instance(21, 90, 70, s)
     qctx.set("power_steps", 3)
     try:
-        X, info = q.solve(qctx, to_dev(inst["A"], "f64"), "qhpi19", scaling="learned", tol=1e-10, stop="e1_rel",
+        X, info = q.solve(qctx, to_dev(inst["A"], "f64"), "qhpi19", scaling="learned", tol=1e-10, stop=stop,
                           precision="f64")
+        Xc, ic = q.solve(qctx, to_dev(inst["A"], "f64"), "qhpi19", scaling="power", tol=1e-10, stop=stop,
+                         precision="f64")
     finally:
         qctx.set("power_steps", 8)
     assert 1.9 / info["sigma1_sq_est"] > 2.0 / s[0] ** 2  # the network's alpha lies outside Theorem 1's interval
-    assert info["fallback_used"] == 1 and info["reason"] == "tol"
+    assert info["fallback_used"] == 1 and info["reason"] in (("tol",) if stop == "e1_rel" else ("tol", "rise"))
     assert info["alpha_used"] == pytest.approx(1.0 / info["sigma1_sq_est"])
+    assert ic["iters"] == info["iters"] and rel_fro(to_np(X), to_np(Xc)) == 0.0
+
+
+def test_learned_restarts_at_max_iter(qctx):
+    """A learned solve that reaches max_iter without meeting its test starts over from the classical alpha (a
+    constant network answering mu = 0.05 on a flat spectrum 1 .. 0.9, where the clamp's lower end is 0.016:
+    3 updates against the classical alpha's 1 by the spectral model, with max_iter = 1)."""
+    import paper_2605_01464_amd as q
+
+    theta = np.zeros(OM.NPARAM, dtype=np.float32)
+    theta[-1] = np.log(0.05)
+    q._err(q.qpinv_mlp_set_params(qctx.handle, list(np.concatenate([theta, np.zeros(10), np.ones(10)]))), "set")
+    inst = qsynth.small_spectral_instance(22, 90, 70, np.linspace(1.0, 0.9, 70))
+    Ad = to_dev(inst["A"], "f64")
+    Xc, ic = q.solve(qctx, Ad, "qhpi19", scaling="power", tol=1e-10, stop="e1_rel", precision="f64", max_iter=40)
+    X, info = q.solve(qctx, Ad, "qhpi19", scaling="learned", tol=1e-10, stop="e1_rel", precision="f64",
+                      max_iter=ic["iters"])
+    assert info["fallback_used"] == 1 and info["status"] == q.OK and info["reason"] == "tol", info
+    assert info["iters"] == ic["iters"] and rel_fro(to_np(X), to_np(Xc)) == 0.0
