@@ -74,6 +74,9 @@ void set_option(qp::Ctx& c, const std::string& key, double v) {
   } else if (key == "finish_method") {
     need(v == -1 || v == QPINV_NS || v == QPINV_QSAI || v == QPINV_QHPI19);
     c.opt.finish_method = (int)v;
+  } else if (key == "small_path") {
+    need(v == 0 || v == 1);
+    c.opt.small_path = (int)v;
   } else if (key == "penrose_finish") {
     need(v == 0 || v == 1 || v == 2);
     c.opt.penrose_finish = (int)v;

@@ -114,6 +114,7 @@ Ctx::Ctx(int dev) : device(dev) {
   QP_HIP(hipMalloc(&scratch.partial, sizeof(double) * scratch.capacity));
   QP_HIP(hipMalloc(&dsc, sizeof(double) * 64));
   QP_HIP(hipHostMalloc(&hsc, sizeof(double) * 64, hipHostMallocDefault));
+  QP_HIP(hipHostMalloc(&hstage, kStageBytes, hipHostMallocDefault));
   (void)noalloc_scratch(dev);  // look up this device's no-allocation scratch now, with the device current
 }
 
@@ -130,6 +131,7 @@ Ctx::~Ctx() {
   if (scratch.stage) (void)hipFree(scratch.stage);
   if (dsc) (void)hipFree(dsc);
   if (hsc) (void)hipHostFree(hsc);
+  if (hstage) (void)hipHostFree(hstage);
 }
 
 int Ctx::config_for(Prec p, int64_t M, int64_t N, int64_t K, hipStream_t s) {
@@ -882,6 +884,8 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     return status;
   };
   if (m == 0 || n == 0) return finish(QPINV_OK);
+  if (small_eligible(c, method, scaling, stop, precision, m, n))
+    return finish(small_solve(c, method, A0, scaling, am, tol, max_iter, stop, precision, Xout, inf, s));
 
   // A in each storage type on demand
   Mat Acache[2];

@@ -40,6 +40,7 @@ struct Options {
   int f64_refined = 1;  // 1: FP64 finish updates with FP64 residual and sum, FP32 polynomial (NS, HPI, QSAI, QHPI19)
   int finish_method = QPINV_NS;  // method of the FP64 finish updates (-1: the solve's own method)
   int penrose_finish = 0;        // FP64 projection of the returned iterate: 0 none, 1 X A X, 2 (X A)^H X (A X)^H
+  int small_path = 1;            // single solves of at most 128 per side in one launch (small.hip) when eligible
   double mixed_switch = 1e-2;
   int mixed_rnorm_steps = 6;
   int max_bf16_iters = 8;
@@ -60,11 +61,14 @@ struct Ctx {
   GemmScratch scratch;
   double* dsc = nullptr;  // device scalars
   double* hsc = nullptr;  // pinned host scalars
+  static constexpr size_t kStageBytes = 8192;
+  void* hstage = nullptr;  // pinned host staging area for small parameter blocks (kStageBytes)
   std::map<std::tuple<int, int64_t, int64_t, int64_t>, int> tuned;
   MlpState* mlp = nullptr;
   BatchedState* batched = nullptr;
   std::map<std::vector<int64_t>, int> batched_tuned;  // batch signature -> tile configuration
   bool no_alloc = false;  // allocation-free call in progress: no autotuning, no product timing, no growth
+  void* small_state = nullptr;  // the small solve's record whose barrier words are known to be clear
   double flops = 0.0;  // running count of algorithmic product flops
   // event pairs around product launches (option gemm_timing)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -105,6 +109,11 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* A, int scaling, doubl
 // The same solve with every workspace buffer carved from the device's static no-allocation scratch (noalloc.hip).
 int solve_noalloc(Ctx& c, int method, int order, const qpinv_qmat* A, int scaling, double alpha_or_mu, double tol,
                   int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info, hipStream_t s);
+
+// One-launch solve of a small matrix (small.hip): eligibility and the solve (returns a status code).
+bool small_eligible(const Ctx& c, int method, int scaling, int stop, int precision, int64_t m, int64_t n);
+int small_solve(Ctx& c, int method, const Mat& A0, int scaling, double am, double tol, int max_iter, int stop,
+                int precision, const Mat& Xout, qpinv_info& inf, hipStream_t s);
 
 // Address of the device's no-allocation scratch, looked up once per device with that device current (noalloc.hip).
 void* noalloc_scratch(int device);

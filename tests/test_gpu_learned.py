@@ -222,10 +222,12 @@ def test_learned_guard_falls_back(qctx, stop):
     try:
         X, info = q.solve(qctx, to_dev(inst["A"], "f64"), "qhpi19", scaling="learned", tol=1e-10, stop=stop,
                           precision="f64")
+        qctx.set("small_path", 0)  # the learned solve runs product by product: compare with the same path
         Xc, ic = q.solve(qctx, to_dev(inst["A"], "f64"), "qhpi19", scaling="power", tol=1e-10, stop=stop,
                          precision="f64")
     finally:
         qctx.set("power_steps", 8)
+        qctx.set("small_path", 1)
     assert 1.9 / info["sigma1_sq_est"] > 2.0 / s[0] ** 2  # the network's alpha lies outside Theorem 1's interval
     assert info["fallback_used"] == 1 and info["reason"] in (("tol",) if stop == "e1_rel" else ("tol", "rise"))
     assert info["alpha_used"] == pytest.approx(1.0 / info["sigma1_sq_est"])
@@ -243,7 +245,11 @@ def test_learned_restarts_at_max_iter(qctx):
     q._err(q.qpinv_mlp_set_params(qctx.handle, list(np.concatenate([theta, np.zeros(10), np.ones(10)]))), "set")
     inst = qsynth.small_spectral_instance(22, 90, 70, np.linspace(1.0, 0.9, 70))
     Ad = to_dev(inst["A"], "f64")
-    Xc, ic = q.solve(qctx, Ad, "qhpi19", scaling="power", tol=1e-10, stop="e1_rel", precision="f64", max_iter=40)
+    qctx.set("small_path", 0)  # the learned solve runs product by product: compare with the same path
+    try:
+        Xc, ic = q.solve(qctx, Ad, "qhpi19", scaling="power", tol=1e-10, stop="e1_rel", precision="f64", max_iter=40)
+    finally:
+        qctx.set("small_path", 1)
     X, info = q.solve(qctx, Ad, "qhpi19", scaling="learned", tol=1e-10, stop="e1_rel", precision="f64",
                       max_iter=ic["iters"])
     assert info["fallback_used"] == 1 and info["status"] == q.OK and info["reason"] == "tol", info

@@ -278,3 +278,87 @@ def test_penrose_projection_needs_fp64_updates(qctx, rank_def):
     finally:
         qctx.set("penrose_finish", 0)
     assert info["status"] == q.EINVAL
+
+
+# ------------------------------------------------------------------ one-launch path for small matrices
+SMALL_SHAPES = [(64, 48), (48, 64), (37, 29), (29, 37), (128, 128), (128, 97), (1, 1), (9, 1), (1, 7)]
+
+
+@pytest.mark.parametrize("shape", SMALL_SHAPES)
+@pytest.mark.parametrize("method,order", [("ns", 2), ("qsai", 10), ("qhpi19", 19)])
+@pytest.mark.parametrize("stop,scaling", [("e1_rel", "power"), ("dx_rel", "frob"), ("dx_abs", "given")])
+def test_small_path_matches_oracle_and_regular_path(qctx, shape, method, order, stop, scaling):
+    """FP64 solves of at most 128 per side run as one launch (small_path = 1, the default): the same update
+    count and returned iterate as the oracle from the same alpha (<= 1e-12) and as the product-by-product
+    path (small_path = 0)."""
+    import paper_2605_01464_amd as q
+
+    A = np.random.default_rng(40 + shape[0] + 3 * shape[1]).standard_normal((4,) + shape)
+    alpha = 0.9 * M.alpha_sigma(A) if scaling == "given" else 0.0
+    tol = {"e1_rel": 1e-12, "dx_rel": 1e-12, "dx_abs": 1e-10 * Q.fro(Q.pinv_svd(A))}[stop]
+    kw = dict(scaling=scaling, alpha=alpha, tol=tol, stop=stop, precision="f64", max_iter=100)
+    Ad = to_dev(A, "f64")
+    X, info = q.solve(qctx, Ad, method, order, **kw)
+    try:
+        qctx.set("small_path", 0)
+        Xr, ir = q.solve(qctx, Ad, method, order, **kw)
+    finally:
+        qctx.set("small_path", 1)
+    side = "left" if shape[0] > shape[1] else "right"
+    ro = M.solve(A, method, order, alpha=info["alpha_used"], tol=tol, stop=stop, side=side, max_iter=100)
+    assert info["status"] == q.OK and info["reason"] == "tol", info
+    assert info["iters"] == ro.iters == ir["iters"], (info["iters"], ro.iters, ir["iters"])
+    assert info["returned"] == ir["returned"] and info["side"] == ir["side"]
+    assert info["alpha_used"] == pytest.approx(ir["alpha_used"], rel=1e-13)
+    assert rel_fro(to_np(X), ro.X) <= 1e-12
+    assert rel_fro(to_np(X), to_np(Xr)) <= 1e-12
+    if stop == "e1_rel":
+        assert info["e1_rel"] <= tol
+
+
+@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("ns", 2)])
+def test_small_path_fp32(qctx, method, order):
+    """FP32 one-launch solves of a 100 x 70 matrix: the regular path's update count, and both within FP32
+    rounding of the oracle's iterate."""
+    import paper_2605_01464_amd as q
+
+    A = qsynth.round_f32(np.random.default_rng(43).standard_normal((4, 100, 70)))
+    kw = dict(scaling="power", tol=1e-6, stop="dx_rel", precision="f32", max_iter=100)
+    X, info = q.solve(qctx, to_dev(A, "f32"), method, order, **kw)
+    try:
+        qctx.set("small_path", 0)
+        Xr, ir = q.solve(qctx, to_dev(A, "f32"), method, order, **kw)
+    finally:
+        qctx.set("small_path", 1)
+    ro = M.solve(A, method, order, alpha=info["alpha_used"], tol=1e-12, stop="e1_rel", side="left")
+    assert info["status"] == q.OK and info["iters"] == ir["iters"], (info, ir)
+    assert rel_fro(to_np(X), ro.X) <= 2e-5 and rel_fro(to_np(Xr), ro.X) <= 2e-5
+
+
+def test_small_path_error_paths(qctx):
+    """The one-launch path's statuses: divergence for alpha outside Theorem 1's interval, max_iter, a
+    non-finite input, a zero matrix (pseudoinverse 0), an FP32 input solved in FP64 (converted first)."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    A = np.random.default_rng(44).standard_normal((4, 30, 20))
+    Ad = to_dev(A, "f64")
+    s1 = Q.singular_values(A)[0]
+    _, info = q.solve(qctx, Ad, "qhpi19", scaling="given", alpha=2.5 / s1 ** 2, tol=1e-12, stop="dx_rel",
+                      precision="f64", check=False)
+    assert info["status"] == q.EDIVERGED and info["reason"] == "diverged"
+    _, info = q.solve(qctx, Ad, "ns", scaling="given", alpha=1.0 / s1 ** 2, tol=0.0, max_iter=2, stop="e1_rel",
+                      precision="f64", check=False)
+    assert info["status"] == q.ENOTCONVERGED and info["iters"] == 2
+    Abad = A.copy()
+    Abad[2, 7, 3] = np.nan
+    _, info = q.solve(qctx, to_dev(Abad, "f64"), "qhpi19", stop="e1_rel", precision="f64", check=False)
+    assert info["status"] == q.ENONFINITE
+    Z = torch.zeros((4, 6, 4), dtype=torch.float64, device="cuda")
+    Xz, info = q.solve(qctx, Z, "qhpi19", stop="e1_rel", tol=1e-12, precision="f64")
+    assert info["status"] == q.OK and float(Xz.abs().max()) == 0.0
+    X64, info = q.solve(qctx, to_dev(A, "f32"), "qhpi19", stop="e1_rel", tol=1e-12, precision="f64",
+                        out_dtype=torch.float64)
+    ro = M.solve(qsynth.round_f32(A), "qhpi19", alpha=info["alpha_used"], tol=1e-12, stop="e1_rel", side="left")
+    assert info["iters"] == ro.iters and rel_fro(to_np(X64), ro.X) <= 1e-12
