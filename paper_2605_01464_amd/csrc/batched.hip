@@ -801,7 +801,7 @@ struct SParams {
   float* pool;
   double* partial;
   double* dwork;
-  unsigned int* bar;  // [0] arrivals, [1] generation, [2] timeout flag
+  unsigned int* bar;  // [0] group arrivals, [1] generation, [2] timeout flag, [BAR_GROUP + 64 g] arrivals of group g
   const double* alpha;
   int method, stop, max_iter;
   double tol;
@@ -819,30 +819,43 @@ constexpr int SYNC_MAX = 2048;   // matrices per launch (the per-phase tile pref
 constexpr int kTraceCap = 4096;  // time stamps kept per launch: barriers from 0, per-matrix set-up from the middle
 constexpr long long SPIN_MAX = 1ll << 22;  // barrier polls before the wait is abandoned
 
-// Grid barrier; returns false once any workgroup has abandoned a wait.
+// Grid barrier; returns false once any workgroup has abandoned a wait.  Two levels: a workgroup arrives on
+// its group's counter (group = blockIdx mod 8, the XCD it was dealt to; counters on separate 256-byte lines),
+// the group's last arrival arrives on the global counter, and the last of those moves the generation.  One
+// counter taking every arrival serialises them at the memory side (measured 57 us per barrier for 512
+// workgroups, 25 us with the groups).  Arrivals release this workgroup's writes; waiters poll the generation
+// relaxed and acquire once when it moves.
+constexpr int BAR_GROUP = 64, BAR_WORDS = BAR_GROUP + 64 * 8;
 __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    __threadfence();
-    const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const unsigned int g = blockIdx.x & 7u;
+    const unsigned int gsize = nblocks / 8u + ((nblocks & 7u) > g ? 1u : 0u);
+    const unsigned int ngroups = nblocks < 8u ? nblocks : 8u;
+    const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool last = false;
+    unsigned int* gw = &bar[BAR_GROUP + 64 * g];
+    if (__hip_atomic_fetch_add(gw, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == gsize) {
+      __hip_atomic_store(gw, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == ngroups) {
+        __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
       long long spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > SPIN_MAX) {
           __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __threadfence();
     if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ok = 0;
     s_ok = ok;
   }
@@ -1575,7 +1588,7 @@ __global__ void zero_int_kernel(int* p) {
 // timeout flag, barrier words and a status sentinel for every matrix (overwritten when it retires)
 __global__ void sync_reset_kernel(unsigned int* bar, BInfo* info, int count, unsigned int* qctr, int qcap) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 4) bar[i] = 0u;
+  for (int k = i; k < BAR_WORDS; k += gridDim.x * blockDim.x) bar[k] = 0u;
   for (int k = i; k < qcap; k += gridDim.x * blockDim.x) qctr[k] = 0u;
   for (int b = i; b < count; b += gridDim.x * blockDim.x) {
     info[b].iters = 0;
@@ -1637,7 +1650,7 @@ static void build_sync(BatchedState& st, const BKey& key, int64_t pool_cap, int6
   BDesc* d_desc = static_cast<BDesc*>(dev_alloc(st, sizeof(BDesc) * count));
   BInfo* d_info = static_cast<BInfo*>(dev_alloc(st, sizeof(BInfo) * count));
   LState* d_st = static_cast<LState*>(dev_alloc(st, sizeof(LState) * count));
-  unsigned int* d_bar = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * 4));
+  unsigned int* d_bar = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * BAR_WORDS));
   // one item counter per phase: (max_iter + 2) passes of at most 32 phases
   const int qcap = (key.max_iter + 2) * 32;
   unsigned int* d_qctr = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * (size_t)qcap));
