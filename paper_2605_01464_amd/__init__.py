@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from collections.abc import Sequence
 from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -187,15 +188,19 @@ def qpinv_solve_noalloc(ctx, method, order, A, scaling, alpha_or_mu, tol, max_it
     return st, info
 
 
-def qpinv_solve_batched(ctx, method, order, As, Xs, scaling, alphas, tol, max_iter, stop, stream=None):
+def qpinv_solve_batched(ctx, method, order, As, Xs, scaling, alphas, tol, max_iter, stop, stream=None, Aq=None,
+                        Xq=None):
+    """Aq, Xq: descriptor arrays of As, Xs already built (BatchArgs); the raw Info array is returned."""
     n = len(As)
-    Aq = (QMat * max(n, 1))(*[qmat(a) for a in As])
-    Xq = (QMat * max(n, 1))(*[qmat(x) for x in Xs])
-    al = (ctypes.c_double * max(n, 1))(*(alphas if alphas is not None else [0.0] * n))
+    if Aq is None:
+        Aq = (QMat * max(n, 1))(*[qmat(a) for a in As])
+    if Xq is None:
+        Xq = (QMat * max(n, 1))(*[qmat(x) for x in Xs])
+    al = (ctypes.c_double * max(n, 1))(*alphas) if alphas is not None else None
     infos = (Info * max(n, 1))()
-    st = _lib.qpinv_solve_batched(ctx, method, order, n, Aq, Xq, scaling, al if alphas is not None else None,
-                                  float(tol), int(max_iter), stop, infos, _stream(stream))
-    return st, [infos[i] for i in range(n)]
+    st = _lib.qpinv_solve_batched(ctx, method, order, n, Aq, Xq, scaling, al, float(tol), int(max_iter), stop, infos,
+                                  _stream(stream))
+    return st, infos
 
 
 def qpinv_step(ctx, method, order, side, gemm_prec, A, X_in, X_out, stream=None):
@@ -426,23 +431,69 @@ def solve_noalloc(ctx: Context, A, X, method="qhpi19", order=None, scaling="powe
     return d
 
 
+class BatchArgs:
+    """The marshalled arguments of a batched solve: the descriptors of the matrices As and of the outputs Xs
+    (allocated here when not given), built once.  Passing it to solve_batched in place of the list skips the
+    per-call marshalling of every tensor; the tensors must stay as they are (same storage, shape, strides)."""
+
+    def __init__(self, As, Xs=None):
+        import torch
+
+        self.As = list(As)
+        if Xs is None:
+            Xs = [torch.empty((4, a.shape[2], a.shape[1]), dtype=torch.float32, device=a.device) for a in self.As]
+        self.Xs = list(Xs)
+        if len(self.Xs) != len(self.As):
+            raise ValueError("one output per matrix")
+        n = max(len(self.As), 1)
+        self.Aq = (QMat * n)(*[qmat(a) for a in self.As])
+        self.Xq = (QMat * n)(*[qmat(x) for x in self.Xs])
+
+
+class BatchInfos(Sequence):
+    """The per-matrix results of a batched solve, each converted to a dict (as solve returns) when read."""
+
+    def __init__(self, raw, n):
+        self._raw, self._n, self._done = raw, n, {}
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[k] for k in range(*i.indices(self._n))]
+        if i < 0:
+            i += self._n
+        if not 0 <= i < self._n:
+            raise IndexError(i)
+        d = self._done.get(i)
+        if d is None:
+            d = self._raw[i].as_dict()
+            d["status"] = self._raw[i].reserved
+            self._done[i] = d
+        return d
+
+
 def solve_batched(ctx: Context, As, method="qhpi19", order=None, scaling="power", alphas=None, tol=1e-6,
                   max_iter=100, stop="guarded", Xs=None, stream=None, check=True):
-    """X_b ~= A_b^dagger for every FP32 matrix of the list, in one persistent launch.  Returns (Xs, infos)."""
+    """X_b ~= A_b^dagger for every FP32 matrix of the list (or of a BatchArgs), in one persistent launch.
+    Returns (Xs, infos)."""
     import torch
 
-    if Xs is None:
-        Xs = [torch.empty((4, a.shape[2], a.shape[1]), dtype=torch.float32, device=a.device) for a in As]
-    st, infos = qpinv_solve_batched(ctx.handle, METHOD[method], _order(method, order), As, Xs, SCALING[scaling],
-                                    alphas, tol, max_iter, STOP[stop], stream)
-    out = []
-    for inf in infos:
-        d = inf.as_dict()
-        d["status"] = inf.reserved
-        out.append(d)
+    if isinstance(As, BatchArgs):
+        if Xs is not None:
+            raise ValueError("the outputs of a BatchArgs are its own")
+        args = As
+        As, Xs, Aq, Xq = args.As, args.Xs, args.Aq, args.Xq
+    else:
+        if Xs is None:
+            Xs = [torch.empty((4, a.shape[2], a.shape[1]), dtype=torch.float32, device=a.device) for a in As]
+        Aq = Xq = None
+    st, raw = qpinv_solve_batched(ctx.handle, METHOD[method], _order(method, order), As, Xs, SCALING[scaling],
+                                  alphas, tol, max_iter, STOP[stop], stream, Aq, Xq)
     if check and st not in (OK, ENOTCONVERGED):
         _err(st, "qpinv_solve_batched")
-    return Xs, out
+    return Xs, BatchInfos(raw, len(As))
 
 
 def step(ctx: Context, A, X, method="qhpi19", order=None, side="auto", gemm_prec=None, out=None, stream=None):

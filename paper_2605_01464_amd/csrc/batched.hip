@@ -279,6 +279,96 @@ __device__ __forceinline__ double power_lds(const DM& A, int steps, unsigned lon
   return lam;
 }
 
+// Power iteration on A^H A in ONE pass over A per step, for n <= 64 PF_CH: lanes along the columns (chunk k
+// of a lane is column lane + 64 k), v in registers.  For a batch of PF_ROWS rows of a wave, w_i = (A v)_i /
+// ||v|| is the wave sum of the lanes' partial products, and each lane then adds conj(a_ij) w_i into its
+// columns of A^H w while the row is still in registers; the waves' partial A^H w are added in wave order
+// through LDS.  Half the reads of the two-pass form.  (Loading the next batch during this one's arithmetic
+// needs a second batch of registers, which the kernel's budget does not leave.)
+// vs: 4 n doubles; red: (waves) 4 x 64 doubles.  Returns ||w||^2 of the last step.
+constexpr int PF_CH = 4, PF_ROWS = 2;
+__device__ __forceinline__ double power_fused(const DM& A, int steps, unsigned long long seed, double* vs, double* red,
+                                              double* sh) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  const int m = A.rows, n = A.cols;
+  for (int e = tid; e < 4 * n; e += nthr) vs[e] = (double)(bsplitmix64((uint64_t)e, seed) >> 11) * 0x1p-52 - 1.0;
+  __syncthreads();
+  double lam = 0.0;
+  for (int step = 0; step < steps; ++step) {
+    double nv = 0.0;
+    for (int e = tid; e < 4 * n; e += nthr) nv += vs[e] * vs[e];
+    nv = wg_sum(nv, sh);
+    const double inv = 1.0 / sqrt(nv);
+    double vr[PF_CH][4], acc[PF_CH][4];
+#pragma unroll
+    for (int k = 0; k < PF_CH; ++k) {
+      const int j = lane + 64 * k;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        vr[k][p] = j < n ? vs[p * n + j] : 0.0;  // zero outside A: the clamped loads there add nothing to w
+        acc[k][p] = 0.0;
+      }
+    }
+    double l2 = 0.0;
+    for (int i0 = PF_ROWS * wave; i0 < m; i0 += PF_ROWS * nw) {
+      float a[PF_ROWS][PF_CH][4];
+#pragma unroll
+      for (int r = 0; r < PF_ROWS; ++r) {
+        const int64_t i = i0 + r < m ? i0 + r : m - 1;
+#pragma unroll
+        for (int k = 0; k < PF_CH; ++k) {
+          const int j = lane + 64 * k;
+          const int64_t o = i * A.ld + (j < n ? j : n - 1);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) a[r][k][p] = gload(A.p, p * A.ps + o);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < PF_ROWS; ++r) {
+        double w[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < PF_CH; ++k) {
+          const double as = a[r][k][0], ax = a[r][k][1], ay = a[r][k][2], az = a[r][k][3];
+          const double v0 = vr[k][0], vx = vr[k][1], vy = vr[k][2], vz = vr[k][3];
+          w[0] += as * v0 - ax * vx - ay * vy - az * vz;
+          w[1] += as * vx + ax * v0 + ay * vz - az * vy;
+          w[2] += as * vy - ax * vz + ay * v0 + az * vx;
+          w[3] += as * vz + ax * vy - ay * vx + az * v0;
+        }
+        const bool rin = i0 + r < m;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w[c] = rin ? wave_sum(w[c]) * inv : 0.0;
+        l2 += w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+#pragma unroll
+        for (int k = 0; k < PF_CH; ++k) {
+          const double as = a[r][k][0], ax = a[r][k][1], ay = a[r][k][2], az = a[r][k][3];
+          acc[k][0] += as * w[0] + ax * w[1] + ay * w[2] + az * w[3];
+          acc[k][1] += as * w[1] - ax * w[0] - ay * w[3] + az * w[2];
+          acc[k][2] += as * w[2] + ax * w[3] - ay * w[0] - az * w[1];
+          acc[k][3] += as * w[3] - ax * w[2] + ay * w[1] - az * w[0];
+        }
+      }
+    }
+    lam = wg_sum(lane == 0 ? l2 : 0.0, sh);  // every lane of a wave holds the wave's sum
+#pragma unroll
+    for (int k = 0; k < PF_CH; ++k) {
+      if (64 * k >= n) break;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) red[(wave * 4 + p) * 64 + lane] = acc[k][p];
+      __syncthreads();
+      for (int e = tid; e < 4 * 64; e += nthr) {
+        const int p = e >> 6, l = e & 63, j = 64 * k + l;
+        double t = 0.0;
+        for (int q = 0; q < nw; ++q) t += red[(q * 4 + p) * 64 + l];
+        if (j < n) vs[p * n + j] = t;
+      }
+      __syncthreads();
+    }
+  }
+  return lam;
+}
+
 // Per-matrix set-up by one workgroup: finiteness and ||A||_F, the scaling (power iteration on A^H A
 // from the SplitMix64 start vector, or the given alpha) and X_0 = alpha A^H into X0; A is also copied
 // to Ac unless Ac.p is null.  The power iteration keeps its vectors in `lds` (lds_floats floats) when
@@ -337,6 +427,11 @@ __device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsig
   normA = sqrt(fro2);
   if (scaling == 2) {
     alpha = alpha_given;
+  } else if (n <= 64 * PF_CH && 8 * n + 512 * nw <= lds_floats) {
+    const double lam = power_fused(A, power_steps, seed, reinterpret_cast<double*>(lds),
+                                   reinterpret_cast<double*>(lds) + 4 * n, sh);
+    info.sigma1_sq = lam;
+    alpha = 1.0 / lam;
   } else if (8 * (m + n) <= lds_floats) {
     const double lam = power_lds(A, power_steps, seed, reinterpret_cast<double*>(lds),
                                  reinterpret_cast<double*>(lds) + 4 * n, sh);
@@ -789,6 +884,7 @@ struct LState {
   int j;  // updates done; the current iterate is X_j
   int cur, best0, best1, best_j;
   int rsj0, rsj1;  // iterates whose residuals the R buffers 0 and 1 hold
+  unsigned int base;  // work items of this matrix completed before the current update (dataflow form)
   double alpha, normA, sigma1_sq, xn_prev, xn_a, xn_b, dx_rel;
   StopController ctl;
 };
@@ -813,27 +909,32 @@ struct SParams {
   unsigned int* qctr;  // per phase of the launch: the next work item (zeroed before the launch)
   int qctr_cap;        // phases with a counter; later phases (and dyn == 0) deal items g, g + G, ...
   int dyn;
+  unsigned int* done;  // dataflow form: work items completed per matrix (zeroed before the launch)
 };
 
 constexpr int SYNC_MAX = 2048;   // matrices per launch (the per-phase tile prefix lives in LDS)
-constexpr int kTraceCap = 4096;  // time stamps kept per launch: barriers from 0, per-matrix set-up from the middle
+// Verbose trace of one launch (100 MHz wall-clock ticks): barrier stamps of workgroup 0 from 0, the per-matrix
+// set-up durations from kTraceSetup, and every workgroup's time inside update work items from kTraceBusy.
+constexpr int kTraceCap = 8192;
+constexpr int kTraceSetup = 2048;
+constexpr int kTraceBusy = 4096;
 constexpr long long SPIN_MAX = 1ll << 22;  // barrier polls before the wait is abandoned
 
 // Grid barrier; returns false once any workgroup has abandoned a wait.  Two levels: a workgroup arrives on
-// its group's counter (group = blockIdx mod 8, the XCD it was dealt to; counters on separate 256-byte lines),
-// the group's last arrival arrives on the global counter, and the last of those moves the generation.  One
-// counter taking every arrival serialises them at the memory side (measured 57 us per barrier for 512
-// workgroups, 25 us with the groups).  Arrivals release this workgroup's writes; waiters poll the generation
-// relaxed and acquire once when it moves.
-constexpr int BAR_GROUP = 64, BAR_WORDS = BAR_GROUP + 64 * 8;
+// its group's counter (group = blockIdx mod BAR_NG, the XCD it was dealt to; counters on separate 256-byte
+// lines), the group's last arrival arrives on the global counter, and the last of those moves the generation.
+// One counter taking every arrival serialises them at the memory side (measured 57 us per barrier for 512
+// workgroups, 25 us with the groups; 32 groups, or sleeping between polls, measured no faster).  Arrivals
+// release this workgroup's writes; waiters poll the generation relaxed and acquire once when it moves.
+constexpr int BAR_NG = 8, BAR_GROUP = 64, BAR_WORDS = BAR_GROUP + 64 * BAR_NG;
 __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    const unsigned int g = blockIdx.x & 7u;
-    const unsigned int gsize = nblocks / 8u + ((nblocks & 7u) > g ? 1u : 0u);
-    const unsigned int ngroups = nblocks < 8u ? nblocks : 8u;
+    const unsigned int g = blockIdx.x % BAR_NG;
+    const unsigned int gsize = nblocks / BAR_NG + ((nblocks % BAR_NG) > g ? 1u : 0u);
+    const unsigned int ngroups = nblocks < (unsigned int)BAR_NG ? nblocks : (unsigned int)BAR_NG;
     const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool last = false;
     unsigned int* gw = &bar[BAR_GROUP + 64 * g];
@@ -1127,9 +1228,31 @@ __device__ __forceinline__ int next_buf(const LState& S) {
   return nxt;
 }
 
+// Work items of matrix b in phase ph of an update (1-based; np + 1 is the controller), from the state the
+// update started in (flags: 1 active, 2 rise-rule candidates due, 4 result copy due) and the tile counts of
+// its s x s and n x m products.
+__device__ __forceinline__ int phase_items(int flags, int ph, int np, int sq, int out) {
+  if (!(flags & 1)) return 0;
+  if (ph > np) return 1;
+  if (flags & 4) return ph == 1 ? out : 0;
+  if (flags & 2) return ph <= 2 ? out : 0;
+  return ph == np ? out : sq;
+}
+
 // PER_CU: resident workgroups per compute unit the register allocation leaves room for (and the
 // launch uses, at most).
-template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2>
+// FLOW: the dataflow form, for the updates whose first phase has at most FLOW_ITEMS items per workgroup
+// (the last few matrices; with many, the barrier form measured faster).  In such an update the workgroups
+// meet at a grid barrier once (after the controllers) instead of after every phase: they take the phases'
+// items in phase order, each phase
+// from its own counter, and an item of phase ph of matrix b first waits until b's items of the earlier
+// phases of the update are complete (a per-matrix counter of completed items, raised with release
+// semantics after each item and polled, then acquired, before the item).  A workgroup only takes a phase's
+// items once that phase's counter has run out, so every item an item waits for was taken earlier by a
+// resident workgroup that waits only for still earlier items: the waits always end.  Each wait is bounded
+// like the barrier's and raises the same give-up flag.
+constexpr int FLOW_ITEMS = 6;
+template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2, bool FLOW = false>
 __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SParams P) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) float smem[C::SMEM];
@@ -1137,15 +1260,18 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
   __shared__ double sh[16];
   __shared__ int pref[SYNC_MAX + 1];
   __shared__ int s_mn[SYNC_MAX];  // m | n << 16 per matrix
+  __shared__ unsigned char s_fl[SYNC_MAX];  // state of each matrix at the start of the update (phase_items)
   __shared__ int s_total;
   __shared__ int s_item;
+  __shared__ int s_dep;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const unsigned int G = gridDim.x;
   const int np = num_phases(P.method);
   unsigned long long* const trace = (blockIdx.x == 0 && tid == 0) ? P.trace : nullptr;
-  const int trace_cap = P.trace_cap;
+  const int trace_cap = P.trace_cap < kTraceSetup ? P.trace_cap : kTraceSetup;
   int nstamp = 0;
+  unsigned long long busy = 0;  // this workgroup's ticks inside update work items (verbose trace only)
 #define QP_STAMP()                                            \
   do {                                                        \
     if (trace && nstamp < trace_cap) trace[nstamp] = wall_clock64(); \
@@ -1182,7 +1308,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
     Ac.ps = d.psap;
     const bool ok = setup_matrix(P.scaling, P.power_steps, P.seed, P.scaling == 2 ? P.alpha[b] : 0.0, A, Ac, B.xw(0),
                                  P.dwork + d.doff, Dv, sh, smem, C::SMEM, info, normA, alpha);
-    if (P.trace && tid == 0 && kTraceCap / 2 + b < kTraceCap) P.trace[kTraceCap / 2 + b] = wall_clock64() - t_set;
+    if (P.trace && tid == 0 && kTraceSetup + b < kTraceBusy) P.trace[kTraceSetup + b] = wall_clock64() - t_set;
     if (tid == 0) {
       LState S;
       S.active = ok ? 1 : 0;
@@ -1199,6 +1325,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
       S.normA = normA;
       S.sigma1_sq = info.sigma1_sq;
       S.xn_prev = S.xn_a = S.xn_b = 0.0;
+      S.base = 0u;
       S.dx_rel = 0.0;
       S.ctl = StopController(P.stop, P.tol);
       P.st[b] = S;
@@ -1212,6 +1339,15 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
   // ---------------------------------------------------------------- updates
   // max_iter updates, plus one pass for the rise rule's candidate products
   for (int it = 0; it <= P.max_iter + 1; ++it) {
+    // the matrices' states as the update starts (the controllers change them only in its last phase)
+    for (int b = tid; b < P.count; b += nthr) {
+      const LState& Sb = P.st[b];
+      s_fl[b] = (unsigned char)(Sb.active ? 1 | (Sb.pending ? 2 : 0) | (Sb.copy_buf >= 0 ? 4 : 0) : 0);
+    }
+    __syncthreads();
+    int known_b = -1;         // thread 0 (dataflow form): matrix and phase whose earlier items this
+    int known_ph = 0;         // workgroup has already seen complete (and acquired)
+    bool flowu = false;       // this update runs in the dataflow form (the same choice in every workgroup)
     for (int ph = 1; ph <= np + 1; ++ph) {
       // tile counts of this phase over the active matrices (phase np + 1: one item per active matrix)
       const int per = (P.count + nthr - 1) / nthr;
@@ -1219,17 +1355,12 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
       for (int q = 0; q < per; ++q) {
         const int b = tid * per + q;
         int c = 0;
-        if (b < P.count && P.st[b].active) {
+        if (b < P.count) {
           const int mb = s_mn[b] & 0xffff, nb = s_mn[b] >> 16;
           const int sd = mb > nb ? nb : mb;
-          if (P.st[b].copy_buf >= 0)  // the result copy, then the controller
-            c = ph > np ? 1 : ph == 1 ? tiles_of<BM, BN>(nb, mb) : 0;
-          else if (P.st[b].pending)  // the rise rule's two candidate products, then the controller
-            c = ph > np ? 1 : ph <= 2 ? tiles_of<BM, BN>(nb, mb) : 0;
-          else
-            c = ph > np ? 1 : ph == np ? tiles_of<BM, BN>(nb, mb) : tiles_of<BM, BN>(sd, sd);
+          c = phase_items(s_fl[b], ph, np, tiles_of<BM, BN>(sd, sd), tiles_of<BM, BN>(nb, mb));
+          pref[b + 1] = c;
         }
-        if (b < P.count) pref[b + 1] = c;
         loc += c;
       }
       // exclusive scan: per-thread totals through the workgroup, then each thread's run
@@ -1262,6 +1393,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
       __syncthreads();
       const int total = s_total;
       if (ph == 1 && total == 0) return;  // nothing active: every workgroup sees the same states
+      if (ph == 1) flowu = FLOW && total <= FLOW_ITEMS * (int)G;
       // Work items of this phase.  Dynamic: a workgroup takes the next unclaimed item from the phase's
       // counter (asking for the following one as it starts an item, so the atomic's latency hides
       // behind the tile), which balances items of different K; static: items g, g + G, ...  Either way
@@ -1282,7 +1414,13 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
         __syncthreads();
         return s_item;
       };
+      unsigned long long t_item = 0;
       for (int item = first_item(); item < total; item = next_item(item)) {
+        if (P.trace && tid == 0) {
+          const unsigned long long now = wall_clock64();
+          if (t_item) busy += now - t_item;
+          t_item = now;
+        }
         if (dyn && tid == 0) pre = __hip_atomic_fetch_add(&P.qctr[seq], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // matrix of this item: last b with pref[b] <= item
         int lo = 0, hi = P.count;
@@ -1295,6 +1433,42 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
         const BDesc d = P.desc[b];
         const MBufs B = mbufs(P, d);
         LState S = P.st[b];
+        if constexpr (FLOW) {
+          if (flowu && ph >= 2) {
+            // wait for matrix b's items of phases 1 .. ph - 1 of this update
+            if (tid == 0) {
+              int ok = 1;
+              if (known_b != b || known_ph != ph) {
+                const int sd = d.m > d.n ? d.n : d.m;
+                const int sq = tiles_of<BM, BN>(sd, sd), out = tiles_of<BM, BN>(d.n, d.m);
+                unsigned int need = S.base;
+                for (int q = 1; q < ph; ++q) need += (unsigned int)phase_items(s_fl[b], q, np, sq, out);
+                long long spins = 0;
+                while (__hip_atomic_load(&P.done[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                  if (__hip_atomic_load(&P.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                      ++spins > SPIN_MAX) {
+                    __hip_atomic_store(&P.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                  }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                known_b = b;
+                known_ph = ph;
+              }
+              s_dep = ok;
+            }
+            __syncthreads();
+            if (!s_dep) return;
+          }
+        }
+        // matrix b's item is complete: count it (dataflow form)
+        auto item_done = [&]() {
+          if (flowu) {
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(&P.done[b], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        };
         if (ph <= np && S.copy_buf >= 0) {
           // tile t of the chosen iterate to the caller's X
           const DM Xr = B.xw(S.copy_buf);
@@ -1307,6 +1481,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
               for (int p = 0; p < 4; ++p)
                 gstore(d.X, p * d.psx + (int64_t)i * d.ldx + c, gload(Xr.p, p * Xr.ps + (int64_t)i * Xr.ld + c));
           }
+          item_done();
           continue;
         }
         if (ph <= np && S.pending) {
@@ -1324,6 +1499,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
           a0 = wg_sum(a0, sh);
           if (tid == 0) P.partial[d.poff + 2 * ((ph - 1) * tiles_of<BM, BN>(d.n, d.m) + t)] = a0;
           __syncthreads();
+          item_done();
           continue;
         }
         if (ph <= np) {
@@ -1364,11 +1540,17 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
             }
           }
           __syncthreads();
+          item_done();
           continue;
         }
         // ---------------------------------------------------------------- controller of matrix b
         const int nxt = next_buf(S);
         const int ntile = tiles_of<BM, BN>(d.n, d.m);
+        if (flowu) {  // this update's items of matrix b, counted for the next dataflow update's waits
+          const int sd = d.m > d.n ? d.n : d.m;
+          for (int q = 1; q <= np; ++q)
+            S.base += (unsigned int)phase_items(s_fl[b], q, np, tiles_of<BM, BN>(sd, sd), ntile);
+        }
         if (S.copy_buf >= 0) {  // the copy ran in phase 1 of this pass
           S.copy_buf = -1;
           S.active = 0;
@@ -1486,6 +1668,11 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
         if (tid == 0) P.st[b] = S;
         __syncthreads();
       }
+      if (P.trace && tid == 0) {
+        if (t_item) busy += wall_clock64() - t_item;
+        if (kTraceBusy + (int)blockIdx.x < kTraceCap) P.trace[kTraceBusy + blockIdx.x] = busy;
+      }
+      if (flowu && ph <= np) continue;
       if (!grid_sync(P.bar, G)) return;
       QP_STAMP();
     }
@@ -1505,9 +1692,10 @@ static void launch_batched(const BParams& P, int grid, hipStream_t s) {
   QP_HIP(hipGetLastError());
 }
 
-template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2>
+template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2, bool FLOW = false>
 static void launch_sync(const SParams& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((batched_sync_kernel<MM, BM, BN, BK, WM, WN, PER_CU>), dim3(grid), dim3(64 * WM * WN), 0, s, P);
+  hipLaunchKernelGGL((batched_sync_kernel<MM, BM, BN, BK, WM, WN, PER_CU, FLOW>), dim3(grid), dim3(64 * WM * WN), 0, s,
+                     P);
   QP_HIP(hipGetLastError());
 }
 
@@ -1518,10 +1706,10 @@ static int occupancy_of() {
   return std::max(nb, 1);
 }
 
-template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2>
+template <class MM, int BM, int BN, int BK, int WM, int WN, int PER_CU = 2, bool FLOW = false>
 static int occupancy_sync() {
   int nb = 0;
-  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_sync_kernel<MM, BM, BN, BK, WM, WN, PER_CU>,
+  QP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_sync_kernel<MM, BM, BN, BK, WM, WN, PER_CU, FLOW>,
                                                       64 * WM * WN, 0));
   return std::min(std::max(nb, 1), PER_CU);
 }
@@ -1533,6 +1721,7 @@ struct BatchedEntry {
   SyncLaunch sfn;
   int (*occ)();
   int bm, bn;
+  bool flow;  // phase-synchronous kernel in its dataflow form (one grid barrier per update)
 };
 
 static const std::vector<BatchedEntry>& batched_table() {
@@ -1549,6 +1738,10 @@ static const std::vector<BatchedEntry>& batched_table() {
        occupancy_sync<MM32F, 64, 64, 16, 2, 2>, 64, 64},
       {"batched_sync_f32_32x32x32_mfma16", nullptr, launch_sync<MM16F, 32, 32, 32, 2, 2>,
        occupancy_sync<MM16F, 32, 32, 32, 2, 2>, 32, 32},
+      {"batched_flow_f32_32x32x32_mfma16", nullptr, launch_sync<MM16F, 32, 32, 32, 2, 2, 2, true>,
+       occupancy_sync<MM16F, 32, 32, 32, 2, 2, 2, true>, 32, 32, true},
+      {"batched_flow_f32_32x32x16_mfma16", nullptr, launch_sync<MM16F, 32, 32, 16, 2, 2, 2, true>,
+       occupancy_sync<MM16F, 32, 32, 16, 2, 2, 2, true>, 32, 32, true},
   };
   return t;
 }
@@ -1586,11 +1779,13 @@ __global__ void zero_int_kernel(int* p) {
 }
 
 // timeout flag, barrier words and a status sentinel for every matrix (overwritten when it retires)
-__global__ void sync_reset_kernel(unsigned int* bar, BInfo* info, int count, unsigned int* qctr, int qcap) {
+__global__ void sync_reset_kernel(unsigned int* bar, BInfo* info, int count, unsigned int* qctr, int qcap,
+                                  unsigned int* done) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int k = i; k < BAR_WORDS; k += gridDim.x * blockDim.x) bar[k] = 0u;
   for (int k = i; k < qcap; k += gridDim.x * blockDim.x) qctr[k] = 0u;
   for (int b = i; b < count; b += gridDim.x * blockDim.x) {
+    done[b] = 0u;
     info[b].iters = 0;
     info[b].returned = 0;
     info[b].reason = 0;
@@ -1654,6 +1849,7 @@ static void build_sync(BatchedState& st, const BKey& key, int64_t pool_cap, int6
   // one item counter per phase: (max_iter + 2) passes of at most 32 phases
   const int qcap = (key.max_iter + 2) * 32;
   unsigned int* d_qctr = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * (size_t)qcap));
+  unsigned int* d_done = static_cast<unsigned int*>(dev_alloc(st, sizeof(unsigned int) * (size_t)count));
   double* d_alpha = static_cast<double*>(dev_alloc(st, sizeof(double) * count));
   float* pool = static_cast<float*>(dev_alloc(st, sizeof(float) * (size_t)pool_cap));
   double* partial = static_cast<double*>(dev_alloc(st, sizeof(double) * (size_t)part_cap));
@@ -1685,13 +1881,14 @@ static void build_sync(BatchedState& st, const BKey& key, int64_t pool_cap, int6
   P.qctr = d_qctr;
   P.qctr_cap = qcap;
   P.dyn = key.dyn;
+  P.done = d_done;
 
   hipStream_t s = st.stream;
   QP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   QP_HIP(hipMemcpyAsync(d_desc, st.h_desc, sizeof(BDesc) * count, hipMemcpyHostToDevice, s));
   QP_HIP(hipMemcpyAsync(d_alpha, st.h_alpha, sizeof(double) * count, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(sync_reset_kernel, dim3((count + 255) / 256 + 1), dim3(256), 0, s, d_bar, d_info, count, d_qctr,
-                     qcap);
+                     qcap, d_done);
   ent.sfn(P, st.grid, s);
   QP_HIP(hipMemcpyAsync(st.h_info, d_info, sizeof(BInfo) * count, hipMemcpyDeviceToHost, s));
   QP_HIP(hipMemcpyAsync(st.h_order, d_bar, sizeof(unsigned int) * 4, hipMemcpyDeviceToHost, s));
@@ -1789,12 +1986,13 @@ void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& de
     // and the controller phase
     const unsigned long long* t = st.h_trace;
     const int np = key.method == 0 ? 2 : key.method == 2 ? 6 : 7;
+    const bool flow = batched_table().at(key.cfg).flow;  // then the updates' stamp counts differ
     fprintf(stderr, "[qpinv] batched set-up %.1f us\n", (double)(t[1] - t[0]) * 1e-2);
     {  // per-matrix set-up durations (stamped by the workgroup that did it)
       double mx = 0.0, sum = 0.0;
       int arg = 0;
-      for (int b = 0; b < count && kTraceCap / 2 + b < kTraceCap; ++b) {
-        const double v = (double)t[kTraceCap / 2 + b] * 1e-2;
+      for (int b = 0; b < count && kTraceSetup + b < kTraceBusy; ++b) {
+        const double v = (double)t[kTraceSetup + b] * 1e-2;
         sum += v;
         if (v > mx) {
           mx = v;
@@ -1805,13 +2003,30 @@ void run_batched(BatchedState& st, const BKey& key, const std::vector<BDesc>& de
               sum / std::max(count, 1), mx, arg, desc[arg].m, desc[arg].n);
     }
     int k = 2;
-    while (k < kTraceCap && t[k] > t[k - 1] && t[k] - t[k - 1] < 100000000ull) {
-      if ((k - 2) % (np + 1) == 0) fprintf(stderr, "[qpinv] batched update %d:", (k - 2) / (np + 1) + 1);
-      fprintf(stderr, " %.1f", (double)(t[k] - t[k - 1]) * 1e-2);
-      if ((k - 2) % (np + 1) == np) fprintf(stderr, " us\n");
+    while (k < kTraceSetup && t[k] > t[k - 1] && t[k] - t[k - 1] < 100000000ull) {
+      if (flow) {
+        if (k == 2) fprintf(stderr, "[qpinv] batched barrier intervals (us):");
+        fprintf(stderr, " %.1f", (double)(t[k] - t[k - 1]) * 1e-2);
+      } else {
+        if ((k - 2) % (np + 1) == 0) fprintf(stderr, "[qpinv] batched update %d:", (k - 2) / (np + 1) + 1);
+        fprintf(stderr, " %.1f", (double)(t[k] - t[k - 1]) * 1e-2);
+        if ((k - 2) % (np + 1) == np) fprintf(stderr, " us\n");
+      }
       ++k;
     }
     fprintf(stderr, "\n");
+    {  // share of the update time the workgroups spent inside work items
+      const double upd = (double)(t[k - 1] - t[1]) * 1e-2;
+      double sum = 0.0, mx = 0.0;
+      const int G = st.grid;
+      for (int g = 0; g < G && kTraceBusy + g < kTraceCap; ++g) {
+        const double v = (double)t[kTraceBusy + g] * 1e-2;
+        sum += v;
+        mx = std::max(mx, v);
+      }
+      fprintf(stderr, "[qpinv] batched updates %.1f us; workgroups inside items: mean %.1f us (%.1f%%), max %.1f us\n",
+              upd, sum / std::max(G, 1), upd > 0 ? 100.0 * sum / std::max(G, 1) / upd : 0.0, mx);
+    }
   }
   if (sync && reinterpret_cast<const unsigned int*>(st.h_order)[2] != 0u)
     throw Error(-7, "batched solve: a grid barrier wait expired (workgroups not co-resident?)");

@@ -63,7 +63,7 @@ def test_batched_configuration_table_without_gpu():
     names = [q.qpinv_batched_config_name(c) for c in range(n)]
     assert names[5] == "batched_sync_f32_32x32x32_mfma16"
     assert names[2] == "batched_f32_64x64x16_mfma16"
-    assert all(nm.startswith(("batched_f32_", "batched_sync_f32_")) for nm in names)
+    assert all(nm.startswith(("batched_f32_", "batched_sync_f32_", "batched_flow_f32_")) for nm in names)
 
 
 def test_product_configuration_tables_without_gpu():
@@ -133,3 +133,23 @@ def test_controller_agrees_with_oracle_stop_decision():
     used, dec = q.qpinv_controller_replay(q.STOP["guarded"], 1e-14, r.dx, r.xn)
     assert used == r.iters
     assert dec[used - 1] == (2 if r.reason == "rise" else 1)
+
+
+def test_batch_infos_convert_on_read_without_gpu():
+    """BatchInfos: a sequence over the raw per-matrix records, each turned into solve's dict when read."""
+    import paper_2605_01464_amd as q
+
+    raw = (q.Info * 3)()
+    for i in range(3):
+        raw[i].iters = 10 + i
+        raw[i].stop_reason = 0
+        raw[i].reserved = -i
+    infos = q.BatchInfos(raw, 3)
+    assert len(infos) == 3
+    assert infos[1]["iters"] == 11 and infos[1]["status"] == -1 and infos[1]["reason"] == q.REASON[0]
+    assert infos[-1]["iters"] == 12
+    assert [d["iters"] for d in infos] == [10, 11, 12]
+    assert [d["iters"] for d in infos[1:]] == [11, 12]
+    assert infos[0] is infos[0]
+    with pytest.raises(IndexError):
+        infos[3]

@@ -9,9 +9,11 @@ from oracle import methods as M
 
 pytestmark = pytest.mark.gpu
 
-# kernel forms: the queue kernel (one workgroup per matrix) and the phase-synchronous kernel (all
-# workgroups per product), with the same 32 x 32 tile routine
-FORMS = {"queue": 0, "sync": 3, "sync_bk32": 5}
+# kernel forms: the queue kernel (one workgroup per matrix), the phase-synchronous kernel (all
+# workgroups per product, a grid barrier after each) and its dataflow form (per-matrix completion counters,
+# one grid barrier per update), with the same 32 x 32 tile routine
+FORMS = {"queue": 0, "sync": 3, "sync_bk32": 5, "flow": 6, "flow_bk16": 7}
+PREFIX = {"queue": "batched_f32", "sync": "batched_sync", "flow": "batched_flow"}
 
 
 @pytest.fixture(autouse=True, params=sorted(FORMS))
@@ -19,7 +21,7 @@ def batched_form(request, qctx):
     import paper_2605_01464_amd as q
 
     cfg = FORMS[request.param]
-    assert q.qpinv_batched_config_name(cfg).startswith("batched_sync" if request.param.startswith("sync") else "batched_f32")
+    assert q.qpinv_batched_config_name(cfg).startswith(PREFIX[request.param.split("_")[0]])
     qctx.set("batched_cfg", cfg)
     yield request.param
     qctx.set("batched_cfg", -1)
@@ -171,3 +173,23 @@ def test_sync_item_dealing_does_not_change_results(qctx, small_batch, batched_fo
     assert out[0][1] == out[1][1]
     for a, b in zip(out[0][0], out[1][0]):
         assert torch.equal(a, b)
+
+
+def test_batch_args_equal_list_arguments(qctx, small_batch, batched_form):
+    """Descriptors marshalled once (BatchArgs) and reused: the same solve as the per-call tensor lists, bit for
+    bit, on repeated calls; the outputs are the BatchArgs' own tensors."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    As = [to_dev(A, "f32") for A in small_batch]
+    Xs_list, inf_list = q.solve_batched(qctx, As, "qhpi19", tol=1e-6, stop="guarded")
+    args = q.BatchArgs(As)
+    for _ in range(2):
+        Xs_args, inf_args = q.solve_batched(qctx, args, "qhpi19", tol=1e-6, stop="guarded")
+        assert all(x is y for x, y in zip(Xs_args, args.Xs))
+        assert [(i["iters"], i["status"]) for i in inf_args] == [(i["iters"], i["status"]) for i in inf_list]
+        for a, b in zip(Xs_args, Xs_list):
+            assert torch.equal(a, b)
+    with pytest.raises(ValueError):
+        q.solve_batched(qctx, args, "qhpi19", Xs=Xs_list)
