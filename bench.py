@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}  # TFLOP/s, dense MFMA, MI355X datasheet
+PEAK["bf16x3"] = PEAK["bf16"] / 3  # three BF16 products per product: the BF16 peak in product flops
 METRIC = "pinv solves/s + quaternion GEMM TFLOP/s at rel-err<=1e-6; mixed/learned vs plain"
 
 
@@ -116,7 +117,7 @@ def ladder_breakdown(q, ctx, torch, A, kw):
     t_one = time.perf_counter() - t
     _, rows = q.qpinv_gemm_stats(ctx.handle)
     ctx.set("gemm_timing", 0)
-    names = {q.GEMM_PREC[k]: k for k in ("f64", "f32", "bf16")}
+    names = {v: k for k, v in q.GEMM_PREC.items()}
     byp = {}
     for r in rows:
         e = byp.setdefault(names[r["prec"]], {"launches": 0, "ms": 0.0, "flops": 0.0})
@@ -465,7 +466,7 @@ def main() -> int:
     value = args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
     dom = max(rows, key=lambda r: r["ms"])
-    prec_name = {0: "f64", 1: "f32", 2: "bf16"}[dom["prec"]]
+    prec_name = {0: "f64", 1: "f32", 2: "bf16", 3: "bf16x3"}[dom["prec"]]
     dom_name = q.qpinv_tile_config_name(dom["prec"], dom["cfg"])
     launches = max(dom["launches"], 1)
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
@@ -502,7 +503,7 @@ def main() -> int:
         for nn in (2048, 4096):
             r = qgemm_rate(q, ctx, nn, nn, nn, reps=10)
             gemm[f"f32_n{nn}"] = {"tflops": r["tflops"], "frac": r["frac_peak"], "rel_err": r["rel_err_sampled_rows"]}
-        for prec in ("f64", "bf16"):
+        for prec in ("f64", "bf16", "bf16x3"):
             r = qgemm_rate(q, ctx, 4096, 4096, 4096, prec=prec, reps=10)
             gemm[f"{prec}_n4096"] = {"tflops": r["tflops"], "frac": r["frac_peak"],
                                      "rel_err": r["rel_err_sampled_rows"]}

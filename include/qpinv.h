@@ -102,10 +102,12 @@ typedef enum {
                                   (power estimate, option mixed_rnorm_steps) or ||R||_2^p drops below
                                   option mixed_switch (1e-2), or ||R||_2 < 0.9 fails to halve in one
                                   update, or stops falling, or after max_bf16_iters (8) updates; then
-                                  as F32_F64FINISH */
+                                  as F32_F64FINISH, with every product of FP32 storage (the FP32 phase,
+                                  the finish's corrections) as GEMM_BF16X3 (option mixed_split = 1, the
+                                  default; 0: native FP32 products) */
 } qpinv_precision;
 
-typedef enum { QPINV_GEMM_F64 = 0, QPINV_GEMM_F32 = 1, QPINV_GEMM_BF16 = 2 } qpinv_gemm_prec;
+typedef enum { QPINV_GEMM_F64 = 0, QPINV_GEMM_F32 = 1, QPINV_GEMM_BF16 = 2, QPINV_GEMM_BF16X3 = 3 } qpinv_gemm_prec;
 
 typedef enum { QPINV_SIDE_AUTO = 0, QPINV_SIDE_LEFT = 1, QPINV_SIDE_RIGHT = 2 } qpinv_side;
 
@@ -147,7 +149,8 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
  * rounding relative to |(T - I) X| -- for the default Newton-Schulz finish T - I = R, and the second
  * update's correction is already at the FP64 level; 0: every finish product in FP64), mixed_switch (||R||_2
  * threshold, default 1e-2), mixed_rnorm_steps,
- * max_bf16_iters, gemm_timing (0/1), gemm_cfg_f64 / gemm_cfg_f32 / gemm_cfg_bf16 (tile configuration
+ * max_bf16_iters, mixed_split (0/1, default 1: the MIXED ladder's FP32-storage products as GEMM_BF16X3),
+ * gemm_timing (0/1), gemm_cfg_f64 / gemm_cfg_f32 / gemm_cfg_bf16 / gemm_cfg_bf16x3 (tile configuration
  * index used for every product of that precision, -1 = tuned or heuristic choice), batched_cfg
  * (configuration of qpinv_solve_batched, -1 = tuned or default), batched_dynamic (phase-synchronous
  * batched form: 1 (default) workgroups claim work items from a counter, 0 workgroup g takes items
@@ -260,6 +263,12 @@ int qpinv_residuals(qpinv_ctx* ctx, const qpinv_qmat* A, const qpinv_qmat* X, do
  * operand would reach 2^31 bytes takes the direct form instead, with no copies).  The buffer grows on
  * demand (the stream is synchronised first) and is freed by qpinv_finalize; products on one context
  * share it, so they must not run concurrently on different streams.
+ * GEMM_BF16X3 (FP32 storage) splits every FP32 operand element x into hi = bf16(x) and lo = bf16(x - hi)
+ * (|x - hi - lo| <= 2^-16 |x|) and sums the three BF16 products hi.hi + hi.lo + lo.hi in one FP32-accumulated
+ * product over 3 Kp, from split copies in the same stage buffer (three times the bytes above): every term of
+ * the Hamilton product carries an error of at most about 3 2^-16 |a| |b| besides the FP32 accumulation, in
+ * 0.39 of an FP32 product's time at 4096^3.  Products whose split copies would reach 2^31 bytes are refused
+ * (EINVAL); the solver then keeps native FP32 products.
  * Errors: EINVAL, EHIP, ENOMEM (stage buffer). */
 int qpinv_qgemm(qpinv_ctx* ctx, int gemm_prec, const qpinv_qmat* A, const qpinv_qmat* B, qpinv_qmat* C,
                 double alpha, double beta, double gamma, void* hip_stream);

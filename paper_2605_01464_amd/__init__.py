@@ -26,7 +26,7 @@ METHOD = {"ns": 0, "hpi": 1, "qsai": 2, "qhpi19": 3, "qrapid": 4}
 SCALING = {"power": 0, "frob": 1, "given": 2, "learned": 3, "x0": 4}
 STOP = {"dx_abs": 0, "dx_rel": 1, "e1_rel": 2, "guarded": 3}
 PRECISION = {"f64": 0, "f32": 1, "f32_f64finish": 2, "mixed": 3}
-GEMM_PREC = {"f64": 0, "f32": 1, "bf16": 2}
+GEMM_PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 SIDE = {"auto": 0, "left": 1, "right": 2}
 REASON = {0: "tol", 1: "rise", 2: "max_iter", 3: "diverged"}
 DEFAULT_ORDER = {"ns": 2, "hpi": None, "qsai": 10, "qhpi19": 19, "qrapid": 5}

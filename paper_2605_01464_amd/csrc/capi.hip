@@ -46,7 +46,7 @@ qp::Ctx& ctx_of(qpinv_ctx* c) {
 hipStream_t stream_of(void* s) { return static_cast<hipStream_t>(s); }
 
 int prec_check(int gemm_prec) {
-  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16) throw qp::Error(QPINV_EINVAL, "bad product precision");
+  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16X3) throw qp::Error(QPINV_EINVAL, "bad product precision");
   return gemm_prec;
 }
 
@@ -92,11 +92,17 @@ void set_option(qp::Ctx& c, const std::string& key, double v) {
   } else if (key == "max_bf16_iters") {
     need(v >= 0 && v <= 100);
     c.opt.max_bf16_iters = (int)v;
+  } else if (key == "mixed_split") {
+    need(v == 0 || v == 1);
+    c.opt.mixed_split = (int)v;
   } else if (key == "gemm_timing") {
     need(v == 0 || v == 1);
     c.opt.gemm_timing = (int)v;
-  } else if (key == "gemm_cfg_f64" || key == "gemm_cfg_f32" || key == "gemm_cfg_bf16") {
-    const qp::Prec p = key == "gemm_cfg_f64" ? qp::P_F64 : key == "gemm_cfg_f32" ? qp::P_F32 : qp::P_BF16;
+  } else if (key == "gemm_cfg_f64" || key == "gemm_cfg_f32" || key == "gemm_cfg_bf16" || key == "gemm_cfg_bf16x3") {
+    const qp::Prec p = key == "gemm_cfg_f64"    ? qp::P_F64
+                       : key == "gemm_cfg_f32"  ? qp::P_F32
+                       : key == "gemm_cfg_bf16" ? qp::P_BF16
+                                                : qp::P_BF16X3;
     need(v == -1 || (v >= 0 && v < (double)qp::tile_configs(p).size() && v == (int)v));
     c.opt.force_cfg[(int)p] = (int)v;
   } else if (key == "batched_cfg") {
@@ -504,12 +510,12 @@ int qpinv_autotune(qpinv_ctx* c, int gemm_prec, int64_t M, int64_t N, int64_t K,
 }
 
 int qpinv_num_tile_configs(int gemm_prec) {
-  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16) return QPINV_EINVAL;
+  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16X3) return QPINV_EINVAL;
   return (int)qp::tile_configs((qp::Prec)gemm_prec).size();
 }
 
 const char* qpinv_tile_config_name(int gemm_prec, int cfg) {
-  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16) return "";
+  if (gemm_prec < QPINV_GEMM_F64 || gemm_prec > QPINV_GEMM_BF16X3) return "";
   const auto& t = qp::tile_configs((qp::Prec)gemm_prec);
   if (cfg < 0 || cfg >= (int)t.size()) return "";
   return t[cfg].name;

@@ -223,7 +223,8 @@ static const std::vector<F64Entry>& f64_table() {
   return t;
 }
 
-const std::vector<TileConfig>& bf16_configs();  // qgemm_bf16.hip
+const std::vector<TileConfig>& bf16_configs();    // qgemm_bf16.hip
+const std::vector<TileConfig>& bf16x3_configs();  // qgemm_bf16.hip
 
 const std::vector<TileConfig>& tile_configs(Prec p) {
   static std::vector<TileConfig> f32, f64;
@@ -232,6 +233,7 @@ const std::vector<TileConfig>& tile_configs(Prec p) {
     for (auto& e : f64_table()) f64.push_back(e.cfg);
   }
   if (p == P_BF16) return bf16_configs();
+  if (p == P_BF16X3) return bf16x3_configs();
   return p == P_F64 ? f64 : f32;
 }
 
@@ -251,6 +253,7 @@ int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
   const int64_t b64 = ((M + 63) / 64) * ((N + 63) / 64);
   if (p == P_F64) return b64 >= 1024 ? 4 : 1;
   if (p == P_BF16) return b64 >= 1024 ? 8 : b64 >= 256 ? 0 : 1;
+  if (p == P_BF16X3) return 0;
   return b64 >= 1024 ? 5 : 6;
 }
 
@@ -291,6 +294,8 @@ static GemmParams<T> make_params(const QView& A, const QView& B, int64_t M, int6
 
 int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s, GemmScratch& scratch);  // qgemm_bf16.hip
 int64_t bf16_blocks(int cfg, int64_t M, int64_t N);
+int64_t bf16x3_launch(const GemmParams<float>& P, int cfg, hipStream_t s, GemmScratch& scratch);
+int64_t bf16x3_blocks(int cfg, int64_t M, int64_t N);
 
 void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t K, const Epilogue& epi,
            double* red, GemmScratch& scratch, hipStream_t stream, int cfg) {
@@ -301,7 +306,9 @@ void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t
   const auto& cfgs = tile_configs(p);
   if (cfg >= (int)cfgs.size()) throw Error(-1, "qgemm: bad tile config");
   // an upper bound of the workgroups launched (a per-CU configuration launches at most this many)
-  const int64_t nb = p == P_BF16 ? bf16_blocks(cfg, M, N) : blocks_for(cfgs[cfg], M, N);
+  const int64_t nb = p == P_BF16     ? bf16_blocks(cfg, M, N)
+                     : p == P_BF16X3 ? bf16x3_blocks(cfg, M, N)
+                                     : blocks_for(cfgs[cfg], M, N);
   if (epi.reduce && nb > scratch.capacity / 2) throw Error(-1, "qgemm: reduction scratch too small");
   double* partial = epi.reduce ? scratch.partial : nullptr;
   int64_t launched = 0;
@@ -309,8 +316,10 @@ void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t
     launched = f64_table()[cfg].fn(make_params<double>(A, B, M, N, K, epi, partial), stream);
   } else if (p == P_F32) {
     launched = f32_table()[cfg].fn(make_params<float>(A, B, M, N, K, epi, partial), stream);
-  } else {
+  } else if (p == P_BF16) {
     launched = bf16_launch(make_params<float>(A, B, M, N, K, epi, partial), cfg, stream, scratch);
+  } else {
+    launched = bf16x3_launch(make_params<float>(A, B, M, N, K, epi, partial), cfg, stream, scratch);
   }
   if (epi.reduce) reduce_pairs(partial, launched, red, stream);
 }

@@ -18,7 +18,8 @@
 
 namespace qp {
 
-enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+// P_BF16X3: FP32 storage, each product as three BF16 products of split operands (hi.hi + hi.lo + lo.hi)
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
 struct Epilogue {
   int nout = 1;
@@ -76,6 +77,8 @@ void qgemm(Prec p, const QView& A, const QView& B, int64_t M, int64_t N, int64_t
 
 // Number of workgroups a configuration launches for an M x N output (sizes scratch).
 int64_t qgemm_blocks(Prec p, int cfg, int64_t M, int64_t N);
+// whether a P_BF16X3 product of this shape fits the split copies' 32-bit buffer offsets
+bool bf16x3_fits(int64_t M, int64_t N, int64_t K);
 
 // Sum `count` pairs of partial sums at `partial` into red[0..1] (fixed order, deterministic).
 void reduce_pairs(const double* partial, int64_t count, double* red, hipStream_t stream);

@@ -779,10 +779,45 @@ __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16s_kernel(GemmPar
   store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
 }
 
-// out[q][r][8c .. 8c+7] = bf16(A[q][r][8c ..]) inside the matrix, 0 in the padding (r < mp, 8c < kp).
-// vec: 16-byte aligned base, lda and psa.
+// Split operands (three-product form): x = hi + lo + d with hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in
+// FP32) and |d| <= 2^-16 |x|.  Rows of the split copies hold 3 kp elements, three segments of kp along k:
+// A as [hi | hi | lo] and B (transposed) as [hi | lo | hi], so that one product over 3 kp sums
+// hi.hi + hi.lo + lo.hi; the dropped lo.lo term and d bound the error by about 3 2^-16 |a||b| per term.
+enum : int { kSplitNone = 0, kSplitA = 1, kSplitB = 2 };
+
+// Eight consecutive k of one row (x0: the first four, x1: the next four) to the copy at column k of `row`.
+__device__ __forceinline__ void split_store(__bf16* __restrict__ row, int kp, int k, const floatx4& x0,
+                                            const floatx4& x1, int split) {
+  bf16x8 h, l;
+  const bf16x4 h0 = __builtin_convertvector(x0, bf16x4), h1 = __builtin_convertvector(x1, bf16x4);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = h0[e];
+    h[e + 4] = h1[e];
+  }
+  *reinterpret_cast<bf16x8*>(row + k) = h;
+  if (split == kSplitNone) return;
+  floatx4 r0, r1;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    r0[e] = x0[e] - (float)h0[e];
+    r1[e] = x1[e] - (float)h1[e];
+  }
+  const bf16x4 l0 = __builtin_convertvector(r0, bf16x4), l1 = __builtin_convertvector(r1, bf16x4);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    l[e] = l0[e];
+    l[e + 4] = l1[e];
+  }
+  *reinterpret_cast<bf16x8*>(row + kp + k) = split == kSplitA ? h : l;
+  *reinterpret_cast<bf16x8*>(row + 2 * kp + k) = split == kSplitA ? l : h;
+}
+
+// out[q][r][8c .. 8c+7] = bf16(A[q][r][8c ..]) inside the matrix, 0 in the padding (r < mp, 8c < kp); rows
+// of kp elements, or of 3 kp for split copies.  vec: 16-byte aligned base, lda and psa.
 __global__ void __launch_bounds__(256) bf16_rows_kernel(const float* __restrict__ A, int64_t lda, int64_t psa, int M,
-                                                        int K, __bf16* __restrict__ out, int mp, int kp, int vec) {
+                                                        int K, __bf16* __restrict__ out, int mp, int kp, int vec,
+                                                        int split) {
   const int64_t chunks = (int64_t)4 * mp * (kp / 8);
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * blockDim.x) {
     const int kc = (int)(c % (kp / 8));
@@ -803,23 +838,17 @@ __global__ void __launch_bounds__(256) bf16_rows_kernel(const float* __restrict_
         }
       }
     }
-    bf16x8 o;
-    const bf16x4 l = __builtin_convertvector(lo, bf16x4), h = __builtin_convertvector(hi, bf16x4);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      o[e] = l[e];
-      o[e + 4] = h[e];
-    }
-    *reinterpret_cast<bf16x8*>(out + 8 * c) = o;
+    const int64_t rl = split == kSplitNone ? kp : 3 * (int64_t)kp;
+    split_store(out + qr * rl, kp, 8 * kc, lo, hi, split);
   }
 }
 
 // out[q][n][k] = bf16(B[q][k][n]) inside the matrix, 0 in the padding (n < np, k < kp): one 32 (k) x 64 (n)
 // tile per workgroup through LDS, reads along n (16 bytes a lane when vec: 16-byte aligned base, ldb and
-// psb), writes 16 bytes (8 k) per lane.
+// psb), writes 16 bytes (8 k) per lane; rows of kp elements, or of 3 kp for split copies.
 __global__ void __launch_bounds__(256) bf16_transpose_kernel(const float* __restrict__ B, int64_t ldb, int64_t psb,
                                                              int K, int N, __bf16* __restrict__ out, int np, int kp,
-                                                             int vec) {
+                                                             int vec, int split) {
   __shared__ float tile[32][65];
   const int tk = kp / 32, tn = np / 64;
   const int64_t t = blockIdx.x;
@@ -855,24 +884,26 @@ __global__ void __launch_bounds__(256) bf16_transpose_kernel(const float* __rest
     lo[e] = tile[kc + e][nl];
     hi[e] = tile[kc + 4 + e][nl];
   }
-  bf16x8 o;
-  const bf16x4 l = __builtin_convertvector(lo, bf16x4), h = __builtin_convertvector(hi, bf16x4);
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    o[e] = l[e];
-    o[e + 4] = h[e];
-  }
-  *reinterpret_cast<bf16x8*>(out + ((int64_t)q * np + n0 + nl) * kp + k0 + kc) = o;
+  const int64_t rl = split == kSplitNone ? kp : 3 * (int64_t)kp;
+  split_store(out + ((int64_t)q * np + n0 + nl) * rl, kp, k0 + kc, lo, hi, split);
 }
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Stage bytes of a staged product (rows padded to 128 cover every staged tile shape).
-static int64_t stage_bytes(int64_t M, int64_t N, int64_t K) {
-  return 2 * 4 * (round_up(M, 128) + round_up(N, 128)) * round_up(std::max<int64_t>(K, 1), 32);
+// Stage bytes of a staged product (rows padded to 128 cover every staged tile shape; split copies hold
+// three segments per row).
+static int64_t stage_bytes(int64_t M, int64_t N, int64_t K, bool split = false) {
+  return (split ? 3 : 1) * 2 * 4 * (round_up(M, 128) + round_up(N, 128)) * round_up(std::max<int64_t>(K, 1), 32);
 }
 
-template <int BM, int BN, int WM, int WN, int MINW, class MB = BfM16, bool PRIO = false>
+// The split copies' buffer loads take byte offsets below 2^31 over the four planes.
+bool bf16x3_fits(int64_t M, int64_t N, int64_t K) {
+  return 4 * std::max(round_up(M, 128), round_up(N, 128)) * 3 * std::max<int64_t>(round_up(K, 32), 32) * 2 <
+         (int64_t(1) << 31);
+}
+
+// SPLIT: the three-product form (operands split into BF16 hi and lo, products summed over 3 kp).
+template <int BM, int BN, int WM, int WN, int MINW, class MB = BfM16, bool PRIO = false, bool SPLIT = false>
 static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipStream_t s, GemmScratch& sc) {
   using C = Bf16SCfg<BM, BN, WM, WN, MB>;
   GemmParams<float> P = P0;
@@ -882,10 +913,13 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
   if (nt == 0) return 0;
   const int64_t mp = round_up(P.M, 128), np = round_up(P.N, 128), kp = round_up(P.K, 32);
   // copies beyond the 32-bit offsets of the buffer loads (about 16k x 16k): the direct form, which rounds
-  // while staging and takes any size, computes the same products
-  if (4 * std::max(mp, np) * std::max<int64_t>(kp, 32) * 2 >= (int64_t(1) << 31))
+  // while staging and takes any size, computes the same products (the split form has no direct form)
+  if (SPLIT && !bf16x3_fits(P.M, P.N, P.K))
+    throw Error(-1, "qgemm: the split BF16 product's copies exceed 2^31 bytes");
+  if (!SPLIT && 4 * std::max(mp, np) * std::max<int64_t>(kp, 32) * 2 >= (int64_t(1) << 31))
     return launch_bf16_db<64, 64, 2, 2, 2>(P0, 0, s);
-  const size_t need = (size_t)stage_bytes(P.M, P.N, P.K);
+  const int64_t kps = SPLIT ? 3 * kp : kp;  // staged row length
+  const size_t need = (size_t)stage_bytes(P.M, P.N, P.K, SPLIT);
   if (sc.stage_bytes < need) {
     if (sc.no_grow)
       throw Error(-1, "qgemm: the staged BF16 product needs a " + std::to_string(need) +
@@ -903,21 +937,21 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
     sc.stage_bytes = need;
   }
   __bf16* const a16 = static_cast<__bf16*>(sc.stage);
-  __bf16* const b16 = a16 + 4 * mp * kp;
+  __bf16* const b16 = a16 + 4 * mp * kps;
   if (kp > 0) {
     const int64_t chunks = 4 * mp * (kp / 8);
     const int64_t grid_r = std::min<int64_t>((chunks + 255) / 256, 65536);
     const int vec_a = (reinterpret_cast<uintptr_t>(P.A) & 15) == 0 && P.lda % 4 == 0 && P.psa % 4 == 0;
     hipLaunchKernelGGL(bf16_rows_kernel, dim3((unsigned)grid_r), dim3(256), 0, s, P.A, P.lda, P.psa, P.M, P.K, a16,
-                       (int)mp, (int)kp, vec_a);
+                       (int)mp, (int)kp, vec_a, SPLIT ? (int)kSplitA : (int)kSplitNone);
     QP_HIP(hipGetLastError());
     const int64_t grid_t = 4 * (kp / 32) * (np / 64);
     const int vec_b = (reinterpret_cast<uintptr_t>(P.B) & 15) == 0 && P.ldb % 4 == 0 && P.psb % 4 == 0;
     hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)grid_t), dim3(256), 0, s, P.B, P.ldb, P.psb, P.K, P.N, b16,
-                       (int)np, (int)kp, vec_b);
+                       (int)np, (int)kp, vec_b, SPLIT ? (int)kSplitB : (int)kSplitNone);
     QP_HIP(hipGetLastError());
   }
-  const Bf16Stage S{a16, b16, (int)mp, (int)np, (int)kp};
+  const Bf16Stage S{a16, b16, (int)mp, (int)np, (int)kps};
   auto kern = qgemm_bf16s_kernel<BM, BN, WM, WN, MINW, MB, PRIO>;
   LaunchShape ls;
   ls.grid = nt;
@@ -985,6 +1019,36 @@ int64_t bf16_launch(const GemmParams<float>& P, int cfg, hipStream_t s, GemmScra
 
 int64_t bf16_blocks(int cfg, int64_t M, int64_t N) {
   const auto& c = bf16_table().at(cfg).cfg;
+  return ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
+}
+
+// The three-product form: the staged kernels over the split copies.
+static const std::vector<Bf16Entry>& bf16x3_table() {
+  static const std::vector<Bf16Entry> t = {
+      {{0, 64, 64, 32, 512, "bf16x3_64x64x32_w2x4_mfma16x16x32_staged"},
+       launch_bf16_staged<64, 64, 2, 4, 4, BfM16, true, true>},
+      {{1, 64, 64, 32, 256, "bf16x3_64x64x32_w2x2_mfma16x16x32_staged"},
+       launch_bf16_staged<64, 64, 2, 2, 2, BfM16, false, true>},
+      {{2, 128, 64, 32, 512, "bf16x3_128x64x32_w4x2_mfma32x32x16_staged"},
+       launch_bf16_staged<128, 64, 4, 2, 2, BfM32, false, true>},
+  };
+  return t;
+}
+
+const std::vector<TileConfig>& bf16x3_configs() {
+  static std::vector<TileConfig> v;
+  if (v.empty())
+    for (auto& e : bf16x3_table()) v.push_back(e.cfg);
+  return v;
+}
+
+int64_t bf16x3_launch(const GemmParams<float>& P, int cfg, hipStream_t s, GemmScratch& scratch) {
+  const auto& e = bf16x3_table().at(cfg);
+  return e.fn(P, e.cfg.per_cu, s, scratch);
+}
+
+int64_t bf16x3_blocks(int cfg, int64_t M, int64_t N) {
+  const auto& c = bf16x3_table().at(cfg).cfg;
   return ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
 }
 

@@ -182,6 +182,7 @@ Mat ws_mat(Ctx& c, const std::string& key, int64_t rows, int64_t cols, int dtype
 void gemm(Ctx& c, Prec p, const Mat& A, const Mat& B, const Epilogue& e, hipStream_t s, double* red) {
   if (A.cols != B.rows) throw Error(QPINV_EINVAL, "gemm: inner dimensions differ");
   const int64_t M = A.rows, N = B.cols, K = A.cols;
+  if (p == P_F32 && c.split_f32 && bf16x3_fits(M, N, K)) p = P_BF16X3;
   const int cfg = c.config_for(p, M, N, K, s);
   const double f = 32.0 * (double)M * (double)N * (double)K;
   c.flops += f;
@@ -886,6 +887,12 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
   if (m == 0 || n == 0) return finish(QPINV_OK);
   if (small_eligible(c, method, scaling, stop, precision, m, n))
     return finish(small_solve(c, method, A0, scaling, am, tol, max_iter, stop, precision, Xout, inf, s));
+  // the ladder's FP32-storage products (its FP32 phase and the finish's corrections) as three BF16 products
+  struct SplitScope {
+    Ctx& c;
+    SplitScope(Ctx& cx, bool on) : c(cx) { c.split_f32 = on; }
+    ~SplitScope() { c.split_f32 = false; }
+  } split_scope(c, precision == QPINV_PREC_MIXED && c.opt.mixed_split != 0);
 
   // A in each storage type on demand
   Mat Acache[2];

@@ -44,9 +44,10 @@ struct Options {
   double mixed_switch = 1e-2;
   int mixed_rnorm_steps = 6;
   int max_bf16_iters = 8;
+  int mixed_split = 1;  // ladder: products of its FP32 phase and finish as three BF16 products (P_BF16X3)
   int verbose = 0;
   int gemm_timing = 0;
-  int force_cfg[3] = {-1, -1, -1};  // per product precision: tile configuration for every product, -1 = choose
+  int force_cfg[4] = {-1, -1, -1, -1};  // per product precision: tile configuration for every product, -1 = choose
   int batched_cfg = -1;             // batched kernel configuration, -1 = tuned or default
   int batched_dynamic = 1;          // phase-synchronous batched form: dynamic (1) or static (0) item dealing
 };
@@ -68,6 +69,7 @@ struct Ctx {
   BatchedState* batched = nullptr;
   std::map<std::vector<int64_t>, int> batched_tuned;  // batch signature -> tile configuration
   bool no_alloc = false;  // allocation-free call in progress: no autotuning, no product timing, no growth
+  bool split_f32 = false;  // a ladder solve in progress computes its FP32-storage products as P_BF16X3
   void* small_state = nullptr;  // the small solve's record whose barrier words are known to be clear
   double flops = 0.0;  // running count of algorithmic product flops
   // event pairs around product launches (option gemm_timing)

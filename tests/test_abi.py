@@ -153,3 +153,14 @@ def test_batch_infos_convert_on_read_without_gpu():
     assert infos[0] is infos[0]
     with pytest.raises(IndexError):
         infos[3]
+
+
+def test_split_product_configuration_table_without_gpu():
+    """The three-product (split BF16) precision has its own staged configurations, default first."""
+    import paper_2605_01464_amd as q
+
+    gp = q.GEMM_PREC["bf16x3"]
+    n = q.qpinv_num_tile_configs(gp)
+    names = [q.qpinv_tile_config_name(gp, c) for c in range(n)]
+    assert n >= 1 and all(nm.startswith("bf16x3_") and nm.endswith("_staged") for nm in names), names
+    assert q.qpinv_num_tile_configs(4) == q.EINVAL

@@ -263,3 +263,57 @@ def test_qgemm_bf16_every_config(qctx, shape):
         err = np.abs(to_np(Cd) - ref)
         name = q.qpinv_tile_config_name(q.GEMM_PREC["bf16"], cfg)
         assert np.all(err <= bound), (name, float(err.max()), float((err / bound).max()))
+
+
+def split_bf16(x):
+    """x = hi + lo + d with hi = bf16(x), lo = bf16(x - hi) (x - hi is exact in FP32), as float64."""
+    hi = round_bf16(x)
+    return hi, round_bf16((np.asarray(x, dtype=np.float64) - hi).astype(np.float32))
+
+
+def test_split_bf16_helper():
+    # BF16 keeps 8 significant bits: spacing 2^-7 above 1, 2^-16 at 2^-9
+    x = np.array([1.0 + 2 ** -9 + 2 ** -20, -3.0, 1e-30, 1.0 + 2 ** -8 + 2 ** -20], dtype=np.float32).astype(np.float64)
+    hi, lo = split_bf16(x)
+    assert hi[0] == 1.0 and lo[0] == 2 ** -9 and hi[1] == -3.0 and lo[1] == 0.0
+    assert hi[3] == 1.0 + 2 ** -7 and lo[3] == -(2 ** -8)  # x - hi = -2^-8 + 2^-20 keeps 8 bits of it
+    assert np.all(np.abs(x - hi - lo) <= 2.0 ** -16 * np.abs(x))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_qgemm_bf16x3_every_config(qctx, shape):
+    """Three-product form: equal, up to FP32 accumulation over its 3 x 4K terms, to hi.hi + hi.lo + lo.hi of
+    the split FP32 inputs, and within that plus 3 2^-16 S (the dropped lo.lo term and the split remainders)
+    of the exact product; at least 30x closer to it than the one-product BF16 form on the larger shapes."""
+    import paper_2605_01464_amd as q
+
+    M_, N_, K_ = shape
+    A = rng_planes(31, M_, K_, "f32")
+    B = rng_planes(32, K_, N_, "f32")
+    C0 = rng_planes(33, M_, N_, "f32")
+    alpha, beta, gamma = 0.75, -0.5, 2.0
+    (Ah, Al), (Bh, Bl) = split_bf16(A), split_bf16(B)
+    A3, B3 = np.concatenate([Ah, Ah, Al], axis=2), np.concatenate([Bh, Bl, Bh], axis=1)
+    ref3 = alpha * Q.qmul(A3, B3) + beta * C0
+    ref3[0] += gamma * np.eye(M_, N_)
+    bound3 = gemm_bound(A3, B3, C0, alpha, beta, gamma, U32)
+    ref = alpha * Q.qmul(A, B) + beta * C0
+    ref[0] += gamma * np.eye(M_, N_)
+    S = np.abs(A).sum(axis=0) @ np.abs(B).sum(axis=0)
+    bound = bound3 + 3.0 * 2.0 ** -16 * abs(alpha) * S[None]
+    gp = q.GEMM_PREC["bf16x3"]
+    assert q.qpinv_num_tile_configs(gp) >= 1
+    Cb = to_dev(C0, "f32")
+    q.qgemm(qctx, to_dev(A, "f32"), to_dev(B, "f32"), Cb, alpha, beta, gamma, gemm_prec="bf16")
+    err_bf16 = np.abs(to_np(Cb) - ref).max()
+    for cfg in range(q.qpinv_num_tile_configs(gp)):
+        Cd = to_dev(C0, "f32")
+        q.qgemm(qctx, to_dev(A, "f32"), to_dev(B, "f32"), Cd, alpha, beta, gamma, gemm_prec="bf16x3", cfg=cfg)
+        out = to_np(Cd)
+        name = q.qpinv_tile_config_name(gp, cfg)
+        e3 = np.abs(out - ref3)
+        assert np.all(e3 <= bound3), (name, float(e3.max()), float((e3 / bound3).max()))
+        e = np.abs(out - ref)
+        assert np.all(e <= bound), (name, float(e.max()), float((e / bound).max()))
+        if K_ >= 64:
+            assert e.max() * 30 <= err_bf16, (name, float(e.max()), float(err_bf16))

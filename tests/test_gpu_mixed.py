@@ -176,3 +176,36 @@ def test_newton_schulz_finish_vs_same_method(qctx, sq512, precision):
     assert e_ns <= 1e-6 and e_same <= 1e-6, (e_ns, e_same)
     assert 1 <= i_ns["iters_f64"] <= 2
     assert i_ns["gemm_flops"] < i_same["gemm_flops"], (i_ns["gemm_flops"], i_same["gemm_flops"])
+
+
+@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("qrapid", 5)])
+def test_ladder_split_products_vs_native_fp32(qctx, sq512, method, order):
+    """The ladder with its FP32-storage products as three BF16 products (option mixed_split = 1, default) and
+    with native FP32 products: both past the 1e-6 target against the oracle, the same phase lengths, and the
+    split form's FP32-phase and finish products all of the three-product kind."""
+    import torch
+
+    import paper_2605_01464_amd as q
+
+    A = sq512["A"]
+    ref = Q.pinv_svd(A)
+    out = {}
+    try:
+        qctx.set("gemm_timing", 1)
+        for split in (0, 1):
+            qctx.set("mixed_split", split)
+            q.qpinv_gemm_stats(qctx.handle)  # reset
+            X, info = q.solve(qctx, to_dev(A, "f32"), method, order, scaling="power", tol=1e-6, stop="guarded",
+                              precision="mixed", out_dtype=torch.float64)
+            _, rows = q.qpinv_gemm_stats(qctx.handle)
+            out[split] = (rel_fro(to_np(X), ref), info, {r["prec"] for r in rows})
+    finally:
+        qctx.set("gemm_timing", 0)
+        qctx.set("mixed_split", 1)
+    (e0, i0, p0), (e1, i1, p1) = out[0], out[1]
+    assert e0 <= 1e-6 and e1 <= 1e-6, (e0, e1)
+    assert (i0["iters_bf16"], i0["iters_f32"]) == (i1["iters_bf16"], i1["iters_f32"]), (i0, i1)
+    assert 1 <= i1["iters_f64"] <= 2, i1
+    gp = q.GEMM_PREC
+    assert gp["f32"] in p0 and gp["bf16x3"] not in p0, p0
+    assert gp["bf16x3"] in p1 and gp["f32"] not in p1, p1
