@@ -496,6 +496,9 @@ def main() -> int:
             if scaling == "learned":
                 forms[label]["mu"] = inf_f["mu_used"]
             results[label] = Xf
+            if label == "mixed:qhpi19":  # where the ladder's time goes, as an earlier line
+                rec = ladder_breakdown(q, ctx, torch, Ain, fkw)
+                print(json.dumps({"section": "ladder_breakdown_4096", **rec}, default=float), flush=True)
 
     # ---------------------------------------------------------------- standalone product rates
     gemm = {}

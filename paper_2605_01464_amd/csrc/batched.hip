@@ -1363,24 +1363,29 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
         }
         loc += c;
       }
-      // exclusive scan: per-thread totals through the workgroup, then each thread's run
+      // exclusive scan of the per-thread totals: inclusive scan within each wave (shuffles), the waves'
+      // totals through LDS, then each thread's run (integer sums: the same result in any order)
       __syncthreads();
       if (tid == 0) pref[0] = 0;
       {
-        __shared__ int part[1024];
-        part[tid] = loc;
-        __syncthreads();
-        if (tid == 0) {
-          int acc = 0;
-          for (int t = 0; t < nthr; ++t) {
-            const int v = part[t];
-            part[t] = acc;
-            acc += v;
-          }
-          s_total = acc;
+        __shared__ int wtot[16];
+        const int lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+        int incl = loc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
         }
+        if (lane == 63) wtot[wv] = incl;
         __syncthreads();
-        int run = part[tid];
+        int base = 0, tot = 0;
+        for (int q = 0; q < nwv; ++q) {
+          const int t = wtot[q];
+          base += q < wv ? t : 0;
+          tot += t;
+        }
+        if (tid == 0) s_total = tot;
+        int run = base + incl - loc;
         for (int q = 0; q < per; ++q) {
           const int b = tid * per + q;
           if (b < P.count) {
