@@ -104,7 +104,7 @@ typedef enum {
                                   update, or stops falling, or after max_bf16_iters (8) updates; then
                                   as F32_F64FINISH, with every product of FP32 storage (the FP32 phase,
                                   the finish's corrections) as GEMM_BF16X3 (option mixed_split = 1, the
-                                  default; 0: native FP32 products) */
+                                  default; 0, and always in qpinv_solve_noalloc: native FP32 products) */
 } qpinv_precision;
 
 typedef enum { QPINV_GEMM_F64 = 0, QPINV_GEMM_F32 = 1, QPINV_GEMM_BF16 = 2, QPINV_GEMM_BF16X3 = 3 } qpinv_gemm_prec;

@@ -887,12 +887,13 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
   if (m == 0 || n == 0) return finish(QPINV_OK);
   if (small_eligible(c, method, scaling, stop, precision, m, n))
     return finish(small_solve(c, method, A0, scaling, am, tol, max_iter, stop, precision, Xout, inf, s));
-  // the ladder's FP32-storage products (its FP32 phase and the finish's corrections) as three BF16 products
+  // the ladder's FP32-storage products (its FP32 phase and the finish's corrections) as three BF16 products;
+  // not in an allocation-free call, whose stage buffer may not grow (the split copies need one)
   struct SplitScope {
     Ctx& c;
     SplitScope(Ctx& cx, bool on) : c(cx) { c.split_f32 = on; }
     ~SplitScope() { c.split_f32 = false; }
-  } split_scope(c, precision == QPINV_PREC_MIXED && c.opt.mixed_split != 0);
+  } split_scope(c, precision == QPINV_PREC_MIXED && c.opt.mixed_split != 0 && !c.no_alloc);
 
   // A in each storage type on demand
   Mat Acache[2];

@@ -50,6 +50,28 @@ def test_noalloc_matches_solve_two_calls(qctx):
     _compare(qctx, A3, "f32_f64finish", "qhpi19", 1e-6, "guarded")
 
 
+def test_noalloc_ladder_uses_native_fp32_products(qctx):
+    """The BF16 -> FP32 -> FP64 ladder without allocation: its FP32-storage products stay native FP32 (the split
+    BF16 products would need the stage buffer to grow), so it equals qpinv_solve with option mixed_split = 0 bit
+    for bit, on a fresh context as well as after the other calls."""
+    import paper_2605_01464_amd as q
+
+    qctx.set("autotune", 0)
+    A = qsynth.round_f32(np.random.default_rng(33).standard_normal((4, 150, 130)))
+    try:
+        qctx.set("mixed_split", 0)
+        _compare(qctx, A, "mixed", "qhpi19", 1e-6, "guarded")
+    finally:
+        qctx.set("mixed_split", 1)
+    fresh = q.Context(0)
+    try:
+        fresh.set("autotune", 0)
+        fresh.set("mixed_split", 0)
+        _compare(fresh, A, "mixed", "qhpi19", 1e-6, "guarded")
+    finally:
+        fresh.close()
+
+
 def test_noalloc_rejects_oversize_before_launch(qctx):
     """A shape whose workspace bound exceeds the scratch is refused with EINVAL; X is left untouched."""
     import torch
