@@ -247,13 +247,15 @@ int64_t qgemm_blocks(Prec p, int cfg, int64_t M, int64_t N) {
 }
 
 // Measured on MI355X: the 64 x 64 double-buffered tiles win once there are >= 4 of them per compute unit,
-// the 32 x 32 ones below that (fewer tiles leave compute units idle in the last wave).
+// the 32 x 32 ones below that (fewer tiles leave compute units idle in the last wave).  BF16 from 1024 tiles
+// of 64 x 64: the staged form with its operand tiles loaded straight into LDS; split BF16: 128 x 128 tiles
+// from 256 of them (one workgroup of 16 waves per CU), 64 x 64 below.
 int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
   (void)K;
   const int64_t b64 = ((M + 63) / 64) * ((N + 63) / 64);
   if (p == P_F64) return b64 >= 1024 ? 4 : 1;
-  if (p == P_BF16) return b64 >= 1024 ? 8 : b64 >= 256 ? 0 : 1;
-  if (p == P_BF16X3) return 0;
+  if (p == P_BF16) return b64 >= 1024 ? 11 : b64 >= 256 ? 0 : 1;
+  if (p == P_BF16X3) return ((M + 127) / 128) * ((N + 127) / 128) >= 256 ? 4 : 3;
   return b64 >= 1024 ? 5 : 6;
 }
 

@@ -597,7 +597,9 @@ struct Bf16Stage {
   int mp, np, kp;
 };
 
-template <int BM, int BN, int WM, int WN, class MB, bool PRIO = false>
+// DIRECT: the operand tiles go from the stage buffer straight to LDS (16-byte buffer loads with an LDS
+// destination) instead of through registers, which frees the staging registers for larger tiles.
+template <int BM, int BN, int WM, int WN, class MB, bool PRIO = false, bool DIRECT = false>
 __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf16Stage& S, int tm, int tn,
                                            __bf16* smem, double& s_d, double& s_x) {
   using C = Bf16SCfg<BM, BN, WM, WN, MB>;
@@ -720,7 +722,60 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
 
   constexpr int IH = C::ITEMS / 2;
   const int nk = S.kp / BK;
-  if (nk > 0) {
+  if constexpr (DIRECT) {
+    // One instruction per wave fills 16 LDS rows (64 bytes each) of one plane, lane l at byte 16 l: row
+    // 16 blk + l / 4, slot l % 4, which db_off gives the chunk (l % 4) ^ ((row >> 1) & 3) of that row.
+    constexpr int NIA = 4 * BM / 16, NI = NIA + 4 * BN / 16;
+    static_assert(NI % C::NW == 0, "whole LDS-direct instructions per wave");
+    auto issue = [&](__bf16* St, int k0) __attribute__((always_inline)) {
+#pragma unroll
+      for (int u = 0; u < NI / C::NW; ++u) {
+        const int i = w + u * C::NW;  // wave-uniform
+        const bool isA = i < NIA;
+        const int ii = isA ? i : i - NIA;
+        const int rows = isA ? BM : BN;
+        const int q = ii / (rows / 16), blk = ii % (rows / 16);
+        const int row = 16 * blk + (lane >> 2);
+        const int c = (lane & 3) ^ ((row >> 1) & 3);
+        const int voff = (((isA ? m0 : n0) + row) * S.kp + 8 * c) * 2;
+        const int soff = q * (isA ? psa : psb) + 2 * k0;
+        __bf16* const dst = St + (isA ? 0 : 4 * BM * BK) + (q * rows + 16 * blk) * BK;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(isA ? srcA : srcB, (__attribute__((address_space(3))) void*)dst, 16,
+                                                 voff, soff, 0, 0);
+      }
+    };
+    if (nk > 0) {
+      __syncthreads();  // the caller may have used the LDS just before (previous tile)
+      issue(smem, 0);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      for (int kt = 0; kt < nk; ++kt) {
+        __bf16* const cur = smem + (kt & 1) * C::STAGE;
+        // the other stage was last read in step kt - 1, before the barrier that ended it
+        if (kt + 1 < nk) issue(smem + ((kt + 1) & 1) * C::STAGE, (kt + 1) * BK);
+        if constexpr (C::TM == 1 && MB::KSUB > 1) {
+          // one row block per wave: the B fragments of one k sub-step at a time (half the registers; the
+          // same LDS reads and the same MFMA sequence)
+#pragma unroll
+          for (int h = 0; h < MB::KSUB; ++h) {
+            const __bf16* const Bs = cur + 4 * BM * BK;
+#pragma unroll
+            for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                b[j][h][q] = *reinterpret_cast<const bf16x8*>(
+                    &Bs[db_off(q * BN + wn * C::WTN + j * MB::BLK + fr, MB::chunk(lane, h))]);
+            compute(cur, h, h + 1);
+          }
+        } else {
+          frag_b(cur);
+          compute(cur, 0, C::ITEMS);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of step kt + 1 are in LDS
+        __syncthreads();
+      }
+    }
+  } else if (nk > 0) {
     load_a(0);
     load_b(0);
     store_a(smem);
@@ -764,7 +819,7 @@ __device__ __forceinline__ void bf16s_tile(const GemmParams<float>& P, const Bf1
     }
 }
 
-template <int BM, int BN, int WM, int WN, int MINW, class MB, bool PRIO>
+template <int BM, int BN, int WM, int WN, int MINW, class MB, bool PRIO, bool DIRECT>
 __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16s_kernel(GemmParams<float> P, Bf16Stage S) {
   using C = Bf16SCfg<BM, BN, WM, WN, MB>;
   __shared__ __attribute__((aligned(16))) __bf16 smem[2 * C::STAGE];
@@ -774,7 +829,7 @@ __global__ void __launch_bounds__(64 * WM * WN, MINW) qgemm_bf16s_kernel(GemmPar
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     int tm, tn;
     tile_of_block(t, nt, P.tiles_m, P.tiles_n, tm, tn);
-    bf16s_tile<BM, BN, WM, WN, MB, PRIO>(P, S, tm, tn, smem, s_d, s_x);
+    bf16s_tile<BM, BN, WM, WN, MB, PRIO, DIRECT>(P, S, tm, tn, smem, s_d, s_x);
   }
   store_partials<C::NW>(P.partial, s_d, s_x, red_lds, threadIdx.x & 63, threadIdx.x >> 6, threadIdx.x);
 }
@@ -903,7 +958,9 @@ bool bf16x3_fits(int64_t M, int64_t N, int64_t K) {
 }
 
 // SPLIT: the three-product form (operands split into BF16 hi and lo, products summed over 3 kp).
-template <int BM, int BN, int WM, int WN, int MINW, class MB = BfM16, bool PRIO = false, bool SPLIT = false>
+// DIRECT: operand tiles loaded straight into LDS.
+template <int BM, int BN, int WM, int WN, int MINW, class MB = BfM16, bool PRIO = false, bool SPLIT = false,
+          bool DIRECT = false>
 static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipStream_t s, GemmScratch& sc) {
   using C = Bf16SCfg<BM, BN, WM, WN, MB>;
   GemmParams<float> P = P0;
@@ -952,7 +1009,7 @@ static int64_t launch_bf16_staged(const GemmParams<float>& P0, int per_cu, hipSt
     QP_HIP(hipGetLastError());
   }
   const Bf16Stage S{a16, b16, (int)mp, (int)np, (int)kps};
-  auto kern = qgemm_bf16s_kernel<BM, BN, WM, WN, MINW, MB, PRIO>;
+  auto kern = qgemm_bf16s_kernel<BM, BN, WM, WN, MINW, MB, PRIO, DIRECT>;
   LaunchShape ls;
   ls.grid = nt;
   if (per_cu > 0) {
@@ -1001,6 +1058,15 @@ static const std::vector<Bf16Entry>& bf16_table() {
       {{8, 64, 64, 32, 512, "bf16_64x64x32_w2x4_mfma16x16x32_staged"}, launch_bf16_staged<64, 64, 2, 4, 4, BfM16, true>},
       {{9, 64, 64, 32, 256, "bf16_64x64x32_w2x2_mfma32x32x16_staged"}, launch_bf16_staged<64, 64, 2, 2, 2, BfM32>},
       {{10, 128, 64, 32, 512, "bf16_128x64x32_w4x2_mfma32x32x16_staged"}, launch_bf16_staged<128, 64, 4, 2, 2, BfM32>},
+      // Operand tiles loaded straight into LDS (no staging registers).  Measured at 4096^3 with the copies:
+      // 11 1108-1127 TFLOP/s (the default above 1024 tiles of 64 x 64; its products equal 8's and the direct
+      // forms' bit for bit), 12 (128 x 128, 16 waves of 32 x 32, one workgroup per CU) 1128-1168.  Dropped:
+      // 128 x 64 with 8 waves (933-965), 128 x 128 with 8 waves of 64 x 32 (333: one workgroup of 8 waves
+      // per CU), 128 x 128 with 16 waves on the 16 x 16 x 32 MFMA (634: spills in the K loop).
+      {{11, 64, 64, 32, 512, "bf16_64x64x32_w2x4_mfma16x16x32_staged_lds"},
+       launch_bf16_staged<64, 64, 2, 4, 4, BfM16, true, false, true>},
+      {{12, 128, 128, 32, 1024, "bf16_128x128x32_w4x4_mfma32x32x16_staged_lds"},
+       launch_bf16_staged<128, 128, 4, 4, 4, BfM32, false, false, true>},
   };
   return t;
 }
@@ -1031,6 +1097,12 @@ static const std::vector<Bf16Entry>& bf16x3_table() {
        launch_bf16_staged<64, 64, 2, 2, 2, BfM16, false, true>},
       {{2, 128, 64, 32, 512, "bf16x3_128x64x32_w4x2_mfma32x32x16_staged"},
        launch_bf16_staged<128, 64, 4, 2, 2, BfM32, false, true>},
+      // operand tiles straight into LDS; at 4096^3: 3 355-362 TFLOP/s of product flops (the default below 256
+      // tiles of 128 x 128), 4 408-410 (the default from 256 such tiles), 0 342-345, 2 353-355
+      {{3, 64, 64, 32, 512, "bf16x3_64x64x32_w2x4_mfma16x16x32_staged_lds"},
+       launch_bf16_staged<64, 64, 2, 4, 4, BfM16, true, true, true>},
+      {{4, 128, 128, 32, 1024, "bf16x3_128x128x32_w4x4_mfma32x32x16_staged_lds"},
+       launch_bf16_staged<128, 128, 4, 4, 4, BfM32, false, true, true>},
   };
   return t;
 }
