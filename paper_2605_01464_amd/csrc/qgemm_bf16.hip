@@ -1062,7 +1062,8 @@ static const std::vector<Bf16Entry>& bf16_table() {
       // 11 1108-1127 TFLOP/s (the default above 1024 tiles of 64 x 64; its products equal 8's and the direct
       // forms' bit for bit), 12 (128 x 128, 16 waves of 32 x 32, one workgroup per CU) 1128-1168.  Dropped:
       // 128 x 64 with 8 waves (933-965), 128 x 128 with 8 waves of 64 x 32 (333: one workgroup of 8 waves
-      // per CU), 128 x 128 with 16 waves on the 16 x 16 x 32 MFMA (634: spills in the K loop).
+      // per CU), 128 x 128 with 16 waves on the 16 x 16 x 32 MFMA (634: spills in the K loop), 12 with the
+      // issue priority raised around the MFMA blocks (1089; split 376 against 403).
       {{11, 64, 64, 32, 512, "bf16_64x64x32_w2x4_mfma16x16x32_staged_lds"},
        launch_bf16_staged<64, 64, 2, 4, 4, BfM16, true, false, true>},
       {{12, 128, 128, 32, 1024, "bf16_128x128x32_w4x4_mfma32x32x16_staged_lds"},
