@@ -5,9 +5,9 @@
 // synchronisations take most of the time.  Here one persistent launch runs the whole solve: workgroup 0
 // computes ||A||_F, the finiteness check and the power iteration, the grid forms X_0 = alpha A^H, and then
 // every product of every update is a phase whose items are 16 x 16 output blocks (all four planes), dealt to
-// the workgroups, which meet at a bounded grid barrier after each phase.  Within a block the 16 waves split
-// the four output planes and four slices of K (each lane's partial sums meet in LDS), so a product of
-// K = 64 costs each wave 16 MFMAs instead of the 256 one wave would issue alone.  The per-element epilogue
+// the workgroups, which meet at a bounded grid barrier after each phase.  Within a block the 8 waves split
+// the four output planes and two slices of K (each lane's partial sums meet in LDS), so a product of
+// K = 64 costs each wave 32 MFMAs instead of the 256 one wave would issue alone.  The per-element epilogue
 // is the standalone product kernel's (identity shifts, polynomial combinations, change norms).
 //
 // The products and epilogues of an update are the chain of the regular path (a program the host builds
@@ -83,6 +83,9 @@ struct SmParams {
   unsigned int* bar;     // [0] arrivals, [1] generation, [2] give-up flag
   unsigned long long* trace;  // optional (option verbose): workgroup 0 stamps wall_clock64() after each barrier
   int trace_cap;
+  // every product of the program with its buffers resolved, per phase, product and current iterate buffer
+  // (built on the host, read from LDS by each phase with independent loads)
+  GemmParams<T> gp[8][2][2];
 };
 
 // result record, doubles
@@ -90,6 +93,54 @@ enum : int {
   S_STATUS = 0, S_ITERS, S_RETURNED, S_REASON, S_ALPHA, S_S1SQ, S_NORMA2, S_DXREL, S_E1, S_RETBUF, S_NONFINITE,
   S_COUNT
 };
+
+constexpr int SM_SU = 8;  // loads in flight per thread in the element-wise passes
+
+// smallest lg with 2^lg >= x (x >= 1)
+__device__ __forceinline__ int lg_ceil(int x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
+// plane of row `row` in a plane-major stack of four m-row planes
+__device__ __forceinline__ int plane_of(int row, int m) { return (row >= m) + (row >= 2 * m) + (row >= 3 * m); }
+
+// A double moved between lanes of a row of 16 by a DPP control (both halves): no LDS round trip.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_XOR1 = 0xb1;         // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4e;         // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i of each 8 <- lane 7 - i
+constexpr int DPP_MIRROR = 0x140;      // lane i of each 16 <- lane 15 - i
+
+// Sum over aligned groups of L contiguous lanes (L a power of two <= 64), every lane of a group getting
+// the group's sum.  Each step adds two partial sums of equal size (the pairs commute, so every lane of a
+// group holds the same bits): quads by DPP, then the quads and halves of a row by mirrors, then the rows by
+// shuffles.
+__device__ __forceinline__ double group_sum(double x, int L) {
+  if (L >= 2) x += dpp_move<DPP_XOR1>(x);
+  if (L >= 4) x += dpp_move<DPP_XOR2>(x);
+  if (L >= 8) x += dpp_move<DPP_HALF_MIRROR>(x);
+  if (L >= 16) x += dpp_move<DPP_MIRROR>(x);
+  if (L >= 32) x += __shfl_xor(x, 16, 64);
+  if (L >= 64) x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
+// Sum over the wave, the same bits in every lane: row sums by DPP, then the four rows' sums in a fixed order.
+__device__ __forceinline__ double wave_sum(double x) {
+  x = group_sum(x, 16);
+  const long long b = __double_as_longlong(x);
+  double r[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 16 * q);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * q);
+    r[q] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  return (r[0] + r[1]) + (r[2] + r[3]);
+}
 
 __device__ __forceinline__ uint64_t sm_splitmix64(uint64_t counter, uint64_t seed) {
   uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
@@ -139,8 +190,7 @@ __device__ bool sm_sync(unsigned int* bar, unsigned int nblocks) {
 
 // workgroup sum of a double, fixed order (every thread gets it)
 __device__ __forceinline__ double sm_sum(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[w] = v;
@@ -151,7 +201,7 @@ __device__ __forceinline__ double sm_sum(double v, double* sh) {
 }
 
 template <class T>
-__device__ __forceinline__ SmView resolve(const SmParams<T>* P, int b, int cur) {
+__host__ __device__ __forceinline__ SmView resolve(const SmParams<T>* P, int b, int cur) {
   if (b == B_XC) return P->buf[1 + cur];
   if (b == B_XN) return P->buf[2 - cur];
   return P->buf[b];
@@ -203,8 +253,9 @@ __device__ __forceinline__ void make_uniform(GemmParams<T>& G) {
   }
 }
 
+// The product d of the program with its buffers resolved for the current iterate buffer `cur` (host).
 template <class T>
-__device__ __forceinline__ GemmParams<T> make_gemm(const SmParams<T>* P, const SmProd& d, int cur) {
+GemmParams<T> resolve_product(const SmParams<T>* P, const SmProd& d, int cur) {
   GemmParams<T> G{};
   const SmView a = resolve(P, d.a, cur), b = resolve(P, d.b, cur);
   G.A = static_cast<const T*>(a.p);
@@ -235,16 +286,36 @@ __device__ __forceinline__ GemmParams<T> make_gemm(const SmParams<T>* P, const S
     for (int u = 0; u < 3; ++u) G.cb[t][u] = (T)d.cb[t][u];
   }
   G.reduce = d.reduce != 0;
-  make_uniform(G);
   return G;
 }
 
+// The epilogue's inputs at one element of plane p.  All three loads are issued unconditionally (an absent
+// input, or every input when there is none, re-reads a valid address: the first input's element, or the
+// first element of A) and the values are selected afterwards: a load under a branch on the input count
+// would be waited for inside the branch, one memory latency per load instead of one for all of them.
+template <class T>
+__device__ __forceinline__ void sm_inputs(const GemmParams<T>& G, int p, int row, int col, T (&inv)[3]) {
+  const bool ok = row < G.M && col < G.N;
+  const int64_t r = row < G.M ? row : G.M - 1, c = col < G.N ? col : G.N - 1;
+  const bool any = G.nin > 0;
+  const T* const base = any ? G.in[0] : G.A;
+  const int64_t off0 = any ? p * G.psi[0] + r * G.ldi[0] + c : 0;
+  T x[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const bool use = u < G.nin;
+    x[u] = gload(use ? G.in[u] : base, use ? p * G.psi[u] + r * G.ldi[u] + c : off0);
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) inv[u] = ok && u < G.nin ? x[u] : T(0);
+}
+
 // One 16 x 16 output block (all four planes) of C = A B with the epilogue.  The block's operands are staged
-// in LDS SM_KB deep in k, every thread loading two elements of each (one memory latency per round): A as
-// [plane][row][k], B as [plane][k][column], both padded by one element.  Wave w then takes output plane w % 4
-// and the k chunks (of 4) with index = w / 4 modulo SM_KSPLIT; the slices' partial sums meet in LDS (`red`,
-// which reuses the staging area), and the first slice's waves run the epilogue.  The reduction terms are
-// added to s_d, s_x.
+// in LDS SM_KB deep in k, every thread loading eight elements of each (one memory latency per round): A as
+// [plane][row][k], B as [plane][k][column], both padded by one element; the k slots beyond the operands hold
+// zeros.  Wave w then takes output plane w % 4 and the k chunks (of 4) with index = w / 4 modulo SM_KSPLIT;
+// the slices' partial sums meet in LDS (`red`, which reuses the staging area), and the first slice's waves
+// run the epilogue.  The reduction terms are added to s_d, s_x.
 constexpr int SM_KB = 64;  // k staged per round (products of K <= 64 take one round)
 template <class T>
 constexpr int sm_stage_elems() {
@@ -267,38 +338,37 @@ __device__ void sm_block(const GemmParams<T>& G, int tm, int tn, T* stage, typen
   T inv[4][3];
   if (ks == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) epilogue_inputs(G, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
+    for (int r = 0; r < 4; ++r) sm_inputs(G, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
   }
-  constexpr int NU = 4 * 16 * SM_KB / SM_THREADS;  // staged elements of each operand per thread, at most
+  constexpr int NU = 4 * 16 * SM_KB / SM_THREADS;  // staged elements of each operand per thread
+  static_assert(NU * SM_THREADS == 4 * 16 * SM_KB && SM_KB == 64, "staging map: 4 planes x 16 x 64 slots");
   for (int k0 = 0; k0 < G.K; k0 += SM_KB) {
     const int kr = G.K - k0 < SM_KB ? G.K - k0 : SM_KB;  // k of this round
     const int kr4 = (kr + 3) & ~3;
-    const int lim = 4 * 16 * kr4;
     // every load is issued before the first LDS store (one memory latency per round); addresses are clamped
-    // into the operands and the values outside them replaced by zeros
+    // into the operands and the values outside them (k beyond the round included) replaced by zeros.  Slot
+    // e of A is (plane e / 1024, row (e / 64) % 16, k e % 64), k fastest (rows of A are contiguous in k);
+    // slot e of B is (plane e / 1024, k (e / 16) % 64, column e % 16), columns fastest.
     T va[NU], vb[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int e = tid + u * SM_THREADS;
-      // A: k fastest (rows of A are contiguous in k); B: columns fastest
-      const int qa = e / (16 * kr4), ra = (e / kr4) % 16, kka = e % kr4;
-      const int row = rb + ra, ka = k0 + kka;
-      const bool oka = e < lim && row < G.M && ka < G.K;
-      const int qb = e / (kr4 * 16), kkb = (e / 16) % kr4, cc = e % 16;
-      const int col = cb + cc, kb = k0 + kkb;
-      const bool okb = e < lim && kb < G.K && col < G.N;
-      va[u] = gload(G.A, (oka ? qa : 0) * G.psa + (int64_t)(oka ? row : 0) * G.lda + (oka ? ka : 0));
-      vb[u] = gload(G.B, (okb ? qb : 0) * G.psb + (int64_t)(okb ? kb : 0) * G.ldb + (okb ? col : 0));
-      va[u] = oka ? va[u] : T(0);
-      vb[u] = okb ? vb[u] : T(0);
+      const int qa = e >> 10, ra = (e >> 6) & 15, kka = e & 63;
+      const int row = rb + ra;
+      const bool oka = kka < kr && row < G.M;
+      const int qb = e >> 10, kkb = (e >> 4) & 63, cc = e & 15;
+      const int col = cb + cc;
+      const bool okb = kkb < kr && col < G.N;
+      va[u] = gload(G.A, oka ? qa * G.psa + (int64_t)row * G.lda + (k0 + kka) : 0);
+      vb[u] = gload(G.B, okb ? qb * G.psb + (int64_t)(k0 + kkb) * G.ldb + col : 0);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int e = tid + u * SM_THREADS;
-      if (e < lim) {
-        As[((e / (16 * kr4)) * 16 + (e / kr4) % 16) * (SM_KB + 1) + e % kr4] = va[u];
-        Bs[((e / (kr4 * 16)) * SM_KB + (e / 16) % kr4) * 17 + e % 16] = vb[u];
-      }
+      const bool oka = (e & 63) < kr && rb + ((e >> 6) & 15) < G.M;
+      const bool okb = ((e >> 4) & 63) < kr && cb + (e & 15) < G.N;
+      As[((e >> 10) * 16 + ((e >> 6) & 15)) * (SM_KB + 1) + (e & 63)] = oka ? va[u] : T(0);
+      Bs[((e >> 10) * SM_KB + ((e >> 4) & 63)) * 17 + (e & 15)] = okb ? vb[u] : T(0);
     }
     __syncthreads();
     const int r16 = lane & 15, kl = lane >> 4;
@@ -333,24 +403,30 @@ __device__ void sm_block(const GemmParams<T>& G, int tm, int tn, T* stage, typen
   __syncthreads();  // the staging area is reused by the next block
 }
 
-// w = A v (adj = false; v: 4 n, w: 4 m) or w = A^H v (adj = true; v: 4 m, w: 4 n), planes [p][i], in LDS;
-// part holds the column-chunk partial sums.  Sums over fixed chunks in a fixed order.
-template <class T>
-__device__ void sm_gemv(const T* a, int64_t lda, int64_t psa, int m, int n, bool adj, const double* v, double* w,
-                        double* part) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int rows = adj ? n : m, cols = adj ? m : n;
-  const int chunks = nt / rows;  // rows <= 128 -> at least 4
-  if (tid < rows * chunks) {
-    const int i = tid % rows, c = tid / rows;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = c; j < cols; j += chunks) {
+// w = c A v (ADJ = false; v: 4 n, w: 4 m) or w = c A^H v (ADJ = true; v: 4 m, w: 4 n), planes [p][i], v
+// and w in LDS, A in LDS or in device memory (the address space of AP).  Element i of w is the sum of a group
+// of L lanes (L a power of two, the largest with one group per row; groups are contiguous within a wave),
+// lane l of the group taking the columns l, l + L, ...; the group's sums meet in a fixed order (group_sum).
+// Returns the sum of |w_i|^2 over the rows this lane wrote (nonzero on the groups' first lanes only).
+template <bool ADJ, class AP>
+__device__ double sm_gemv(AP a, int64_t lda, int64_t psa, int m, int n, double c, const double* v, double* w) {
+  const int tid = threadIdx.x;
+  const int rows = ADJ ? n : m, cols = ADJ ? m : n;
+  const int lgl = min(6, 31 - __clz((int)blockDim.x / rows));  // rows <= 128, 512 threads: L >= 4
+  const int L = 1 << lgl, i = tid >> lgl, l = tid & (L - 1);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < rows) {
+#pragma unroll 2
+    for (int j = l; j < cols; j += L) {
       // element (i, j) of A or of A^H (= conj of A's (j, i))
-      const int64_t off = adj ? (int64_t)j * lda + i : (int64_t)i * lda + j;
-      double aq[4];
+      const int64_t off = ADJ ? (int64_t)j * lda + i : (int64_t)i * lda + j;
+      double aq[4], vq[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) aq[q] = (double)a[q * psa + off];
-      if (adj) {
+      for (int q = 0; q < 4; ++q) {
+        aq[q] = (double)a[q * psa + off];
+        vq[q] = v[q * cols + j];
+      }
+      if (ADJ) {
         aq[1] = -aq[1];
         aq[2] = -aq[2];
         aq[3] = -aq[3];
@@ -358,40 +434,85 @@ __device__ void sm_gemv(const T* a, int64_t lda, int64_t psa, int m, int n, bool
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[pl] += qsign(pl, q) * aq[q] * v[(pl ^ q) * cols + j];
+        for (int q = 0; q < 4; ++q) s[pl] += qsign(pl, q) * aq[q] * vq[pl ^ q];
     }
+  }
 #pragma unroll
-    for (int pl = 0; pl < 4; ++pl) part[(c * 4 + pl) * rows + i] = s[pl];
+  for (int pl = 0; pl < 4; ++pl) s[pl] = group_sum(s[pl], L);
+  double nrm = 0.0;
+  if (i < rows && l == 0) {
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      const double x = c * s[pl];
+      w[pl * rows + i] = x;
+      nrm += x * x;
+    }
   }
-  __syncthreads();
-  if (tid < 4 * rows) {
-    const int pl = tid / rows, i = tid % rows;
-    double t = 0.0;
-    for (int c = 0; c < chunks; ++c) t += part[(c * 4 + pl) * rows + i];
-    w[pl * rows + i] = t;
+  return nrm;
+}
+
+// Sum over the workgroup of one double per thread, through per-wave partials in sh[0 .. waves): the waves'
+// sums are written, then after the barrier every thread adds them in wave order.
+__device__ __forceinline__ double sm_sum_partials(const double* sh) {
+  double t = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
+  return t;
+}
+
+// Sum of count <= 64 per-tile values v[t * stride], one load per lane and a fixed-order wave sum: every
+// workgroup adds the same pairs in the same order, so all of them get the same bits.
+static_assert((SM_MAXD / 16) * (SM_MAXD / 16) <= 64, "a product's output blocks fit one wave");
+__device__ __forceinline__ double sm_tile_sum(const double* v, int count, int stride) {
+  const int lane = threadIdx.x & 63;
+  const double x = gload(v, (int64_t)(lane < count ? lane : 0) * stride);
+  return wave_sum(lane < count ? x : 0.0);
+}
+
+// The power iteration of the classical scaling, run by one workgroup: v_0 from the seeded generator, then
+// per step v <- v / ||v||, w = A v, sigma_1^2 estimate ||w||^2, v <- A^H w.  The normalisation is folded into
+// the product (w = (A v) / ||v||), ||v||^2 and ||w||^2 ride along as wave partials, so a step is two
+// workgroup barriers.  Returns the last step's ||w||^2.
+template <class AP>
+__device__ double sm_power(AP a, int64_t lda, int64_t psa, int m, int n, int steps, uint64_t seed, double* vs,
+                           double* wsv, double* shv, double* shw) {
+  const int tid = threadIdx.x, wv = tid >> 6;
+  double vv = 0.0;
+  for (int e = tid; e < 4 * n; e += blockDim.x) {
+    const double x = (double)(sm_splitmix64((uint64_t)e, seed) >> 11) * 0x1p-52 - 1.0;
+    vs[e] = x;
+    vv += x * x;
   }
+  vv = wave_sum(vv);
+  if ((tid & 63) == 0) shv[wv] = vv;
   __syncthreads();
+  double s1sq = 0.0;
+  for (int it = 0; it < steps; ++it) {
+    const double inv = 1.0 / sqrt(sm_sum_partials(shv));
+    const double ww = wave_sum(sm_gemv<false>(a, lda, psa, m, n, inv, vs, wsv));
+    if ((tid & 63) == 0) shw[wv] = ww;
+    __syncthreads();
+    s1sq = sm_sum_partials(shw);
+    const double nv = wave_sum(sm_gemv<true>(a, lda, psa, m, n, 1.0, wsv, vs));
+    if ((tid & 63) == 0) shv[wv] = nv;
+    __syncthreads();
+  }
+  return s1sq;
 }
 
 template <class T, class MM>
 __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<T>* __restrict__ Pg) {
-  // one LDS area serves the K-slice exchange of the products ((SM_KSPLIT - 1) x 4 planes x 64 lanes of
-  // accumulators) and the power iteration's chunk sums (chunks x 4 planes x rows <= 4 x threads doubles)
-  // one LDS area: the operand staging of a product (whole K), the K-slice exchange after it, and in the
-  // set-up the power iteration's chunk sums followed by a copy of A when A fits
+  // one LDS area: the operand staging of a product (one K round), the K-slice exchange after it ((SM_KSPLIT - 1)
+  // x 4 planes x 64 lanes of accumulators), and in the set-up a copy of A when A fits
   constexpr int RED_BYTES = (SM_KSPLIT - 1) * 4 * 64 * (int)sizeof(typename MM::Acc);
-  constexpr int PART_BYTES = 4 * SM_THREADS * (int)sizeof(double);
   constexpr int STAGE_BYTES = sm_stage_elems<T>() * (int)sizeof(T);
-  constexpr int SETUP_BYTES = 120 * 1024;  // chunk sums + a copy of A of up to 104 KB
+  constexpr int SETUP_BYTES = 120 * 1024;  // a copy of A of up to 120 KB
   constexpr int LDS_BYTES0 = STAGE_BYTES > RED_BYTES ? STAGE_BYTES : RED_BYTES;
   constexpr int LDS_BYTES = LDS_BYTES0 > SETUP_BYTES ? LDS_BYTES0 : SETUP_BYTES;
-  static_assert(LDS_BYTES >= PART_BYTES, "set-up scratch fits");
   __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
   typename MM::Acc* const red = reinterpret_cast<typename MM::Acc*>(lds);
-  double* const part = reinterpret_cast<double*>(lds);
   T* const stage = reinterpret_cast<T*>(lds);
-  T* const acopy = reinterpret_cast<T*>(lds + PART_BYTES);
-  constexpr int ACOPY_ELEMS = (LDS_BYTES - PART_BYTES) / (int)sizeof(T);
+  T* const acopy = reinterpret_cast<T*>(lds);
+  constexpr int ACOPY_ELEMS = LDS_BYTES / (int)sizeof(T);
   __shared__ double sh[32];
   __shared__ double vs[4 * SM_MAXD], wsv[4 * SM_MAXD];
   // the parameter block, read once from device memory (phases index it by product and buffer)
@@ -416,43 +537,46 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
 
   // ---------------------------------------------------------------- set-up (workgroup 0)
   if (blockIdx.x == 0) {
+    // one pass over A: ||A||_F^2, the non-finite count and, for the power iteration, a copy of A in LDS
+    // when it fits (every power step reads all of it twice).  Rows (plane-major, 4 m of them) are mapped
+    // on slots of 2^lgw >= n columns, so a slot's row and column are a shift and a mask, and every thread
+    // has SM_SU loads in flight at a time.
+    const bool in_lds = P->scaling == QPINV_ALPHA_POWER && 4 * m * n <= ACOPY_ELEMS;
     double fro = 0.0, bad = 0.0;
-    for (int e = tid; e < 4 * m * n; e += blockDim.x) {
-      const int pl = e / (m * n), r = (e / n) % m, c = e % n;
-      const double x = (double)gload(a, pl * A.ps + (int64_t)r * A.ld + c);
-      if (!__builtin_isfinite(x)) bad += 1.0;
-      fro += x * x;
+    {
+      const int lgw = lg_ceil(n), slots = (4 * m) << lgw;
+      for (int e0 = tid; e0 < slots; e0 += SM_SU * (int)blockDim.x) {
+        T v[SM_SU];
+#pragma unroll
+        for (int u = 0; u < SM_SU; ++u) {
+          const int e = e0 + u * (int)blockDim.x, row = e >> lgw, c = e & ((1 << lgw) - 1);
+          const int pl = plane_of(row, m);
+          const bool ok = e < slots && c < n;
+          v[u] = gload(a, ok ? pl * A.ps + (int64_t)(row - pl * m) * A.ld + c : 0);
+        }
+#pragma unroll
+        for (int u = 0; u < SM_SU; ++u) {
+          const int e = e0 + u * (int)blockDim.x, row = e >> lgw, c = e & ((1 << lgw) - 1);
+          if (e < slots && c < n) {
+            const double x = (double)v[u];
+            if (!__builtin_isfinite(x)) bad += 1.0;
+            fro += x * x;
+            if (in_lds) acopy[row * n + c] = v[u];
+          }
+        }
+      }
     }
     fro = sm_sum(fro, sh);
     bad = sm_sum(bad, sh);
     double alpha = 0.0, s1sq = 0.0;
     if (bad == 0.0 && fro > 0.0) {
       if (P->scaling == QPINV_ALPHA_POWER) {
-        // A into LDS when it fits (every power step reads all of it twice)
-        const bool in_lds = 4 * m * n <= ACOPY_ELEMS;
         if (in_lds)
-          for (int e = tid; e < 4 * m * n; e += blockDim.x) {
-            const int pl = e / (m * n), r = (e / n) % m, c = e % n;
-            acopy[e] = gload(a, pl * A.ps + (int64_t)r * A.ld + c);
-          }
-        const T* const ap = in_lds ? acopy : a;
-        const int64_t ald = in_lds ? n : A.ld, aps = in_lds ? (int64_t)m * n : A.ps;
-        for (int e = tid; e < 4 * n; e += blockDim.x)
-          vs[e] = (double)(sm_splitmix64((uint64_t)e, P->seed) >> 11) * 0x1p-52 - 1.0;
-        __syncthreads();
-        for (int it = 0; it < P->power_steps; ++it) {
-          double vv = 0.0;
-          for (int e = tid; e < 4 * n; e += blockDim.x) vv += vs[e] * vs[e];
-          vv = sm_sum(vv, sh);
-          const double inv = 1.0 / sqrt(vv);
-          for (int e = tid; e < 4 * n; e += blockDim.x) vs[e] *= inv;
-          __syncthreads();
-          sm_gemv<T>(ap, ald, aps, m, n, false, vs, wsv, part);
-          double ww = 0.0;
-          for (int e = tid; e < 4 * m; e += blockDim.x) ww += wsv[e] * wsv[e];
-          s1sq = sm_sum(ww, sh);
-          sm_gemv<T>(ap, ald, aps, m, n, true, wsv, vs, part);
-        }
+          s1sq = sm_power((const __attribute__((address_space(3))) T*)acopy, n, (int64_t)m * n, m, n,
+                          P->power_steps, P->seed, vs, wsv, sh, sh + 16);
+        else
+          s1sq = sm_power((const __attribute__((address_space(1))) T*)a, A.ld, A.ps, m, n,
+                          P->power_steps, P->seed, vs, wsv, sh, sh + 16);
         alpha = (P->mu > 0.0 ? P->mu : 1.0) / s1sq;
       } else if (P->scaling == QPINV_ALPHA_FROB) {
         alpha = 1.0 / fro;
@@ -481,12 +605,23 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
 
   // ---------------------------------------------------------------- X_0 = alpha A^H into iterate 0
   {
+    // X_0 element (r, c) = alpha conj(A(c, r)); X_0's 4 n rows on slots of 2^lgw >= m columns
     const SmView X0 = P->buf[1];
     T* x = static_cast<T*>(X0.p);
-    for (int e = gtid; e < 4 * m * n; e += gthreads) {
-      const int pl = e / (m * n), r = (e / m) % n, c = e % m;  // X0 element (r, c) = conj(A(c, r))
-      const T v = gload(a, pl * A.ps + (int64_t)c * A.ld + r);
-      gstore(x, pl * X0.ps + (int64_t)r * X0.ld + c, (T)(alpha * (double)(pl == 0 ? v : -v)));
+    const int lgw = lg_ceil(m), slots = (4 * n) << lgw;
+    for (int e0 = gtid; e0 < slots; e0 += SM_SU * gthreads) {
+      T v[SM_SU];
+#pragma unroll
+      for (int u = 0; u < SM_SU; ++u) {
+        const int e = e0 + u * gthreads, row = e >> lgw, c = e & ((1 << lgw) - 1), pl = plane_of(row, n);
+        v[u] = gload(a, e < slots && c < m ? pl * A.ps + (int64_t)c * A.ld + (row - pl * n) : 0);
+      }
+#pragma unroll
+      for (int u = 0; u < SM_SU; ++u) {
+        const int e = e0 + u * gthreads, row = e >> lgw, c = e & ((1 << lgw) - 1), pl = plane_of(row, n);
+        if (e < slots && c < m)
+          gstore(x, pl * X0.ps + (int64_t)(row - pl * n) * X0.ld + c, (T)(alpha * (double)(pl == 0 ? v[u] : -v[u])));
+      }
     }
   }
   if (!sm_sync(P->bar, G)) return;
@@ -506,15 +641,14 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
       int tiles[2] = {0, 0};
       for (int q = 0; q < 2; ++q) {
         if (q >= np || (q == 1 && ph == P->prog.e1_phase && j == 0)) continue;
-        const SmProd& d = P->prog.prod[ph][q];
-        const SmView a = resolve(P, d.a, cur), b = resolve(P, d.b, cur);
-        tiles[q] = ((a.rows + 15) / 16) * ((b.cols + 15) / 16);
+        tiles[q] = P->gp[ph][q][cur].tiles_m * P->gp[ph][q][cur].tiles_n;
       }
       const int total = tiles[0] + tiles[1];
       for (int item = blockIdx.x; item < total; item += G) {
         const int q = item < tiles[0] ? 0 : 1;
         const int t = item - (q ? tiles[0] : 0);
-        const GemmParams<T> gq = make_gemm(P, P->prog.prod[ph][q], cur);
+        GemmParams<T> gq = P->gp[ph][q][cur];
+        make_uniform(gq);
         double s_d = 0.0, s_x = 0.0;
         sm_block<T, MM>(gq, t / gq.tiles_n, t % gq.tiles_n, stage, red, s_d, s_x);
         const int kind = P->prog.prod[ph][q].reduce;
@@ -532,8 +666,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   stamp();
       if (e1 && ph == P->prog.e1_phase && j >= 1) {
         // ||A X_j A - A||_F / ||A||_F from the tiles of the E1 product, summed in tile order
-        double s = 0.0;
-        for (int t = 0; t < tiles[1]; ++t) s += P->partial[2 * 2 * SM_MAXG + 2 * t + 1];
+        const double s = sm_tile_sum(P->partial + 2 * 2 * SM_MAXG + 1, tiles[1], 2);
         e1_rel = sqrt(s) / normA;
         const int dec = ctl.update(j, 0.0, 1.0, e1_rel);
         if (dec == D_DIVERGED) {
@@ -553,13 +686,9 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
         }
       }
       if (done || ph != P->prog.nphase - 1) continue;
-      // the update X_{j+1} = X_nxt is formed: change norms in tile order, then the stop rule
+      // the update X_{j+1} = X_nxt is formed: its change norms summed over the tiles, then the stop rule
       const int tu = P->prog.prod[ph][0].reduce == 1 ? tiles[0] : 0;
-      double d2 = 0.0, x2 = 0.0;
-      for (int t = 0; t < tu; ++t) {
-        d2 += P->partial[2 * t];
-        x2 += P->partial[2 * t + 1];
-      }
+      const double d2 = sm_tile_sum(P->partial, tu, 2), x2 = sm_tile_sum(P->partial + 1, tu, 2);
       const double d_abs = sqrt(fmax(0.0, d2)), xn = sqrt(fmax(0.0, x2));
       ++j;
       dx_rel = xn > 0.0 ? d_abs / xn : 0.0;
@@ -594,9 +723,19 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   if (P->xout_direct) {
     const SmView Xr = P->buf[1 + ret_buf];
     const T* x = static_cast<const T*>(Xr.p);
-    for (int e = gtid; e < 4 * m * n; e += gthreads) {
-      const int pl = e / (m * n), r = (e / m) % n, c = e % m;
-      gstore(P->xout, pl * P->psx + (int64_t)r * P->ldx + c, gload(x, pl * Xr.ps + (int64_t)r * Xr.ld + c));
+    const int lgw = lg_ceil(m), slots = (4 * n) << lgw;
+    for (int e0 = gtid; e0 < slots; e0 += SM_SU * gthreads) {
+      T v[SM_SU];
+#pragma unroll
+      for (int u = 0; u < SM_SU; ++u) {
+        const int e = e0 + u * gthreads, row = e >> lgw, c = e & ((1 << lgw) - 1), pl = plane_of(row, n);
+        v[u] = gload(x, e < slots && c < m ? pl * Xr.ps + (int64_t)(row - pl * n) * Xr.ld + c : 0);
+      }
+#pragma unroll
+      for (int u = 0; u < SM_SU; ++u) {
+        const int e = e0 + u * gthreads, row = e >> lgw, c = e & ((1 << lgw) - 1), pl = plane_of(row, n);
+        if (e < slots && c < m) gstore(P->xout, pl * P->psx + (int64_t)(row - pl * n) * P->ldx + c, v[u]);
+      }
     }
   }
   if (blockIdx.x == 0 && tid == 0) {
@@ -860,6 +999,9 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
   P.partial = static_cast<double*>(c.ws.get("smPartial", sizeof(double) * 2 * 2 * 2 * SM_MAXG));
   P.state = static_cast<double*>(c.ws.get("smState", sizeof(double) * (S_COUNT + 2)));
   P.bar = reinterpret_cast<unsigned int*>(P.state + S_COUNT);
+  for (int ph = 0; ph < P.prog.nphase; ++ph)
+    for (int q = 0; q < P.prog.nprod[ph]; ++q)
+      for (int cur = 0; cur < 2; ++cur) P.gp[ph][q][cur] = resolve_product(&P, P.prog.prod[ph][q], cur);
   constexpr int kTrace = 256;
   if (c.opt.verbose) {
     P.trace = static_cast<unsigned long long*>(c.ws.get("smTrace", sizeof(unsigned long long) * kTrace));

@@ -62,7 +62,7 @@ struct Ctx {
   GemmScratch scratch;
   double* dsc = nullptr;  // device scalars
   double* hsc = nullptr;  // pinned host scalars
-  static constexpr size_t kStageBytes = 8192;
+  static constexpr size_t kStageBytes = 16384;
   void* hstage = nullptr;  // pinned host staging area for small parameter blocks (kStageBytes)
   std::map<std::tuple<int, int64_t, int64_t, int64_t>, int> tuned;
   MlpState* mlp = nullptr;
