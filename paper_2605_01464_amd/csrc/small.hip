@@ -67,10 +67,7 @@ struct SmProgram {
 
 template <class T>
 struct SmParams {
-  SmView buf[B_N];       // B_XC / B_XN hold iterate buffers 0 / 1
-  T* xout;               // the caller's X (n x m), written directly when xout_direct
-  int64_t ldx, psx;
-  int xout_direct;
+  SmView buf[B_N];       // B_XC / B_XN hold iterate buffers 0 / 1; B_A's pointer and strides come per call
   SmProgram prog;
   int m, n;
   int scaling, power_steps;
@@ -79,19 +76,33 @@ struct SmParams {
   int stop, max_iter;
   double tol;
   double* partial;       // [2][2][SM_MAXG * 2]: per item reduction terms (slot by phase kind)
-  double* state;         // result record (see SmState)
+  double* state;         // the set-up's results, broadcast to the workgroups (record slots)
   unsigned int* bar;     // [0] arrivals, [1] generation, [2] give-up flag
   unsigned long long* trace;  // optional (option verbose): workgroup 0 stamps wall_clock64() after each barrier
   int trace_cap;
   // every product of the program with its buffers resolved, per phase, product and current iterate buffer
-  // (built on the host, read from LDS by each phase with independent loads)
+  // (built on the host, read from LDS by each phase with independent loads); an operand that is the input
+  // matrix is marked in `vec` (bit 0: A, bit 1: B) and filled in per call
   GemmParams<T> gp[8][2][2];
 };
 
-// result record, doubles
+// What changes from one call to the next, passed by value: the input matrix, the caller's X (n x m, written
+// directly when xout_direct) and the result record in pinned host memory (S_COUNT doubles, written by
+// workgroup 0).  The parameter block itself stays in device memory while its bytes do not change.
+template <class T>
+struct SmCall {
+  const T* a;
+  int64_t lda, psa;
+  T* xout;
+  int64_t ldx, psx;
+  int xout_direct;
+  double* hres;
+};
+
+// result record, doubles (S_GIVEUP: the barrier's give-up flag as workgroup 0 saw it at the end)
 enum : int {
   S_STATUS = 0, S_ITERS, S_RETURNED, S_REASON, S_ALPHA, S_S1SQ, S_NORMA2, S_DXREL, S_E1, S_RETBUF, S_NONFINITE,
-  S_COUNT
+  S_GIVEUP, S_COUNT
 };
 
 constexpr int SM_SU = 8;  // loads in flight per thread in the element-wise passes
@@ -286,6 +297,20 @@ GemmParams<T> resolve_product(const SmParams<T>* P, const SmProd& d, int cur) {
     for (int u = 0; u < 3; ++u) G.cb[t][u] = (T)d.cb[t][u];
   }
   G.reduce = d.reduce != 0;
+  // the input matrix comes per call: marked here, no pointer or strides of it in the table
+  G.vec = (d.a == B_A ? 1 : 0) | (d.b == B_A ? 2 : 0);
+  if (d.a == B_A) {
+    G.A = nullptr;
+    G.lda = G.psa = 0;
+  }
+  if (d.b == B_A) {
+    G.B = nullptr;
+    G.ldb = G.psb = 0;
+  }
+  for (int t = 0; t < 3; ++t) {
+    if (t >= d.nout) G.ldo[t] = G.pso[t] = 0;
+    if (t >= d.nin) G.ldi[t] = G.psi[t] = 0;
+  }
   return G;
 }
 
@@ -499,8 +524,29 @@ __device__ double sm_power(AP a, int64_t lda, int64_t psa, int m, int n, int ste
   return s1sq;
 }
 
+// The result record, written into pinned host memory by one thread at the end of the solve.
+template <class T>
+__device__ void sm_record(const SmParams<T>* P, double* hres, int status, int iters, int returned, int reason, double alpha,
+                          double s1sq, double fro, double dx_rel, double e1_rel, int ret_buf, double bad) {
+  double r[S_COUNT];
+  r[S_STATUS] = status;
+  r[S_ITERS] = iters;
+  r[S_RETURNED] = returned;
+  r[S_REASON] = reason;
+  r[S_ALPHA] = alpha;
+  r[S_S1SQ] = s1sq;
+  r[S_NORMA2] = fro;
+  r[S_DXREL] = dx_rel;
+  r[S_E1] = e1_rel;
+  r[S_RETBUF] = ret_buf;
+  r[S_NONFINITE] = bad;
+  r[S_GIVEUP] = __hip_atomic_load(&P->bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int k = 0; k < S_COUNT; ++k) gstore(hres, k, r[k]);
+}
+
 template <class T, class MM>
-__global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<T>* __restrict__ Pg) {
+__global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<T>* __restrict__ Pg, const SmCall<T> call) {
   // one LDS area: the operand staging of a product (one K round), the K-slice exchange after it ((SM_KSPLIT - 1)
   // x 4 planes x 64 lanes of accumulators), and in the set-up a copy of A when A fits
   constexpr int RED_BYTES = (SM_KSPLIT - 1) * 4 * 64 * (int)sizeof(typename MM::Acc);
@@ -515,11 +561,23 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   constexpr int ACOPY_ELEMS = LDS_BYTES / (int)sizeof(T);
   __shared__ double sh[32];
   __shared__ double vs[4 * SM_MAXD], wsv[4 * SM_MAXD];
-  // the parameter block, read once from device memory (phases index it by product and buffer)
-  __shared__ __attribute__((aligned(16))) unsigned int pcopy[(sizeof(SmParams<T>) + 3) / 4];
+  // the parameter block, read once from device memory (phases index it by product and buffer); every
+  // thread issues its loads before its first LDS store, one round trip for the whole block
+  constexpr int PV = (int)((sizeof(SmParams<T>) + 15) / 16), PU = (PV + SM_THREADS - 1) / SM_THREADS;
+  __shared__ uint4 pcopy[PV];
   {
-    const unsigned int* src = reinterpret_cast<const unsigned int*>(Pg);
-    for (int i = threadIdx.x; i < (int)((sizeof(SmParams<T>) + 3) / 4); i += blockDim.x) pcopy[i] = src[i];
+    const uint4* src = reinterpret_cast<const uint4*>(Pg);
+    uint4 v[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int i = (int)threadIdx.x + u * SM_THREADS;
+      v[u] = src[i < PV ? i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int i = (int)threadIdx.x + u * SM_THREADS;
+      if (i < PV) pcopy[i] = v[u];
+    }
     __syncthreads();
   }
   const SmParams<T>* const P = reinterpret_cast<const SmParams<T>*>(pcopy);
@@ -532,7 +590,10 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   };
   stamp();
   const int m = P->m, n = P->n;
-  const SmView A = P->buf[B_A];
+  SmView A = P->buf[B_A];
+  A.p = const_cast<T*>(call.a);
+  A.ld = call.lda;
+  A.ps = call.psa;
   const T* a = static_cast<const T*>(A.p);
 
   // ---------------------------------------------------------------- set-up (workgroup 0)
@@ -597,7 +658,8 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   const double fro = __hip_atomic_load(&P->state[S_NORMA2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double alpha = __hip_atomic_load(&P->state[S_ALPHA], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (bad != 0.0) {
-    if (blockIdx.x == 0 && tid == 0) P->state[S_STATUS] = QPINV_ENONFINITE;
+    if (blockIdx.x == 0 && tid == 0)
+      sm_record(P, call.hres, QPINV_ENONFINITE, 0, 0, QPINV_REASON_TOL, alpha, P->state[S_S1SQ], fro, 0.0, -1.0, 0, bad);
     return;
   }
   const double normA = sqrt(fro);
@@ -648,6 +710,16 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
         const int q = item < tiles[0] ? 0 : 1;
         const int t = item - (q ? tiles[0] : 0);
         GemmParams<T> gq = P->gp[ph][q][cur];
+        if (gq.vec & 1) {
+          gq.A = call.a;
+          gq.lda = call.lda;
+          gq.psa = call.psa;
+        }
+        if (gq.vec & 2) {
+          gq.B = call.a;
+          gq.ldb = call.lda;
+          gq.psb = call.psa;
+        }
         make_uniform(gq);
         double s_d = 0.0, s_x = 0.0;
         sm_block<T, MM>(gq, t / gq.tiles_n, t % gq.tiles_n, stage, red, s_d, s_x);
@@ -720,7 +792,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   if (normA == 0.0) ret_buf = 0;  // X_0 = 0
 
   // ---------------------------------------------------------------- result
-  if (P->xout_direct) {
+  if (call.xout_direct) {
     const SmView Xr = P->buf[1 + ret_buf];
     const T* x = static_cast<const T*>(Xr.p);
     const int lgw = lg_ceil(m), slots = (4 * n) << lgw;
@@ -734,19 +806,12 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
 #pragma unroll
       for (int u = 0; u < SM_SU; ++u) {
         const int e = e0 + u * gthreads, row = e >> lgw, c = e & ((1 << lgw) - 1), pl = plane_of(row, n);
-        if (e < slots && c < m) gstore(P->xout, pl * P->psx + (int64_t)(row - pl * n) * P->ldx + c, v[u]);
+        if (e < slots && c < m) gstore(call.xout, pl * call.psx + (int64_t)(row - pl * n) * call.ldx + c, v[u]);
       }
     }
   }
-  if (blockIdx.x == 0 && tid == 0) {
-    P->state[S_STATUS] = status;
-    P->state[S_ITERS] = j;
-    P->state[S_RETURNED] = ret_j;
-    P->state[S_REASON] = reason;
-    P->state[S_DXREL] = dx_rel;
-    P->state[S_E1] = e1_rel;
-    P->state[S_RETBUF] = ret_buf;
-  }
+  if (blockIdx.x == 0 && tid == 0)
+    sm_record(P, call.hres, status, j, ret_j, reason, alpha, P->state[S_S1SQ], fro, dx_rel, e1_rel, ret_buf, bad);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -918,8 +983,8 @@ struct SmMma<float> {
 };
 
 template <class T>
-void launch_small(const SmParams<T>* P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((small_solve_kernel<T, typename SmMma<T>::type>), dim3(grid), dim3(SM_THREADS), 0, s, P);
+void launch_small(const SmParams<T>* P, const SmCall<T>& call, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((small_solve_kernel<T, typename SmMma<T>::type>), dim3(grid), dim3(SM_THREADS), 0, s, P, call);
   QP_HIP(hipGetLastError());
 }
 
@@ -976,15 +1041,21 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
     return v;
   };
   P.buf[B_A] = view(A);
+  SmCall<T> call;
+  call.a = static_cast<const T*>(A.v.p);
+  call.lda = A.v.ld;
+  call.psa = A.v.ps;
+  P.buf[B_A].p = nullptr;  // per call
+  P.buf[B_A].ld = P.buf[B_A].ps = 0;
   P.buf[1] = view(ws_mat(c, "smX0", n, m, dtype));
   P.buf[2] = view(ws_mat(c, "smX1", n, m, dtype));
   for (int k = 0; k < 8; ++k) P.buf[B_SQ + k] = view(ws_mat(c, "smS" + std::to_string(k), sd, sd, dtype));
   P.buf[B_E] = view(ws_mat(c, "smE", m, n, dtype));
   const bool direct = Xout.dtype == dtype;
-  P.xout = static_cast<T*>(Xout.v.p);
-  P.ldx = Xout.v.ld;
-  P.psx = Xout.v.ps;
-  P.xout_direct = direct ? 1 : 0;
+  call.xout = static_cast<T*>(Xout.v.p);
+  call.ldx = Xout.v.ld;
+  call.psx = Xout.v.ps;
+  call.xout_direct = direct ? 1 : 0;
   P.prog = build_program(method, left, e1);
   P.m = (int)m;
   P.n = (int)n;
@@ -1026,17 +1097,31 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
     grid = std::max(grid, t);
   }
   grid = std::min(grid, SM_MAXG);
-  // the parameter block goes to device memory through the context's pinned staging area (the kernel reads
-  // it through a pointer: indexing it by phase and buffer does not copy it to private memory)
-  static_assert(sizeof(SmParams<T>) <= Ctx::kStageBytes, "staging area");
-  auto* Pd = static_cast<SmParams<T>*>(c.ws.get("smParams", sizeof(SmParams<T>)));
+  // The parameter block goes to device memory through the context's pinned staging area, and only when
+  // its bytes differ from the block already there (repeated solves of one shape reuse it; the input
+  // matrix, the output and the record pointer go by value).  No-allocation calls share their scratch with
+  // other contexts on the device, so they always copy.  The kernel writes its result record straight into
+  // the pinned scalars, whose status slot holds a marker until the record arrives; both pinned areas
+  // serve one call at a time (the call ends synchronised).
+  static_assert(((sizeof(SmParams<T>) + 15) / 16) * 16 <= Ctx::kStageBytes, "staging area");
+  static_assert(S_COUNT <= 48, "pinned scalars");
+  constexpr double kNoRecord = -1.0e300;
+  const size_t pbytes = ((sizeof(SmParams<T>) + 15) / 16) * 16;
+  auto* Pd = static_cast<SmParams<T>*>(c.ws.get("smParams", pbytes));
+  std::memset(c.hstage, 0, pbytes);
   std::memcpy(c.hstage, &P, sizeof(P));
-  QP_HIP(hipMemcpyAsync(Pd, c.hstage, sizeof(P), hipMemcpyHostToDevice, s));
-  launch_small<T>(Pd, grid, s);
-  double st[S_COUNT + 2];
-  QP_HIP(hipMemcpyAsync(c.hsc, P.state, sizeof(double) * (S_COUNT + 2), hipMemcpyDeviceToHost, s));
+  if (c.no_alloc || c.small_params_dev != Pd || c.small_params.size() != pbytes ||
+      std::memcmp(c.small_params.data(), c.hstage, pbytes) != 0) {
+    QP_HIP(hipMemcpyAsync(Pd, c.hstage, pbytes, hipMemcpyHostToDevice, s));
+    c.small_params.assign(static_cast<const unsigned char*>(c.hstage), static_cast<const unsigned char*>(c.hstage) + pbytes);
+    c.small_params_dev = c.no_alloc ? nullptr : Pd;
+  }
+  call.hres = c.hsc;
+  c.hsc[S_STATUS] = kNoRecord;
+  launch_small<T>(Pd, call, grid, s);
   QP_HIP(hipStreamSynchronize(s));
-  std::memcpy(st, c.hsc, sizeof(double) * (S_COUNT + 2));
+  double st[S_COUNT];
+  std::memcpy(st, c.hsc, sizeof(st));
   if (P.trace) {
     std::vector<unsigned long long> tr(kTrace);
     QP_HIP(hipMemcpy(tr.data(), P.trace, sizeof(unsigned long long) * kTrace, hipMemcpyDeviceToHost));
@@ -1045,11 +1130,14 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
       fprintf(stderr, " %.1f", (tr[i] - tr[0]) * 0.01);
     fprintf(stderr, "\n");
   }
-  unsigned int barw[4];
-  std::memcpy(barw, st + S_COUNT, sizeof(barw));
-  if (barw[2] != 0u) {
+  if (st[S_STATUS] == kNoRecord || st[S_GIVEUP] != 0.0) {
+    // every workgroup left at a barrier whose wait expired (the give-up flag is set): the barrier words are
+    // cleared before the next solve
+    unsigned int barw[4];
+    QP_HIP(hipMemcpy(barw, P.bar, sizeof(barw), hipMemcpyDeviceToHost));
     c.small_state = nullptr;
-    throw Error(QPINV_ETIMEOUT, "small solve: a grid barrier wait expired");
+    if (barw[2] != 0u || st[S_GIVEUP] != 0.0) throw Error(QPINV_ETIMEOUT, "small solve: a grid barrier wait expired");
+    throw Error(QPINV_EHIP, "small solve: the kernel left no result record");
   }
   const int status = (int)st[S_STATUS];
   inf.alpha_used = st[S_ALPHA];
