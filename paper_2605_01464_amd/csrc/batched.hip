@@ -1211,9 +1211,9 @@ __device__ __forceinline__ GemmParams<float> gemm_params(const DM& Aop, const DM
 template <class MM, int BM, int BN, int BK, int WM, int WN>
 __device__ __forceinline__ void tile_any(const GemmParams<float>& G, int t, float* smem, double& a0, double& a1) {
   if (G.vec)
-    gemm_tile<MM, BM, BN, BK, WM, WN, 128, kLoadVec>(G, t / G.tiles_n, t % G.tiles_n, smem, a0, a1);
+    gemm_tile<MM, BM, BN, BK, WM, WN, 128, kLoadVec, false, true>(G, t / G.tiles_n, t % G.tiles_n, smem, a0, a1);
   else
-    gemm_tile<MM, BM, BN, BK, WM, WN, 128, kLoadScalar>(G, t / G.tiles_n, t % G.tiles_n, smem, a0, a1);
+    gemm_tile<MM, BM, BN, BK, WM, WN, 128, kLoadScalar, false, true>(G, t / G.tiles_n, t % G.tiles_n, smem, a0, a1);
 }
 
 template <int BM, int BN>

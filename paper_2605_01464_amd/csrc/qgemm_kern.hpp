@@ -148,6 +148,28 @@ __device__ __forceinline__ void epilogue_inputs(const GemmParams<T>& P, int p, i
   }
 }
 
+// The same inputs with every load issued before any is used: all three loads go out without a branch on
+// the input count (an absent input re-reads a valid address: the first input's element, or the first
+// element of A) and the values are selected afterwards.  Under a branch each load is waited for inside
+// it, one memory latency per load; this form costs one latency for all of them, at the price of more
+// scalar registers (for latency-bound tiles: the batched and one-launch solvers).
+template <class T>
+__device__ __forceinline__ void epilogue_inputs_overlap(const GemmParams<T>& P, int p, int row, int col, T (&inv)[3]) {
+  const bool ok = row < P.M && col < P.N;
+  const int64_t r = row < P.M ? row : P.M - 1, c = col < P.N ? col : P.N - 1;
+  const bool any = P.nin > 0;
+  const T* const base = any ? P.in[0] : P.A;
+  const int64_t off0 = any ? p * P.psi[0] + r * P.ldi[0] + c : 0;
+  T x[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const bool use = u < P.nin;
+    x[u] = gload(use ? P.in[u] : base, use ? p * P.psi[u] + r * P.ldi[u] + c : off0);
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) inv[u] = ok && u < P.nin ? x[u] : T(0);
+}
+
 // out_t = a_t v + sum_u b_tu in_u + g_t I for plane p at one element, plus the reduction terms; inv
 // holds the element's inputs (epilogue_inputs).
 template <class T>
@@ -238,7 +260,9 @@ enum : int { kLoadScalar = 0, kLoadVec = 1, kLoadAligned = 2 };
 //   DB:      two LDS staging buffers (`smem` holds 2 C::SMEM elements): the next K step is written to
 //            one while the MFMAs read the other, one barrier per K step; otherwise one buffer
 //            (C::SMEM elements) and two barriers per K step.
-template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, int LM = kLoadScalar, bool DB = false>
+//   OVL:     the epilogue's inputs loaded by epilogue_inputs_overlap (all loads in flight together).
+template <class MM, int BM, int BN, int BK, int WM, int WN, int FLUSH, int LM = kLoadScalar, bool DB = false,
+          bool OVL = false>
 __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, int tm, int tn, typename MM::T* smem,
                                           double& s_d, double& s_x) {
   using C = GemmCfg<MM, BM, BN, BK, WM, WN>;
@@ -492,7 +516,12 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
         if constexpr (MM::NR <= 4) {
           T inv[MM::NR][3];
 #pragma unroll
-          for (int r = 0; r < MM::NR; ++r) epilogue_inputs(P, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
+          for (int r = 0; r < MM::NR; ++r) {
+            if constexpr (OVL)
+              epilogue_inputs_overlap(P, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
+            else
+              epilogue_inputs(P, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
+          }
 #pragma unroll
           for (int r = 0; r < MM::NR; ++r)
             epilogue_apply(P, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), value(p, i, j, r), inv[r], s_d, s_x);
@@ -507,7 +536,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams<typename MM::T>& P, i
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
               const int e = lane + 64 * (k0 + k);
-              epilogue_inputs(P, p, rb + e / MM::BLK, cb + e % MM::BLK, inv[k]);
+              if constexpr (OVL)
+                epilogue_inputs_overlap(P, p, rb + e / MM::BLK, cb + e % MM::BLK, inv[k]);
+              else
+                epilogue_inputs(P, p, rb + e / MM::BLK, cb + e % MM::BLK, inv[k]);
             }
 #pragma unroll
             for (int k = 0; k < NG; ++k) {

@@ -314,27 +314,6 @@ GemmParams<T> resolve_product(const SmParams<T>* P, const SmProd& d, int cur) {
   return G;
 }
 
-// The epilogue's inputs at one element of plane p.  All three loads are issued unconditionally (an absent
-// input, or every input when there is none, re-reads a valid address: the first input's element, or the
-// first element of A) and the values are selected afterwards: a load under a branch on the input count
-// would be waited for inside the branch, one memory latency per load instead of one for all of them.
-template <class T>
-__device__ __forceinline__ void sm_inputs(const GemmParams<T>& G, int p, int row, int col, T (&inv)[3]) {
-  const bool ok = row < G.M && col < G.N;
-  const int64_t r = row < G.M ? row : G.M - 1, c = col < G.N ? col : G.N - 1;
-  const bool any = G.nin > 0;
-  const T* const base = any ? G.in[0] : G.A;
-  const int64_t off0 = any ? p * G.psi[0] + r * G.ldi[0] + c : 0;
-  T x[3];
-#pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const bool use = u < G.nin;
-    x[u] = gload(use ? G.in[u] : base, use ? p * G.psi[u] + r * G.ldi[u] + c : off0);
-  }
-#pragma unroll
-  for (int u = 0; u < 3; ++u) inv[u] = ok && u < G.nin ? x[u] : T(0);
-}
-
 // One 16 x 16 output block (all four planes) of C = A B with the epilogue.  The block's operands are staged
 // in LDS SM_KB deep in k, every thread loading eight elements of each (one memory latency per round): A as
 // [plane][row][k], B as [plane][k][column], both padded by one element; the k slots beyond the operands hold
@@ -363,7 +342,7 @@ __device__ void sm_block(const GemmParams<T>& G, int tm, int tn, T* stage, typen
   T inv[4][3];
   if (ks == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sm_inputs(G, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
+    for (int r = 0; r < 4; ++r) epilogue_inputs_overlap(G, p, rb + MM::crow(lane, r), cb + MM::ccol(lane), inv[r]);
   }
   constexpr int NU = 4 * 16 * SM_KB / SM_THREADS;  // staged elements of each operand per thread
   static_assert(NU * SM_THREADS == 4 * 16 * SM_KB && SM_KB == 64, "staging map: 4 planes x 16 x 64 slots");
