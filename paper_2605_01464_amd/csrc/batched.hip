@@ -558,19 +558,31 @@ __device__ __forceinline__ bool setup_matrix(int scaling, int power_steps, unsig
     alpha = 1.0 / lam;
   }
   info.alpha = alpha;
-  // X_0 = alpha A^H, transposed through 32 x 32 LDS tiles of all four planes (coalesced reads and writes)
+  // X_0 = alpha A^H, transposed through 32 x 32 LDS tiles of all four planes (coalesced reads and writes).
+  // A thread's rows of a tile (up to XR of them, all four planes) are loaded before any is stored, one
+  // memory latency per tile; addresses are clamped into A and the values outside it replaced by zeros.
+  constexpr int XR = 4;
   float* tile = lds;  // [4][32][33]
   const int tr = tid >> 5, tc = tid & 31, rstep = nthr >> 5;
   for (int ib = 0; ib < m; ib += 32)
     for (int jb = 0; jb < n; jb += 32) {
-      for (int r = tr; r < 32; r += rstep) {
-        const int i = ib + r, j = jb + tc;
-        const bool ok = i < m && j < n;
-        const int64_t o = (int64_t)(i < m ? i : m - 1) * A.ld + (j < n ? j : n - 1);
+      for (int r0 = tr; r0 < 32; r0 += XR * rstep) {
+        float x[XR][4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const float x = gload(A.p, p * A.ps + o);
-          tile[(p * 32 + r) * 33 + tc] = ok ? x : 0.f;
+        for (int u = 0; u < XR; ++u) {
+          const int i = ib + r0 + u * rstep, j = jb + tc;
+          const int64_t o = (int64_t)(i < m ? i : m - 1) * A.ld + (j < n ? j : n - 1);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) x[u][p] = gload(A.p, p * A.ps + o);
+        }
+#pragma unroll
+        for (int u = 0; u < XR; ++u) {
+          const int r = r0 + u * rstep, i = ib + r, j = jb + tc;
+          if (r < 32) {
+            const bool ok = i < m && j < n;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) tile[(p * 32 + r) * 33 + tc] = ok ? x[u][p] : 0.f;
+          }
         }
       }
       __syncthreads();
