@@ -154,7 +154,11 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
  * index used for every product of that precision, -1 = tuned or heuristic choice), batched_cfg
  * (configuration of qpinv_solve_batched, -1 = tuned or default), batched_dynamic (phase-synchronous
  * batched form: 1 (default) workgroups claim work items from a counter, 0 workgroup g takes items
- * g, g + G, ...; the results are the same), verbose (0/1), penrose_finish (projection of the returned
+ * g, g + G, ...; the results are the same), small_path (0/1, default 1: single FP64 or FP32 solves of
+ * NS, QSAI or QHPI19 with at most 128 rows and columns run as one persistent launch), fault_small_giveup
+ * (0/1, a test hook: the one-launch solve's grid-barrier give-up flag is raised before its launch, so every
+ * workgroup leaves at its first barrier and the call returns QPINV_ETIMEOUT without waiting; the next
+ * solve clears the flag), verbose (0/1), penrose_finish (projection of the returned
  * iterate in FP64, Section 2's Penrose conditions: 0 (default) none; 1 X <- X A X (condition (b)) after the
  * last update; 2 X <- (X A)^H X (A X)^H, which A^dagger leaves unchanged by conditions (b)-(d) and whose
  * rows lie in range(A^H) and columns in range(A), the invariants of every exact iterate (Proposition 3.1):

@@ -77,6 +77,9 @@ void set_option(qp::Ctx& c, const std::string& key, double v) {
   } else if (key == "small_path") {
     need(v == 0 || v == 1);
     c.opt.small_path = (int)v;
+  } else if (key == "fault_small_giveup") {
+    need(v == 0 || v == 1);
+    c.opt.fault_small_giveup = (int)v;
   } else if (key == "penrose_finish") {
     need(v == 0 || v == 1 || v == 2);
     c.opt.penrose_finish = (int)v;

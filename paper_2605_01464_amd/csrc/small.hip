@@ -1063,6 +1063,11 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
     zero_doubles(P.state, S_COUNT + 2, s);  // the record and the barrier words (3 uint32 in 2 doubles)
     c.small_state = c.no_alloc ? nullptr : P.state;
   }
+  if (c.opt.fault_small_giveup) {
+    // test hook: every workgroup sees the flag at its first barrier and leaves (no wait runs out)
+    static const unsigned int kRaised = 1u;
+    QP_HIP(hipMemcpyAsync(P.bar + 2, &kRaised, sizeof(kRaised), hipMemcpyHostToDevice, s));
+  }
   // grid: the output blocks of the largest phase
   int grid = 1;
   for (int ph = 0; ph < P.prog.nphase; ++ph) {

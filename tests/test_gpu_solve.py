@@ -335,6 +335,29 @@ def test_small_path_fp32(qctx, method, order):
     assert rel_fro(to_np(X), ro.X) <= 2e-5 and rel_fro(to_np(Xr), ro.X) <= 2e-5
 
 
+def test_small_path_barrier_giveup_reports_timeout(qctx):
+    """A grid-barrier wait of the one-launch path that gives up: forced from the host (the give-up flag
+    raised before the launch), every workgroup leaves at its first barrier and no result record is written;
+    the call reports ETIMEOUT, and the next solve on the same context (which clears the barrier words)
+    matches the oracle."""
+    import paper_2605_01464_amd as q
+
+    A = qsynth.c1_instance(5)
+    Ad = to_dev(A, "f64")
+    kw = dict(scaling="power", tol=1e-12, stop="e1_rel", precision="f64")
+    qctx.set("fault_small_giveup", 1)
+    try:
+        _, info = q.solve(qctx, Ad, "qhpi19", check=False, **kw)
+    finally:
+        qctx.set("fault_small_giveup", 0)
+    assert info["status"] == q.ETIMEOUT
+    X, info = q.solve(qctx, Ad, "qhpi19", **kw)
+    assert info["status"] == q.OK and info["reason"] == "tol"
+    ro = M.solve(A, "qhpi19", alpha=info["alpha_used"], tol=1e-12, stop="e1_rel", side="left")
+    assert info["iters"] == ro.iters
+    assert rel_fro(to_np(X), ro.X) <= 1e-12
+
+
 def test_small_path_error_paths(qctx):
     """The one-launch path's statuses: divergence for alpha outside Theorem 1's interval, max_iter, a
     non-finite input, a zero matrix (pseudoinverse 0), an FP32 input solved in FP64 (converted first)."""
