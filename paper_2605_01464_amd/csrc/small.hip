@@ -97,12 +97,14 @@ struct SmCall {
   int64_t ldx, psx;
   int xout_direct;
   double* hres;
+  unsigned int bar_base;  // the barrier's arrival count when the solve starts
 };
 
-// result record, doubles (S_GIVEUP: the barrier's give-up flag as workgroup 0 saw it at the end)
+// result record, doubles (S_GIVEUP: the barrier's give-up flag as workgroup 0 saw it at the end; S_BARS: the
+// grid barriers of the solve, which advance the arrival counter by S_BARS x grid)
 enum : int {
   S_STATUS = 0, S_ITERS, S_RETURNED, S_REASON, S_ALPHA, S_S1SQ, S_NORMA2, S_DXREL, S_E1, S_RETBUF, S_NONFINITE,
-  S_GIVEUP, S_COUNT
+  S_GIVEUP, S_BARS, S_COUNT
 };
 
 constexpr int SM_SU = 8;  // loads in flight per thread in the element-wise passes
@@ -168,22 +170,23 @@ __device__ __forceinline__ double qsign(int p, int q) {
   return (p == 0 || p == 1) ? -1.0 : 1.0;
 }
 
-// Grid barrier (counter and generation in device memory); false once any workgroup has abandoned a wait.
-__device__ bool sm_sync(unsigned int* bar, unsigned int nblocks) {
+// Grid barrier on one arrival counter that only grows during a solve (device memory): barrier k of the
+// solve is complete when the counter reaches base + k nblocks (unsigned differences, so it may wrap), so
+// the last to arrive has nothing more to do than its own arrival.  Every arrival releases the workgroup's
+// writes and acquires those of the arrivals before it (read-modify-writes on one counter form a release
+// sequence); waiters poll relaxed and acquire once the count is reached.  False once any workgroup has
+// abandoned a wait (bar[2], the give-up flag).
+__device__ bool sm_sync(unsigned int* bar, unsigned int nblocks, unsigned int base, unsigned int& k) {
   __shared__ int s_ok;
   __syncthreads();
+  ++k;
   if (threadIdx.x == 0) {
     int ok = 1;
-    // the generation is read before arriving; the arrival releases this workgroup's writes (and, for the
-    // last to arrive, acquires everyone's); waiters poll relaxed and acquire once when the generation moves
-    const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const unsigned int target = k * nblocks;
+    const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u - base;
+    if (arrived < target) {
       long long spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < target) {
         if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > SM_SPIN_MAX) {
           __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
@@ -506,7 +509,8 @@ __device__ double sm_power(AP a, int64_t lda, int64_t psa, int m, int n, int ste
 // The result record, written into pinned host memory by one thread at the end of the solve.
 template <class T>
 __device__ void sm_record(const SmParams<T>* P, double* hres, int status, int iters, int returned, int reason, double alpha,
-                          double s1sq, double fro, double dx_rel, double e1_rel, int ret_buf, double bad) {
+                          double s1sq, double fro, double dx_rel, double e1_rel, int ret_buf, double bad,
+                          unsigned int bars) {
   double r[S_COUNT];
   r[S_STATUS] = status;
   r[S_ITERS] = iters;
@@ -520,6 +524,7 @@ __device__ void sm_record(const SmParams<T>* P, double* hres, int status, int it
   r[S_RETBUF] = ret_buf;
   r[S_NONFINITE] = bad;
   r[S_GIVEUP] = __hip_atomic_load(&P->bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  r[S_BARS] = bars;
 #pragma unroll
   for (int k = 0; k < S_COUNT; ++k) gstore(hres, k, r[k]);
 }
@@ -562,6 +567,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   const SmParams<T>* const P = reinterpret_cast<const SmParams<T>*>(pcopy);
   const int tid = threadIdx.x;
   const unsigned int G = gridDim.x;
+  unsigned int nbar = 0;  // grid barriers passed in this solve
   int nstamp = 0;
   auto stamp = [&]() {
     if (P->trace && blockIdx.x == 0 && tid == 0 && nstamp < P->trace_cap) P->trace[nstamp] = wall_clock64();
@@ -631,14 +637,15 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
       P->state[S_S1SQ] = s1sq;
     }
   }
-  if (!sm_sync(P->bar, G)) return;
+  if (!sm_sync(P->bar, G, call.bar_base, nbar)) return;
   stamp();
   const double bad = __hip_atomic_load(&P->state[S_NONFINITE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double fro = __hip_atomic_load(&P->state[S_NORMA2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double alpha = __hip_atomic_load(&P->state[S_ALPHA], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (bad != 0.0) {
     if (blockIdx.x == 0 && tid == 0)
-      sm_record(P, call.hres, QPINV_ENONFINITE, 0, 0, QPINV_REASON_TOL, alpha, P->state[S_S1SQ], fro, 0.0, -1.0, 0, bad);
+      sm_record(P, call.hres, QPINV_ENONFINITE, 0, 0, QPINV_REASON_TOL, alpha, P->state[S_S1SQ], fro, 0.0, -1.0, 0, bad,
+                nbar);
     return;
   }
   const double normA = sqrt(fro);
@@ -665,7 +672,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
       }
     }
   }
-  if (!sm_sync(P->bar, G)) return;
+  if (!sm_sync(P->bar, G, call.bar_base, nbar)) return;
   stamp();
 
   // ---------------------------------------------------------------- updates
@@ -713,7 +720,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
           }
         }
       }
-      if (!sm_sync(P->bar, G)) return;
+      if (!sm_sync(P->bar, G, call.bar_base, nbar)) return;
   stamp();
       if (e1 && ph == P->prog.e1_phase && j >= 1) {
         // ||A X_j A - A||_F / ||A||_F from the tiles of the E1 product, summed in tile order
@@ -790,7 +797,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
     }
   }
   if (blockIdx.x == 0 && tid == 0)
-    sm_record(P, call.hres, status, j, ret_j, reason, alpha, P->state[S_S1SQ], fro, dx_rel, e1_rel, ret_buf, bad);
+    sm_record(P, call.hres, status, j, ret_j, reason, alpha, P->state[S_S1SQ], fro, dx_rel, e1_rel, ret_buf, bad, nbar);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1057,11 +1064,13 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
     P.trace = static_cast<unsigned long long*>(c.ws.get("smTrace", sizeof(unsigned long long) * kTrace));
     P.trace_cap = kTrace;
   }
-  // The barrier leaves its arrival count at 0 and its give-up flag clear, so the words need clearing only
-  // in fresh memory (a new buffer, or the no-allocation scratch, shared by other calls) or after a timeout.
+  // The barrier's arrival counter keeps the count the previous solve left (passed as the next one's base)
+  // and its give-up flag stays clear, so the words need clearing only in fresh memory (a new buffer, or
+  // the no-allocation scratch, shared by other calls) or after a timeout.
   if (c.no_alloc || c.small_state != P.state) {
-    zero_doubles(P.state, S_COUNT + 2, s);  // the record and the barrier words (3 uint32 in 2 doubles)
+    zero_doubles(P.state, S_COUNT + 2, s);  // the broadcast slots and the barrier words (3 uint32 in 2 doubles)
     c.small_state = c.no_alloc ? nullptr : P.state;
+    c.small_bar_base = 0;
   }
   if (c.opt.fault_small_giveup) {
     // test hook: every workgroup sees the flag at its first barrier and leaves (no wait runs out)
@@ -1101,6 +1110,7 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
     c.small_params_dev = c.no_alloc ? nullptr : Pd;
   }
   call.hres = c.hsc;
+  call.bar_base = c.small_bar_base;
   c.hsc[S_STATUS] = kNoRecord;
   launch_small<T>(Pd, call, grid, s);
   QP_HIP(hipStreamSynchronize(s));
@@ -1123,6 +1133,7 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
     if (barw[2] != 0u || st[S_GIVEUP] != 0.0) throw Error(QPINV_ETIMEOUT, "small solve: a grid barrier wait expired");
     throw Error(QPINV_EHIP, "small solve: the kernel left no result record");
   }
+  c.small_bar_base = call.bar_base + (unsigned int)st[S_BARS] * (unsigned int)grid;
   const int status = (int)st[S_STATUS];
   inf.alpha_used = st[S_ALPHA];
   if (scaling == QPINV_ALPHA_POWER) {

@@ -71,7 +71,8 @@ struct Ctx {
   std::map<std::vector<int64_t>, int> batched_tuned;  // batch signature -> tile configuration
   bool no_alloc = false;  // allocation-free call in progress: no autotuning, no product timing, no growth
   bool split_f32 = false;  // a ladder solve in progress computes its FP32-storage products as P_BF16X3
-  void* small_state = nullptr;  // the small solve's record whose barrier words are known to be clear
+  void* small_state = nullptr;  // the small solve's record whose barrier words hold a known count and a clear flag
+  unsigned int small_bar_base = 0;  // the arrival count those barrier words hold
   void* small_params_dev = nullptr;         // the small solve's parameter block in device memory, and
   std::vector<unsigned char> small_params;  // the bytes it holds (copied again only when they change)
   double flops = 0.0;  // running count of algorithmic product flops
