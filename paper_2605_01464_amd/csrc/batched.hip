@@ -934,33 +934,31 @@ constexpr long long SPIN_MAX = 1ll << 22;  // barrier polls before the wait is a
 
 // Grid barrier; returns false once any workgroup has abandoned a wait.  Two levels: a workgroup arrives on
 // its group's counter (group = blockIdx mod BAR_NG, the XCD it was dealt to; counters on separate 256-byte
-// lines), the group's last arrival arrives on the global counter, and the last of those moves the generation.
-// One counter taking every arrival serialises them at the memory side (measured 57 us per barrier for 512
-// workgroups, 25 us with the groups; 32 groups, or sleeping between polls, measured no faster).  Arrivals
-// release this workgroup's writes; waiters poll the generation relaxed and acquire once when it moves.
+// lines), the group's last arrival arrives on the global counter.  One counter taking every arrival
+// serialises them at the memory side (measured 57 us per barrier for 512 workgroups, 25 us with the
+// groups; 32 groups, or sleeping between polls, measured no faster).  The counters only grow during a solve
+// (cleared before it): barrier k (the k-th of the solve, counted by every workgroup in `k`) is complete
+// when group g's counter reaches k gsize and the global one k ngroups, so the last arrivals have nothing
+// more to do than arrive.  Arrivals release this workgroup's writes and acquire those of the arrivals
+// before them on the same counter; waiters poll the global counter relaxed and acquire once it is reached.
 constexpr int BAR_NG = 8, BAR_GROUP = 64, BAR_WORDS = BAR_GROUP + 64 * BAR_NG;
-__device__ bool grid_sync(unsigned int* bar, unsigned int nblocks) {
+__device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, unsigned int& k) {
   __shared__ int s_ok;
   __syncthreads();
+  ++k;
   if (threadIdx.x == 0) {
     int ok = 1;
     const unsigned int g = blockIdx.x % BAR_NG;
     const unsigned int gsize = nblocks / BAR_NG + ((nblocks % BAR_NG) > g ? 1u : 0u);
     const unsigned int ngroups = nblocks < (unsigned int)BAR_NG ? nblocks : (unsigned int)BAR_NG;
-    const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int target = k * ngroups;
     bool last = false;
     unsigned int* gw = &bar[BAR_GROUP + 64 * g];
-    if (__hip_atomic_fetch_add(gw, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == gsize) {
-      __hip_atomic_store(gw, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == ngroups) {
-        __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        last = true;
-      }
-    }
+    if (__hip_atomic_fetch_add(gw, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == k * gsize)
+      last = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == target;
     if (!last) {
       long long spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > SPIN_MAX) {
           __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
@@ -1279,6 +1277,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const unsigned int G = gridDim.x;
+  unsigned int nbar = 0;  // grid barriers passed in this solve
   const int np = num_phases(P.method);
   unsigned long long* const trace = (blockIdx.x == 0 && tid == 0) ? P.trace : nullptr;
   const int trace_cap = P.trace_cap < kTraceSetup ? P.trace_cap : kTraceSetup;
@@ -1345,7 +1344,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
     }
     __syncthreads();
   }
-  if (!grid_sync(P.bar, G)) return;
+  if (!grid_sync(P.bar, G, nbar)) return;
   QP_STAMP();
 
   // ---------------------------------------------------------------- updates
@@ -1690,7 +1689,7 @@ __global__ void __launch_bounds__(64 * WM * WN, PER_CU) batched_sync_kernel(SPar
         if (kTraceBusy + (int)blockIdx.x < kTraceCap) P.trace[kTraceBusy + blockIdx.x] = busy;
       }
       if (flowu && ph <= np) continue;
-      if (!grid_sync(P.bar, G)) return;
+      if (!grid_sync(P.bar, G, nbar)) return;
       QP_STAMP();
     }
   }
