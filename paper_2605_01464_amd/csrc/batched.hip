@@ -939,8 +939,10 @@ constexpr long long SPIN_MAX = 1ll << 22;  // barrier polls before the wait is a
 // groups; 32 groups, or sleeping between polls, measured no faster).  The counters only grow during a solve
 // (cleared before it): barrier k (the k-th of the solve, counted by every workgroup in `k`) is complete
 // when group g's counter reaches k gsize and the global one k ngroups, so the last arrivals have nothing
-// more to do than arrive.  Arrivals release this workgroup's writes and acquire those of the arrivals
-// before them on the same counter; waiters poll the global counter relaxed and acquire once it is reached.
+// more to do than arrive.  Arrivals release this workgroup's writes; a group's last arrival acquires its
+// group's (their adds form a release sequence) before it releases them on the global counter; every
+// workgroup acquires once the global count is reached (its own add or a relaxed poll).  The give-up flag
+// is read by every poll: a workgroup whose wait needs no poll learns of a give-up at its next wait.
 constexpr int BAR_NG = 8, BAR_GROUP = 64, BAR_WORDS = BAR_GROUP + 64 * BAR_NG;
 __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, unsigned int& k) {
   __shared__ int s_ok;
@@ -954,8 +956,10 @@ __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, unsigned int&
     const unsigned int target = k * ngroups;
     bool last = false;
     unsigned int* gw = &bar[BAR_GROUP + 64 * g];
-    if (__hip_atomic_fetch_add(gw, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == k * gsize)
-      last = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == target;
+    if (__hip_atomic_fetch_add(gw, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u == k * gsize) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      last = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u == target;
+    }
     if (!last) {
       long long spins = 0;
       while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -965,9 +969,8 @@ __device__ bool grid_sync(unsigned int* bar, unsigned int nblocks, unsigned int&
           break;
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ok = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();

@@ -173,9 +173,10 @@ __device__ __forceinline__ double qsign(int p, int q) {
 // Grid barrier on one arrival counter that only grows during a solve (device memory): barrier k of the
 // solve is complete when the counter reaches base + k nblocks (unsigned differences, so it may wrap), so
 // the last to arrive has nothing more to do than its own arrival.  Every arrival releases the workgroup's
-// writes and acquires those of the arrivals before it (read-modify-writes on one counter form a release
-// sequence); waiters poll relaxed and acquire once the count is reached.  False once any workgroup has
-// abandoned a wait (bar[2], the give-up flag).
+// writes; the read-modify-writes on the counter form a release sequence, so one acquire after the count is
+// reached (by the last arrival's own add or by a relaxed poll) sees every workgroup's writes.  False once
+// any workgroup has abandoned a wait (bar[2], the give-up flag, read by every poll: a workgroup whose wait
+// needs no poll learns of a give-up at its next wait, and workgroup 0 reports the flag in the record).
 __device__ bool sm_sync(unsigned int* bar, unsigned int nblocks, unsigned int base, unsigned int& k) {
   __shared__ int s_ok;
   __syncthreads();
@@ -183,7 +184,7 @@ __device__ bool sm_sync(unsigned int* bar, unsigned int nblocks, unsigned int ba
   if (threadIdx.x == 0) {
     int ok = 1;
     const unsigned int target = k * nblocks;
-    const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u - base;
+    const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u - base;
     if (arrived < target) {
       long long spins = 0;
       while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base < target) {
@@ -193,9 +194,8 @@ __device__ bool sm_sync(unsigned int* bar, unsigned int nblocks, unsigned int ba
           break;
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ok = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
