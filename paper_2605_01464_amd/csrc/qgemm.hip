@@ -219,6 +219,8 @@ static const std::vector<F64Entry>& f64_table() {
       {{2, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16"}, launch_cfg<MM16D, 64, 64, 8, 4, 4, 0, false, 0>},
       {{3, 32, 32, 16, 256, "f64_32x32x16_w2x2_mfma16_db"}, launch_cfg<MM16D, 32, 32, 16, 2, 2, 0, true, 0>},
       {{4, 64, 64, 8, 1024, "f64_64x64x8_w4x4_mfma16_db"}, launch_cfg<MM16D, 64, 64, 8, 4, 4, 0, true, 0>},
+      {{5, 128, 64, 8, 512, "f64_128x64x8_w4x2_mfma16_db"}, launch_cfg<MM16D, 128, 64, 8, 4, 2, 0, true, 0>},
+      {{6, 64, 128, 8, 512, "f64_64x128x8_w2x4_mfma16_db"}, launch_cfg<MM16D, 64, 128, 8, 2, 4, 0, true, 0>},
   };
   return t;
 }
@@ -247,13 +249,15 @@ int64_t qgemm_blocks(Prec p, int cfg, int64_t M, int64_t N) {
 }
 
 // Measured on MI355X: the 64 x 64 double-buffered tiles win once there are >= 4 of them per compute unit,
-// the 32 x 32 ones below that (fewer tiles leave compute units idle in the last wave).  BF16 from 1024 tiles
+// the 32 x 32 ones below that (fewer tiles leave compute units idle in the last wave); for FP64 the 64 x 128
+// double-buffered tiles (8 waves of 32 x 32, twice the MFMA work per K-step barrier) beat 64 x 64 there
+// (4096^3: 30.8 vs 31.3 ms; 128 x 64 with the same waves 36.6 ms).  BF16 from 1024 tiles
 // of 64 x 64: the staged form with its operand tiles loaded straight into LDS; split BF16: 128 x 128 tiles
 // from 256 of them (one workgroup of 16 waves per CU), 64 x 64 below.
 int default_config(Prec p, int64_t M, int64_t N, int64_t K) {
   (void)K;
   const int64_t b64 = ((M + 63) / 64) * ((N + 63) / 64);
-  if (p == P_F64) return b64 >= 1024 ? 4 : 1;
+  if (p == P_F64) return b64 >= 1024 ? 6 : 1;
   if (p == P_BF16) return b64 >= 1024 ? 11 : b64 >= 256 ? 0 : 1;
   if (p == P_BF16X3) return ((M + 127) / 128) * ((N + 127) / 128) >= 256 ? 4 : 3;
   return b64 >= 1024 ? 5 : 6;

@@ -83,11 +83,12 @@ def test_product_configuration_tables_without_gpu():
     assert names[0] == "bf16_64x64x32_w2x2_mfma16x16x32_db_occ2"
     assert names[1] == "bf16_32x32x32_w2x2_mfma16x16x32"
     assert len(set(names)) == len(names) and all(nm.startswith("bf16_") for nm in names)
-    # FP32 / FP64: 5 / 4 (64 x 64 double-buffered tiles) from 1024 tiles of 64 x 64, 6 / 1 below
+    # defaults from 1024 tiles of 64 x 64: FP32 5 (64 x 64 double-buffered), FP64 6 (64 x 128 double-buffered);
+    # below that FP32 6, FP64 1
     f32 = [q.qpinv_tile_config_name(q.GEMM_PREC["f32"], c) for c in (5, 6)]
-    f64 = [q.qpinv_tile_config_name(q.GEMM_PREC["f64"], c) for c in (4, 1)]
+    f64 = [q.qpinv_tile_config_name(q.GEMM_PREC["f64"], c) for c in (6, 1)]
     assert f32 == ["f32_64x64x16_w2x2_mfma32_db", "f32_32x32x16_w2x2_mfma16_db"]
-    assert f64 == ["f64_64x64x8_w4x4_mfma16_db", "f64_32x32x16_w2x2_mfma16"]
+    assert f64 == ["f64_64x128x8_w2x4_mfma16_db", "f64_32x32x16_w2x2_mfma16"]
 
 
 # ------------------------------------------------------------------ stop-rule controller (host logic)
