@@ -90,7 +90,7 @@ size_t noalloc_workspace_bound(int64_t m, int64_t n, int side, int precision, in
   if (finish) b += 8 * mat_bytes(sd, sd, QPINV_F32) + 2 * mat_bytes(sd, sd, QPINV_F64) + 2 * mat_bytes(n, m, QPINV_F32);
   // the Penrose projection (FP64 copy, X A, A X, their adjoints, the first product, output, the update after it)
   b += 4 * mat_bytes(n, m, QPINV_F64) + 2 * mat_bytes(n, n, QPINV_F64) + 2 * mat_bytes(m, m, QPINV_F64);
-  b += 32768;  // the one-launch path's parameter block (<= 16 KB), per-item sums (8 KB) and result record
+  b += 32768;  // the one-launch path's parameter block (<= 20 KB), per-item sums (8 KB) and result record
   b += mat_bytes(n, m, out_dtype);
   b += align256(8 * (size_t)std::max(norms_work_doubles(m, n), norms_work_doubles(n, m)));
   b += align256(8 * (size_t)std::max(power_work_doubles(m, n), power_work_doubles(sd, sd)));

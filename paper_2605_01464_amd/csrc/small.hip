@@ -40,9 +40,11 @@ constexpr int SM_THREADS = 256 * SM_KSPLIT;
 constexpr int SM_MAXG = 128;
 constexpr long long SM_SPIN_MAX = 1ll << 22;  // barrier polls before the wait is abandoned
 
-// buffers of the solve: A, the two iterates (current / next resolved per update), 8 side-by-side, and the
-// E1 product A R (left) or R A (right), m x n
-enum : int { B_A = 0, B_XC = 1, B_XN = 2, B_SQ = 3, B_E = 11, B_N = 12 };
+constexpr int SM_MAXPH = 24;  // phases of one update (QRAPID(N) takes 6 + 2N on the left side, 8 + 2N on the right)
+
+// buffers of the solve: A, the two iterates (current / next resolved per update), 8 side-by-side, the E1
+// product A R (left) or R A (right), m x n, and 3 of the iterate's shape, n x m (QRAPID's U, V and nested terms)
+enum : int { B_A = 0, B_XC = 1, B_XN = 2, B_SQ = 3, B_E = 11, B_XB = 12, B_N = 15 };
 
 struct SmView {
   void* p;
@@ -58,17 +60,31 @@ struct SmProd {
   double ca[3], cg[3], cb[3][3];
 };
 
+// the update's products as the host builds them, phase by phase (products of one phase are independent)
 struct SmProgram {
   int nphase;        // phases of one update; the last forms X_{j+1}
   int e1_phase;      // phase whose second product is the E1 product (-1: none)
-  int nprod[8];
-  SmProd prod[8][2];
+  int nprod[SM_MAXPH];
+  SmProd prod[SM_MAXPH][2];
+};
+
+// One product of the program with its buffers resolved.  The iterate buffers swap roles every update and the
+// input matrix comes per call, so an operand or epilogue slot that names one of them is left for the kernel
+// to bind: `sub` holds 2 bits per slot (A, B, out 0..2, in 0..2 from the low bits up): 0 bound here, 1 the
+// current iterate, 2 the next iterate, 3 the input matrix (its strides come per call too).  Both iterate
+// buffers have the same strides, which the table holds.
+template <class T>
+struct SmItem {
+  GemmParams<T> g;
+  int sub;
 };
 
 template <class T>
 struct SmParams {
   SmView buf[B_N];       // B_XC / B_XN hold iterate buffers 0 / 1; B_A's pointer and strides come per call
-  SmProgram prog;
+  int nphase, e1_phase;  // the program's shape (as SmProgram) and each product's reduction kind (SmProd)
+  int nprod[SM_MAXPH];
+  int kind[SM_MAXPH][2];
   int m, n;
   int scaling, power_steps;
   unsigned long long seed;
@@ -80,11 +96,12 @@ struct SmParams {
   unsigned int* bar;     // [0] arrivals, [1] generation, [2] give-up flag
   unsigned long long* trace;  // optional (option verbose): workgroup 0 stamps wall_clock64() after each barrier
   int trace_cap;
-  // every product of the program with its buffers resolved, per phase, product and current iterate buffer
-  // (built on the host, read from LDS by each phase with independent loads); an operand that is the input
-  // matrix is marked in `vec` (bit 0: A, bit 1: B) and filled in per call
-  GemmParams<T> gp[8][2][2];
+  // every product of the program, per phase and product (built on the host, read from LDS by each phase with
+  // independent loads).  Last: the host uploads, and the kernel copies, only the program's phases of it.
+  SmItem<T> gp[SM_MAXPH][2];
 };
+// the no-allocation reservation counts 20 KB for the block (noalloc.hip)
+static_assert(sizeof(SmParams<double>) <= 20 * 1024 && sizeof(SmParams<float>) <= 20 * 1024, "parameter block size");
 
 // What changes from one call to the next, passed by value: the input matrix, the caller's X (n x m, written
 // directly when xout_direct) and the result record in pinned host memory (S_COUNT doubles, written by
@@ -98,6 +115,7 @@ struct SmCall {
   int xout_direct;
   double* hres;
   unsigned int bar_base;  // the barrier's arrival count when the solve starts
+  int pwords;             // 16-byte words of the parameter block in use (up to the program's last phase)
 };
 
 // result record, doubles (S_GIVEUP: the barrier's give-up flag as workgroup 0 saw it at the end; S_BARS: the
@@ -214,11 +232,11 @@ __device__ __forceinline__ double sm_sum(double v, double* sh) {
   return t;
 }
 
+// A buffer of the program for the host: the iterate buffers by their first copy (both have its shape and
+// strides), every other buffer as it is.
 template <class T>
-__host__ __device__ __forceinline__ SmView resolve(const SmParams<T>* P, int b, int cur) {
-  if (b == B_XC) return P->buf[1 + cur];
-  if (b == B_XN) return P->buf[2 - cur];
-  return P->buf[b];
+SmView view_of(const SmParams<T>* P, int b) {
+  return P->buf[b == B_XC || b == B_XN ? 1 : b];
 }
 
 // Workgroup-uniform values to scalar registers (the per-item product parameters stay out of the vector budget).
@@ -267,17 +285,20 @@ __device__ __forceinline__ void make_uniform(GemmParams<T>& G) {
   }
 }
 
-// The product d of the program with its buffers resolved for the current iterate buffer `cur` (host).
+// The product d of the program with its buffers resolved (host); the slots left for the kernel to bind are
+// coded in `sub` and hold no pointer.
 template <class T>
-GemmParams<T> resolve_product(const SmParams<T>* P, const SmProd& d, int cur) {
-  GemmParams<T> G{};
-  const SmView a = resolve(P, d.a, cur), b = resolve(P, d.b, cur);
-  G.A = static_cast<const T*>(a.p);
-  G.lda = a.ld;
-  G.psa = a.ps;
-  G.B = static_cast<const T*>(b.p);
-  G.ldb = b.ld;
-  G.psb = b.ps;
+SmItem<T> resolve_product(const SmParams<T>* P, const SmProd& d) {
+  SmItem<T> it{};
+  GemmParams<T>& G = it.g;
+  auto code = [](int b) { return b == B_XC ? 1 : b == B_XN ? 2 : b == B_A ? 3 : 0; };
+  const SmView a = view_of(P, d.a), b = view_of(P, d.b);
+  G.A = code(d.a) ? nullptr : static_cast<const T*>(a.p);
+  G.lda = d.a == B_A ? 0 : a.ld;
+  G.psa = d.a == B_A ? 0 : a.ps;
+  G.B = code(d.b) ? nullptr : static_cast<const T*>(b.p);
+  G.ldb = d.b == B_A ? 0 : b.ld;
+  G.psb = d.b == B_A ? 0 : b.ps;
   G.M = a.rows;
   G.N = b.cols;
   G.K = a.cols;
@@ -286,35 +307,55 @@ GemmParams<T> resolve_product(const SmParams<T>* P, const SmProd& d, int cur) {
   G.nout = d.nout;
   G.nin = d.nin;
   G.ref = d.ref;
+  it.sub = code(d.a) | code(d.b) << 2;
   for (int t = 0; t < 3; ++t) {
-    const SmView o = resolve(P, t < d.nout ? d.out[t] : d.a, cur);
-    const SmView in = resolve(P, t < d.nin ? d.in[t] : d.a, cur);
-    G.out[t] = t < d.nout ? static_cast<T*>(o.p) : nullptr;
-    G.ldo[t] = o.ld;
-    G.pso[t] = o.ps;
-    G.in[t] = t < d.nin ? static_cast<const T*>(in.p) : nullptr;
-    G.ldi[t] = in.ld;
-    G.psi[t] = in.ps;
+    if (t < d.nout) {
+      const SmView o = view_of(P, d.out[t]);
+      G.out[t] = code(d.out[t]) ? nullptr : static_cast<T*>(o.p);
+      G.ldo[t] = o.ld;
+      G.pso[t] = o.ps;
+      it.sub |= code(d.out[t]) << (4 + 2 * t);
+    }
+    if (t < d.nin) {
+      const SmView in = view_of(P, d.in[t]);
+      G.in[t] = code(d.in[t]) ? nullptr : static_cast<const T*>(in.p);
+      G.ldi[t] = in.ld;
+      G.psi[t] = in.ps;
+      it.sub |= code(d.in[t]) << (10 + 2 * t);
+    }
     G.ca[t] = (T)d.ca[t];
     G.cg[t] = (T)d.cg[t];
     for (int u = 0; u < 3; ++u) G.cb[t][u] = (T)d.cb[t][u];
   }
   G.reduce = d.reduce != 0;
-  // the input matrix comes per call: marked here, no pointer or strides of it in the table
-  G.vec = (d.a == B_A ? 1 : 0) | (d.b == B_A ? 2 : 0);
-  if (d.a == B_A) {
-    G.A = nullptr;
-    G.lda = G.psa = 0;
+  return it;
+}
+
+// The slots of a product that the host left unbound (SmItem::sub), bound to this update's iterates xc (current)
+// and xn (next) and to the call's input matrix.
+template <class T>
+__device__ __forceinline__ void sm_bind(GemmParams<T>& G, int sub, T* xc, T* xn, const SmCall<T>& call) {
+  auto pick = [&](int code, T* p) { return code == 1 ? xc : code == 2 ? xn : p; };
+  const int ca = sub & 3, cb = (sub >> 2) & 3;
+  if (ca == 3) {
+    G.A = call.a;
+    G.lda = call.lda;
+    G.psa = call.psa;
+  } else if (ca) {
+    G.A = pick(ca, nullptr);
   }
-  if (d.b == B_A) {
-    G.B = nullptr;
-    G.ldb = G.psb = 0;
+  if (cb == 3) {
+    G.B = call.a;
+    G.ldb = call.lda;
+    G.psb = call.psa;
+  } else if (cb) {
+    G.B = pick(cb, nullptr);
   }
+#pragma unroll
   for (int t = 0; t < 3; ++t) {
-    if (t >= d.nout) G.ldo[t] = G.pso[t] = 0;
-    if (t >= d.nin) G.ldi[t] = G.psi[t] = 0;
+    G.out[t] = pick((sub >> (4 + 2 * t)) & 3, G.out[t]);
+    G.in[t] = pick((sub >> (10 + 2 * t)) & 3, const_cast<T*>(G.in[t]));
   }
-  return G;
 }
 
 // One 16 x 16 output block (all four planes) of C = A B with the epilogue.  The block's operands are staged
@@ -545,22 +586,24 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   constexpr int ACOPY_ELEMS = LDS_BYTES / (int)sizeof(T);
   __shared__ double sh[32];
   __shared__ double vs[4 * SM_MAXD], wsv[4 * SM_MAXD];
-  // the parameter block, read once from device memory (phases index it by product and buffer); every
-  // thread issues its loads before its first LDS store, one round trip for the whole block
+  // the parameter block up to the program's last phase (call.pwords 16-byte words), read once from device
+  // memory (phases index it by product); every thread issues its loads before its first LDS store, one round
+  // trip for the whole block
   constexpr int PV = (int)((sizeof(SmParams<T>) + 15) / 16), PU = (PV + SM_THREADS - 1) / SM_THREADS;
   __shared__ uint4 pcopy[PV];
   {
     const uint4* src = reinterpret_cast<const uint4*>(Pg);
+    const int pw = call.pwords < PV ? call.pwords : PV;
     uint4 v[PU];
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
       const int i = (int)threadIdx.x + u * SM_THREADS;
-      v[u] = src[i < PV ? i : 0];
+      v[u] = src[i < pw ? i : 0];
     }
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
       const int i = (int)threadIdx.x + u * SM_THREADS;
-      if (i < PV) pcopy[i] = v[u];
+      if (i < pw) pcopy[i] = v[u];
     }
     __syncthreads();
   }
@@ -683,33 +726,26 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   double dx_rel = 0.0, e1_rel = -1.0;
   bool done = normA == 0.0;  // A = 0: X_0 = 0 is the pseudoinverse
   while (!done) {
-    for (int ph = 0; ph < P->prog.nphase && !done; ++ph) {
-      const int np = P->prog.nprod[ph];
+    T* const xc = static_cast<T*>(P->buf[1 + cur].p);
+    T* const xn = static_cast<T*>(P->buf[2 - cur].p);
+    for (int ph = 0; ph < P->nphase && !done; ++ph) {
+      const int np = P->nprod[ph];
       // output blocks of the phase's products (X_0's E1 is never needed)
       int tiles[2] = {0, 0};
       for (int q = 0; q < 2; ++q) {
-        if (q >= np || (q == 1 && ph == P->prog.e1_phase && j == 0)) continue;
-        tiles[q] = P->gp[ph][q][cur].tiles_m * P->gp[ph][q][cur].tiles_n;
+        if (q >= np || (q == 1 && ph == P->e1_phase && j == 0)) continue;
+        tiles[q] = P->gp[ph][q].g.tiles_m * P->gp[ph][q].g.tiles_n;
       }
       const int total = tiles[0] + tiles[1];
       for (int item = blockIdx.x; item < total; item += G) {
         const int q = item < tiles[0] ? 0 : 1;
         const int t = item - (q ? tiles[0] : 0);
-        GemmParams<T> gq = P->gp[ph][q][cur];
-        if (gq.vec & 1) {
-          gq.A = call.a;
-          gq.lda = call.lda;
-          gq.psa = call.psa;
-        }
-        if (gq.vec & 2) {
-          gq.B = call.a;
-          gq.ldb = call.lda;
-          gq.psb = call.psa;
-        }
+        GemmParams<T> gq = P->gp[ph][q].g;
+        sm_bind(gq, P->gp[ph][q].sub, xc, xn, call);
         make_uniform(gq);
         double s_d = 0.0, s_x = 0.0;
         sm_block<T, MM>(gq, t / gq.tiles_n, t % gq.tiles_n, stage, red, s_d, s_x);
-        const int kind = P->prog.prod[ph][q].reduce;
+        const int kind = P->kind[ph][q];
         if (kind) {
           s_d = sm_sum(s_d, sh);
           s_x = sm_sum(s_x, sh);
@@ -721,8 +757,8 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
         }
       }
       if (!sm_sync(P->bar, G, call.bar_base, nbar)) return;
-  stamp();
-      if (e1 && ph == P->prog.e1_phase && j >= 1) {
+      stamp();
+      if (e1 && ph == P->e1_phase && j >= 1) {
         // ||A X_j A - A||_F / ||A||_F from the tiles of the E1 product, summed in tile order
         const double s = sm_tile_sum(P->partial + 2 * 2 * SM_MAXG + 1, tiles[1], 2);
         e1_rel = sqrt(s) / normA;
@@ -743,9 +779,9 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
           ret_j = j;
         }
       }
-      if (done || ph != P->prog.nphase - 1) continue;
+      if (done || ph != P->nphase - 1) continue;
       // the update X_{j+1} = X_nxt is formed: its change norms summed over the tiles, then the stop rule
-      const int tu = P->prog.prod[ph][0].reduce == 1 ? tiles[0] : 0;
+      const int tu = P->kind[ph][0] == 1 ? tiles[0] : 0;
       const double d2 = sm_tile_sum(P->partial, tu, 2), x2 = sm_tile_sum(P->partial + 1, tu, 2);
       const double d_abs = sqrt(fmax(0.0, d2)), xn = sqrt(fmax(0.0, x2));
       ++j;
@@ -824,8 +860,13 @@ SmProd prod(int a, int b, int out, double ca = 1.0, double cg = 0.0) {
 
 int sq(int k) { return B_SQ + k; }
 
+int xb(int k) { return B_XB + k; }
+
+// Phases of one QRAPID(N) update (Algorithm 1): 6 + 2N on the left side, 8 + 2N on the right.
+int qrapid_phases(int N, bool left) { return (left ? 6 : 8) + 2 * N; }
+
 // Products of one update of `method` on `side` (left: R = I - X A, X+ = T X; right: R = I - A X, X+ = X T).
-SmProgram build_program(int method, bool left, bool e1) {
+SmProgram build_program(int method, int order, bool left, bool e1) {
   SmProgram g;
   std::memset(&g, 0, sizeof(g));
   g.e1_phase = -1;
@@ -890,6 +931,77 @@ SmProgram build_program(int method, bool left, bool e1) {
       g.nphase = 6;
       break;
     }
+    case QPINV_QRAPID: {
+      // Algorithm 1 with N = order nested steps.  Left: Q = X A, H1 = 7I - Q, H2 = 15I - Q H1, F = 13I - Q H2,
+      // U = F X / 4, V = U + X - Q U, Z = W + Y - (Y A) W (N times), X+ = Z + X - Q Z.  Right: P = A X, the same
+      // Horner factors from P, U = X F / 4, V = U + X (I - A U), Z = W + Y (I - A W), X+ = Z + X (I - A Z).
+      // R = I - Q (I - P) rides on the first product for the E1 rule.
+      const int N = order;
+      SmProd d = side_prod(sq(0), 1.0, 0.0);
+      d.nout = e1 ? 3 : 2;
+      d.out[1] = sq(1);
+      d.ca[1] = -1.0;
+      d.cg[1] = 7.0;
+      if (e1) {
+        d.out[2] = sq(4);
+        d.ca[2] = -1.0;
+        d.cg[2] = 1.0;
+      }
+      add(0, d);
+      add(1, prod(sq(0), sq(1), sq(2), -1.0, 15.0));
+      if (e1) {
+        add(1, e1_prod(sq(4)));
+        g.e1_phase = 1;
+      }
+      add(2, prod(sq(0), sq(2), sq(1), -1.0, 13.0));  // F into H1
+      int ph = 3;
+      auto plus = [](SmProd d2, int in0, int in1, double b0, double b1) {
+        d2.nin = in1 < 0 ? 1 : 2;
+        d2.in[0] = in0;
+        d2.cb[0][0] = b0;
+        if (in1 >= 0) {
+          d2.in[1] = in1;
+          d2.cb[0][1] = b1;
+        }
+        return d2;
+      };
+      int Y = xb(0), W = xb(1), F = xb(2);
+      if (left) {
+        add(ph++, prod(sq(1), B_XC, xb(0), 0.25));                                   // U
+        add(ph++, plus(prod(sq(0), xb(0), xb(1), -1.0), xb(0), B_XC, 1.0, 1.0));   // V
+        for (int l = 0; l < N; ++l) {
+          add(ph++, prod(Y, B_A, sq(3)));                                           // Y A
+          add(ph++, plus(prod(sq(3), W, F, -1.0), W, Y, 1.0, 1.0));                 // Z
+          const int freed = Y;
+          Y = W;
+          W = F;
+          F = freed;
+        }
+        SmProd u = plus(prod(sq(0), W, B_XN, -1.0), W, B_XC, 1.0, 1.0);
+        u.ref = 1;
+        u.reduce = 1;
+        add(ph++, u);
+      } else {
+        add(ph++, prod(B_XC, sq(1), xb(0), 0.25));                      // U
+        add(ph++, prod(B_A, xb(0), sq(3), -1.0, 1.0));                  // I - A U
+        add(ph++, plus(prod(B_XC, sq(3), xb(1)), xb(0), -1, 1.0, 0.0));  // V
+        for (int l = 0; l < N; ++l) {
+          add(ph++, prod(B_A, W, sq(3), -1.0, 1.0));                    // I - A W
+          add(ph++, plus(prod(Y, sq(3), F), W, -1, 1.0, 0.0));          // Z
+          const int freed = Y;
+          Y = W;
+          W = F;
+          F = freed;
+        }
+        add(ph++, prod(B_A, W, sq(3), -1.0, 1.0));  // I - A Z
+        SmProd u = plus(prod(B_XC, sq(3), B_XN), W, B_XC, 1.0, 0.0);
+        u.ref = 1;
+        u.reduce = 1;
+        add(ph++, u);
+      }
+      g.nphase = ph;
+      break;
+    }
     default: {  // QHPI19
       add(0, side_prod(sq(0), -1.0, 1.0));
       SmProd d2 = prod(sq(0), sq(0), sq(1));  // R^2 and S = R + R^2
@@ -942,17 +1054,18 @@ SmProgram build_program(int method, bool left, bool e1) {
   return g;
 }
 
-// Algorithmic flops of phases [0, last] of one pass: the side product, the update and the E1 product
-// (when counted) are s x s x o, the others s^3.
+// Algorithmic flops of phases [0, last] of one pass: 32 M N K per quaternion product, from the buffers'
+// shapes (A m x n, the iterates and the B_XB buffers n x m, the side-by-side s x s, the E1 product m x n).
 double program_flops(const SmProgram& g, int64_t m, int64_t n, bool left, bool with_e1, int last) {
-  const double s = left ? n : m, o = left ? m : n;
+  const double s = left ? n : m;
+  auto rows = [&](int b) { return b == B_A || b == B_E ? (double)m : b < B_SQ || b >= B_XB ? (double)n : s; };
+  auto cols = [&](int b) { return b == B_A || b == B_E ? (double)n : b < B_SQ || b >= B_XB ? (double)m : s; };
   double f = 0.0;
   for (int ph = 0; ph <= last && ph < g.nphase; ++ph)
     for (int q = 0; q < g.nprod[ph]; ++q) {
       const SmProd& d = g.prod[ph][q];
       if (d.reduce == 2 && !with_e1) continue;
-      const bool big = d.a == B_A || d.b == B_A || d.reduce != 0;
-      f += 32.0 * (big ? s * s * o : s * s * s);
+      f += 32.0 * rows(d.a) * cols(d.b) * cols(d.a);
     }
   return f;
 }
@@ -1000,8 +1113,8 @@ Mat mat_of(const SmView& v, int dtype) {
 }
 
 template <class T>
-int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, double tol, int max_iter, int stop,
-                  int dtype, const Mat& Xout, qpinv_info& inf, hipStream_t s) {
+int small_solve_t(Ctx& c, int method, int order, const Mat& A0, int scaling, double am, double tol, int max_iter,
+                  int stop, int dtype, const Mat& Xout, qpinv_info& inf, hipStream_t s) {
   const int64_t m = A0.rows, n = A0.cols;
   int side = c.opt.side;
   if (side == QPINV_SIDE_AUTO) side = (m > n) ? QPINV_SIDE_LEFT : QPINV_SIDE_RIGHT;
@@ -1033,16 +1146,20 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
   call.psa = A.v.ps;
   P.buf[B_A].p = nullptr;  // per call
   P.buf[B_A].ld = P.buf[B_A].ps = 0;
-  P.buf[1] = view(ws_mat(c, "smX0", n, m, dtype));
+  P.buf[1] = view(ws_mat(c, "smX0", n, m, dtype));  // one shape, so the same strides (SmItem relies on it)
   P.buf[2] = view(ws_mat(c, "smX1", n, m, dtype));
   for (int k = 0; k < 8; ++k) P.buf[B_SQ + k] = view(ws_mat(c, "smS" + std::to_string(k), sd, sd, dtype));
   P.buf[B_E] = view(ws_mat(c, "smE", m, n, dtype));
+  if (method == QPINV_QRAPID)
+    for (int k = 0; k < 3; ++k) P.buf[B_XB + k] = view(ws_mat(c, "smB" + std::to_string(k), n, m, dtype));
   const bool direct = Xout.dtype == dtype;
   call.xout = static_cast<T*>(Xout.v.p);
   call.ldx = Xout.v.ld;
   call.psx = Xout.v.ps;
   call.xout_direct = direct ? 1 : 0;
-  P.prog = build_program(method, left, e1);
+  const SmProgram prog = build_program(method, order, left, e1);
+  P.nphase = prog.nphase;
+  P.e1_phase = prog.e1_phase;
   P.m = (int)m;
   P.n = (int)n;
   P.scaling = scaling;
@@ -1056,9 +1173,13 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
   P.partial = static_cast<double*>(c.ws.get("smPartial", sizeof(double) * 2 * 2 * 2 * SM_MAXG));
   P.state = static_cast<double*>(c.ws.get("smState", sizeof(double) * (S_COUNT + 2)));
   P.bar = reinterpret_cast<unsigned int*>(P.state + S_COUNT);
-  for (int ph = 0; ph < P.prog.nphase; ++ph)
-    for (int q = 0; q < P.prog.nprod[ph]; ++q)
-      for (int cur = 0; cur < 2; ++cur) P.gp[ph][q][cur] = resolve_product(&P, P.prog.prod[ph][q], cur);
+  for (int ph = 0; ph < prog.nphase; ++ph) {
+    P.nprod[ph] = prog.nprod[ph];
+    for (int q = 0; q < prog.nprod[ph]; ++q) {
+      P.kind[ph][q] = prog.prod[ph][q].reduce;
+      P.gp[ph][q] = resolve_product(&P, prog.prod[ph][q]);
+    }
+  }
   constexpr int kTrace = 256;
   if (c.opt.verbose) {
     P.trace = static_cast<unsigned long long*>(c.ws.get("smTrace", sizeof(unsigned long long) * kTrace));
@@ -1079,14 +1200,9 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
   }
   // grid: the output blocks of the largest phase
   int grid = 1;
-  for (int ph = 0; ph < P.prog.nphase; ++ph) {
+  for (int ph = 0; ph < prog.nphase; ++ph) {
     int t = 0;
-    for (int q = 0; q < P.prog.nprod[ph]; ++q) {
-      const SmProd& d = P.prog.prod[ph][q];
-      const SmView a = d.a == B_XC || d.a == B_XN ? P.buf[1] : P.buf[d.a];
-      const SmView b = d.b == B_XC || d.b == B_XN ? P.buf[1] : P.buf[d.b];
-      t += ((a.rows + 15) / 16) * ((b.cols + 15) / 16);
-    }
+    for (int q = 0; q < prog.nprod[ph]; ++q) t += P.gp[ph][q].g.tiles_m * P.gp[ph][q].g.tiles_n;
     grid = std::max(grid, t);
   }
   grid = std::min(grid, SM_MAXG);
@@ -1096,13 +1212,15 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
   // other contexts on the device, so they always copy.  The kernel writes its result record straight into
   // the pinned scalars, whose status slot holds a marker until the record arrives; both pinned areas
   // serve one call at a time (the call ends synchronised).
+  // Only the block up to the program's last phase is uploaded and copied by the kernel.
   static_assert(((sizeof(SmParams<T>) + 15) / 16) * 16 <= Ctx::kStageBytes, "staging area");
   static_assert(S_COUNT <= 48, "pinned scalars");
   constexpr double kNoRecord = -1.0e300;
-  const size_t pbytes = ((sizeof(SmParams<T>) + 15) / 16) * 16;
-  auto* Pd = static_cast<SmParams<T>*>(c.ws.get("smParams", pbytes));
+  const size_t pbytes = ((offsetof(SmParams<T>, gp) + sizeof(P.gp[0]) * prog.nphase + 15) / 16) * 16;
+  auto* Pd = static_cast<SmParams<T>*>(c.ws.get("smParams", ((sizeof(SmParams<T>) + 15) / 16) * 16));
+  call.pwords = (int)(pbytes / 16);
   std::memset(c.hstage, 0, pbytes);
-  std::memcpy(c.hstage, &P, sizeof(P));
+  std::memcpy(c.hstage, &P, std::min(pbytes, sizeof(P)));
   if (c.no_alloc || c.small_params_dev != Pd || c.small_params.size() != pbytes ||
       std::memcmp(c.small_params.data(), c.hstage, pbytes) != 0) {
     QP_HIP(hipMemcpyAsync(Pd, c.hstage, pbytes, hipMemcpyHostToDevice, s));
@@ -1149,8 +1267,8 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
   inf.e1_rel = st[S_E1];
   // every update's products; with the E1 rule also the E1 products of X_1 .. X_iters and the last pass's
   // phases up to its check
-  inf.gemm_flops = inf.iters * program_flops(P.prog, m, n, left, e1 && inf.iters > 1, 99);
-  if (e1 && inf.iters > 0) inf.gemm_flops += program_flops(P.prog, m, n, left, true, P.prog.e1_phase);
+  inf.gemm_flops = inf.iters * program_flops(prog, m, n, left, e1 && inf.iters > 1, SM_MAXPH);
+  if (e1 && inf.iters > 0) inf.gemm_flops += program_flops(prog, m, n, left, true, prog.e1_phase);
   c.flops += inf.gemm_flops;
   if (!direct) {
     const Mat Xr = mat_of(P.buf[1 + (int)st[S_RETBUF]], dtype);
@@ -1162,22 +1280,26 @@ int small_solve_t(Ctx& c, int method, const Mat& A0, int scaling, double am, dou
 
 }  // namespace
 
-bool small_eligible(const Ctx& c, int method, int scaling, int stop, int precision, int64_t m, int64_t n) {
+bool small_eligible(const Ctx& c, int method, int order, int scaling, int stop, int precision, int64_t m, int64_t n) {
   if (!c.opt.small_path || c.opt.gemm_timing || c.opt.penrose_finish) return false;
   for (int k = 0; k < 3; ++k)
     if (c.opt.force_cfg[k] >= 0) return false;
   if (precision != QPINV_PREC_F64 && precision != QPINV_PREC_F32) return false;
-  if (method != QPINV_NS && method != QPINV_QSAI && method != QPINV_QHPI19) return false;
+  if (method == QPINV_QRAPID) {
+    if (qrapid_phases(order, true) > SM_MAXPH || qrapid_phases(order, false) > SM_MAXPH) return false;
+  } else if (method != QPINV_NS && method != QPINV_QSAI && method != QPINV_QHPI19) {
+    return false;
+  }
   if (stop != STOP_DX_ABS && stop != STOP_DX_REL && stop != STOP_E1_REL) return false;
   if (scaling != QPINV_ALPHA_POWER && scaling != QPINV_ALPHA_FROB && scaling != QPINV_ALPHA_GIVEN) return false;
   return m >= 1 && n >= 1 && m <= SM_MAXD && n <= SM_MAXD;
 }
 
-int small_solve(Ctx& c, int method, const Mat& A0, int scaling, double am, double tol, int max_iter, int stop,
-                int precision, const Mat& Xout, qpinv_info& inf, hipStream_t s) {
+int small_solve(Ctx& c, int method, int order, const Mat& A0, int scaling, double am, double tol, int max_iter,
+                int stop, int precision, const Mat& Xout, qpinv_info& inf, hipStream_t s) {
   if (precision == QPINV_PREC_F64)
-    return small_solve_t<double>(c, method, A0, scaling, am, tol, max_iter, stop, QPINV_F64, Xout, inf, s);
-  return small_solve_t<float>(c, method, A0, scaling, am, tol, max_iter, stop, QPINV_F32, Xout, inf, s);
+    return small_solve_t<double>(c, method, order, A0, scaling, am, tol, max_iter, stop, QPINV_F64, Xout, inf, s);
+  return small_solve_t<float>(c, method, order, A0, scaling, am, tol, max_iter, stop, QPINV_F32, Xout, inf, s);
 }
 
 }  // namespace qp

@@ -885,8 +885,8 @@ int solve(Ctx& c, int method, int order, const qpinv_qmat* Aq, int scaling, doub
     return status;
   };
   if (m == 0 || n == 0) return finish(QPINV_OK);
-  if (small_eligible(c, method, scaling, stop, precision, m, n))
-    return finish(small_solve(c, method, A0, scaling, am, tol, max_iter, stop, precision, Xout, inf, s));
+  if (small_eligible(c, method, order, scaling, stop, precision, m, n))
+    return finish(small_solve(c, method, order, A0, scaling, am, tol, max_iter, stop, precision, Xout, inf, s));
   // the ladder's FP32-storage products (its FP32 phase and the finish's corrections) as three BF16 products;
   // not in an allocation-free call, whose stage buffer may not grow (the split copies need one)
   struct SplitScope {

@@ -63,7 +63,7 @@ struct Ctx {
   GemmScratch scratch;
   double* dsc = nullptr;  // device scalars
   double* hsc = nullptr;  // pinned host scalars
-  static constexpr size_t kStageBytes = 16384;
+  static constexpr size_t kStageBytes = 32768;
   void* hstage = nullptr;  // pinned host staging area for small parameter blocks (kStageBytes)
   std::map<std::tuple<int, int64_t, int64_t, int64_t>, int> tuned;
   MlpState* mlp = nullptr;
@@ -117,9 +117,9 @@ int solve_noalloc(Ctx& c, int method, int order, const qpinv_qmat* A, int scalin
                   int max_iter, int stop, int precision, qpinv_qmat* X, qpinv_info* info, hipStream_t s);
 
 // One-launch solve of a small matrix (small.hip): eligibility and the solve (returns a status code).
-bool small_eligible(const Ctx& c, int method, int scaling, int stop, int precision, int64_t m, int64_t n);
-int small_solve(Ctx& c, int method, const Mat& A0, int scaling, double am, double tol, int max_iter, int stop,
-                int precision, const Mat& Xout, qpinv_info& inf, hipStream_t s);
+bool small_eligible(const Ctx& c, int method, int order, int scaling, int stop, int precision, int64_t m, int64_t n);
+int small_solve(Ctx& c, int method, int order, const Mat& A0, int scaling, double am, double tol, int max_iter,
+                int stop, int precision, const Mat& Xout, qpinv_info& inf, hipStream_t s);
 
 // Address of the device's no-allocation scratch, looked up once per device with that device current (noalloc.hip).
 void* noalloc_scratch(int device);

@@ -285,12 +285,45 @@ SMALL_SHAPES = [(64, 48), (48, 64), (37, 29), (29, 37), (128, 128), (128, 97), (
 
 
 @pytest.mark.parametrize("shape", SMALL_SHAPES)
-@pytest.mark.parametrize("method,order", [("ns", 2), ("qsai", 10), ("qhpi19", 19)])
+@pytest.mark.parametrize("method,order", [("ns", 2), ("qsai", 10), ("qhpi19", 19), ("qrapid", 5)])
 @pytest.mark.parametrize("stop,scaling", [("e1_rel", "power"), ("dx_rel", "frob"), ("dx_abs", "given")])
 def test_small_path_matches_oracle_and_regular_path(qctx, shape, method, order, stop, scaling):
     """FP64 solves of at most 128 per side run as one launch (small_path = 1, the default): the same update
     count and returned iterate as the oracle from the same alpha (<= 1e-12) and as the product-by-product
     path (small_path = 0)."""
+    _small_vs_regular(qctx, shape, method, order, stop, scaling)
+
+
+@pytest.mark.parametrize("shape", [(64, 48), (29, 37), (128, 97), (1, 7)])
+@pytest.mark.parametrize("order", [0, 1, 8, 9])
+@pytest.mark.parametrize("stop,scaling", [("e1_rel", "power"), ("dx_rel", "frob")])
+def test_small_path_qrapid_orders(qctx, shape, order, stop, scaling):
+    """QRAPID(N) in one launch for N <= 8 (6 + 2N phases on the left side, 8 + 2N on the right, at most 24);
+    N = 9 takes the product-by-product path.  Both match the oracle and each other."""
+    _small_vs_regular(qctx, shape, "qrapid", order, stop, scaling)
+
+
+def test_small_path_qrapid_runs_one_launch(qctx, capfd):
+    """QRAPID(8) of a 48 x 64 matrix (24 phases, the table's limit) runs as one launch and QRAPID(9) does
+    not: the one-launch path's trace line (option verbose) is printed for the first only."""
+    import paper_2605_01464_amd as q
+
+    Ad = to_dev(np.random.default_rng(45).standard_normal((4, 48, 64)), "f64")
+    kw = dict(scaling="power", tol=1e-12, stop="dx_rel", precision="f64")
+    qctx.set("verbose", 1)
+    try:
+        capfd.readouterr()
+        _, info = q.solve(qctx, Ad, "qrapid", 8, **kw)
+        err8 = capfd.readouterr().err
+        _, info9 = q.solve(qctx, Ad, "qrapid", 9, **kw)
+        err9 = capfd.readouterr().err
+    finally:
+        qctx.set("verbose", 0)
+    assert info["status"] == q.OK and info9["status"] == q.OK
+    assert "small solve" in err8 and "small solve" not in err9
+
+
+def _small_vs_regular(qctx, shape, method, order, stop, scaling):
     import paper_2605_01464_amd as q
 
     A = np.random.default_rng(40 + shape[0] + 3 * shape[1]).standard_normal((4,) + shape)
@@ -316,7 +349,7 @@ def test_small_path_matches_oracle_and_regular_path(qctx, shape, method, order, 
         assert info["e1_rel"] <= tol
 
 
-@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("ns", 2)])
+@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("ns", 2), ("qrapid", 5)])
 def test_small_path_fp32(qctx, method, order):
     """FP32 one-launch solves of a 100 x 70 matrix: the regular path's update count, and both within FP32
     rounding of the oracle's iterate."""
