@@ -155,7 +155,8 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
  * (configuration of qpinv_solve_batched, -1 = tuned or default), batched_dynamic (phase-synchronous
  * batched form: 1 (default) workgroups claim work items from a counter, 0 workgroup g takes items
  * g, g + G, ...; the results are the same), small_path (0/1, default 1: single FP64 or FP32 solves of
- * NS, QSAI or QHPI19 with at most 128 rows and columns run as one persistent launch), fault_small_giveup
+ * NS, QSAI, QHPI19 or QRAPID(N <= 8) with at most 128 rows and columns run as one persistent launch),
+ * fault_small_giveup
  * (0/1, a test hook: the one-launch solve's grid-barrier give-up flag is raised before its launch, so every
  * workgroup leaves at its first barrier and the call returns QPINV_ETIMEOUT without waiting; the next
  * solve clears the flag), verbose (0/1), penrose_finish (projection of the returned
