@@ -630,7 +630,10 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
     // when it fits (every power step reads all of it twice).  Rows (plane-major, 4 m of them) are mapped
     // on slots of 2^lgw >= n columns, so a slot's row and column are a shift and a mask, and every thread
     // has SM_SU loads in flight at a time.
-    const bool in_lds = P->scaling == QPINV_ALPHA_POWER && 4 * m * n <= ACOPY_ELEMS;
+    // the LDS copy's row stride is n rounded up to 8 mod 16 elements when that fits: the lanes of a wave that
+    // read one column in different rows (both products of a power step) then fall on different banks
+    const int ldp = ((n + 7) >> 4) * 16 + 8, ldc = 4 * m * ldp <= ACOPY_ELEMS ? ldp : n;
+    const bool in_lds = P->scaling == QPINV_ALPHA_POWER && 4 * m * ldc <= ACOPY_ELEMS;
     double fro = 0.0, bad = 0.0;
     {
       const int lgw = lg_ceil(n), slots = (4 * m) << lgw;
@@ -650,7 +653,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
             const double x = (double)v[u];
             if (!__builtin_isfinite(x)) bad += 1.0;
             fro += x * x;
-            if (in_lds) acopy[row * n + c] = v[u];
+            if (in_lds) acopy[row * ldc + c] = v[u];
           }
         }
       }
@@ -661,7 +664,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
     if (bad == 0.0 && fro > 0.0) {
       if (P->scaling == QPINV_ALPHA_POWER) {
         if (in_lds)
-          s1sq = sm_power((const __attribute__((address_space(3))) T*)acopy, n, (int64_t)m * n, m, n,
+          s1sq = sm_power((const __attribute__((address_space(3))) T*)acopy, ldc, (int64_t)m * ldc, m, n,
                           P->power_steps, P->seed, vs, wsv, sh, sh + 16);
         else
           s1sq = sm_power((const __attribute__((address_space(1))) T*)a, A.ld, A.ps, m, n,
