@@ -50,6 +50,21 @@ def test_noalloc_matches_solve_two_calls(qctx):
     _compare(qctx, A3, "f32_f64finish", "qhpi19", 1e-6, "guarded")
 
 
+def test_noalloc_qrapid_one_launch(qctx):
+    """QRAPID's one-launch solves without allocation: QRAPID(5) on the 64 x 48 FP64 input (16 phases per update,
+    left side), then QRAPID(8) on a smaller wide matrix (24 phases, right side) and QRAPID(0) on the first
+    again, each equal to qpinv_solve's result bit for bit; the first follows the oracle from the same alpha."""
+    qctx.set("autotune", 0)
+    A1 = qsynth.c1_instance(6)
+    X1, info1 = _compare(qctx, A1, "f64", "qrapid", 1e-12, "e1_rel", order=5)
+    ro = M.solve(A1, "qrapid", 5, alpha=info1["alpha_used"], tol=1e-12, stop="e1_rel", side="left")
+    assert info1["iters"] == ro.iters
+    assert rel_fro(to_np(X1), ro.X) <= 1e-12
+    A2 = np.random.default_rng(34).standard_normal((4, 29, 37))
+    _compare(qctx, A2, "f64", "qrapid", 1e-12, "dx_rel", order=8)
+    _compare(qctx, A1, "f64", "qrapid", 1e-12, "dx_rel", order=0)
+
+
 def test_noalloc_ladder_uses_native_fp32_products(qctx):
     """The BF16 -> FP32 -> FP64 ladder without allocation: its FP32-storage products stay native FP32 (the split
     BF16 products would need the stage buffer to grow), so it equals qpinv_solve with option mixed_split = 0 bit
