@@ -378,6 +378,18 @@ int qpinv_spectral_labels(qpinv_ctx* ctx, int method, int order, const double* s
 int qpinv_autotune(qpinv_ctx* ctx, int gemm_prec, int64_t M, int64_t N, int64_t K, double* best_ms,
                    void* hip_stream);
 
+/* Persisted tile choices, so that a later process skips the autotuner's timing runs.  qpinv_tune_save
+ * writes every configuration this context has tuned (products per precision and shape, batched solves per
+ * batch signature) to the text file `path` (host string; replaced if it exists), by configuration name and
+ * with a device token (architecture name and compute-unit count); returns the number of entries written or
+ * EINVAL (no path, file not writable).  qpinv_tune_load merges such a file into this context's tuned
+ * choices (an entry for the same shape or signature replaces the context's) and returns the number of
+ * entries applied: 0 for a file written on another device; entries naming a configuration this library
+ * does not have are skipped.  EINVAL for no path, an unreadable file or a malformed one (then nothing is
+ * applied).  Neither call uses the GPU beyond reading the device's properties. */
+int qpinv_tune_save(qpinv_ctx* ctx, const char* path);
+int qpinv_tune_load(qpinv_ctx* ctx, const char* path);
+
 /* Number of tile configurations for a product precision, and the name of one (static storage). */
 int qpinv_num_tile_configs(int gemm_prec);
 const char* qpinv_tile_config_name(int gemm_prec, int cfg);

@@ -87,6 +87,8 @@ def _load() -> ctypes.CDLL:
         "qpinv_gl_krylov": (I, [P, I, QP, QP, QP, QP, D, I, ctypes.POINTER(I), DP, DP, DP, I, P]),
         "qpinv_features": (I, [P, QP, I, DP, P]),
         "qpinv_autotune": (I, [P, I, I64, I64, I64, DP, P]),
+        "qpinv_tune_save": (I, [P, ctypes.c_char_p]),
+        "qpinv_tune_load": (I, [P, ctypes.c_char_p]),
         "qpinv_num_tile_configs": (I, [I]),
         "qpinv_tile_config_name": (ctypes.c_char_p, [I, I]),
         "qpinv_num_batched_configs": (I, []),
@@ -264,6 +266,14 @@ def qpinv_autotune(ctx, gemm_prec, M, N, K, stream=None):
     return r, ms.value
 
 
+def qpinv_tune_save(ctx, path) -> int:
+    return _lib.qpinv_tune_save(ctx, os.fsencode(path))
+
+
+def qpinv_tune_load(ctx, path) -> int:
+    return _lib.qpinv_tune_load(ctx, os.fsencode(path))
+
+
 def qpinv_num_tile_configs(gemm_prec) -> int:
     return _lib.qpinv_num_tile_configs(gemm_prec)
 
@@ -383,6 +393,18 @@ class Context:
 
     def set(self, key: str, value: float):
         _err(qpinv_set_option(self.handle, key, value), f"set_option({key})")
+
+    def save_tuning(self, path) -> int:
+        """Write this context's tuned tile choices to `path`; returns the number of entries."""
+        r = qpinv_tune_save(self.handle, path)
+        _err(r if r < 0 else OK, "qpinv_tune_save")
+        return r
+
+    def load_tuning(self, path) -> int:
+        """Merge tile choices saved by save_tuning (on the same kind of device); returns the entries applied."""
+        r = qpinv_tune_load(self.handle, path)
+        _err(r if r < 0 else OK, "qpinv_tune_load")
+        return r
 
 
 def _order(method: str, order):

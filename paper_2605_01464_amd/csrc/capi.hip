@@ -1,5 +1,7 @@
 // extern "C" boundary of libqpinv.so: argument checks, error codes, no exceptions across the ABI.
 #include <cstring>
+#include <fstream>
+#include <iterator>
 #include <string>
 
 #include "../../include/qpinv.h"
@@ -10,6 +12,7 @@
 #include "krylov.hpp"
 #include "mlp.hpp"
 #include "solver.hpp"
+#include "tunecache.hpp"
 
 struct qpinv_ctx {
   qp::Ctx* impl;
@@ -510,6 +513,68 @@ int qpinv_autotune(qpinv_ctx* c, int gemm_prec, int64_t M, int64_t N, int64_t K,
     return QPINV_OK;
   });
   return st == QPINV_OK ? cfg : st;
+}
+
+namespace {
+// The device token of a tune cache: architecture name and compute-unit count.
+std::string tune_device(int dev) {
+  hipDeviceProp_t pr{};
+  QP_HIP(hipGetDeviceProperties(&pr, dev));
+  return std::string(pr.gcnArchName) + ":" + std::to_string(pr.multiProcessorCount) + "cu";
+}
+}  // namespace
+
+int qpinv_tune_save(qpinv_ctx* c, const char* path) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    if (!path || !*path) throw qp::Error(QPINV_EINVAL, "tune cache: no path");
+    qp::TuneFile f;
+    f.device = tune_device(cx.device);
+    for (const auto& e : cx.tuned) {
+      const int p = std::get<0>(e.first);
+      f.gemm.emplace_back(p, std::get<1>(e.first), std::get<2>(e.first), std::get<3>(e.first),
+                          qp::tile_configs((qp::Prec)p).at(e.second).name);
+    }
+    for (const auto& e : cx.batched_tuned) f.batched.emplace_back(e.first, qp::batched_config_name(e.second));
+    std::ofstream out(path, std::ios::binary | std::ios::trunc);
+    out << qp::tune_format(f);
+    out.close();
+    if (!out) throw qp::Error(QPINV_EINVAL, std::string("tune cache: cannot write ") + path);
+    return (int)(f.gemm.size() + f.batched.size());
+  });
+}
+
+int qpinv_tune_load(qpinv_ctx* c, const char* path) {
+  return guarded([&]() {
+    qp::Ctx& cx = ctx_of(c);
+    if (!path || !*path) throw qp::Error(QPINV_EINVAL, "tune cache: no path");
+    std::ifstream in(path, std::ios::binary);
+    if (!in) throw qp::Error(QPINV_EINVAL, std::string("tune cache: cannot read ") + path);
+    const std::string text((std::istreambuf_iterator<char>(in)), std::istreambuf_iterator<char>());
+    qp::TuneFile f;
+    std::string err;
+    if (!qp::tune_parse(text, f, err)) throw qp::Error(QPINV_EINVAL, err);
+    if (f.device != tune_device(cx.device)) return 0;
+    // names to indices; entries whose configuration this library does not have are skipped
+    int applied = 0;
+    for (const auto& g : f.gemm) {
+      const auto& t = qp::tile_configs((qp::Prec)std::get<0>(g));
+      for (int k = 0; k < (int)t.size(); ++k)
+        if (std::get<4>(g) == t[k].name) {
+          cx.tuned[std::make_tuple(std::get<0>(g), std::get<1>(g), std::get<2>(g), std::get<3>(g))] = k;
+          ++applied;
+          break;
+        }
+    }
+    for (const auto& b : f.batched)
+      for (int k = 0; k < qp::batched_num_configs(); ++k)
+        if (b.second == qp::batched_config_name(k)) {
+          cx.batched_tuned[b.first] = k;
+          ++applied;
+          break;
+        }
+    return applied;
+  });
 }
 
 int qpinv_num_tile_configs(int gemm_prec) {

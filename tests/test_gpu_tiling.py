@@ -1,5 +1,6 @@
 """Tile configurations whose workgroups walk several output tiles (c workgroups per compute unit)
-against the same tile shape with one tile per workgroup, and against the FP64 oracle."""
+against the same tile shape with one tile per workgroup, and against the FP64 oracle; the persisted
+tile choices (tune cache) of a context."""
 import numpy as np
 import pytest
 
@@ -84,3 +85,39 @@ def test_step_reduction_with_walking_tiles(qctx, prec):
                 assert abs(a - b) <= 1e-12 * abs(b), (name, res[0][1], res[1][1])
     finally:
         qctx.set(key, -1)
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """Tile choices tuned on one context, saved to a file and loaded into a fresh context, which then holds the
+    same choices (its own save writes the same file); a file for another device applies nothing, an entry
+    naming an unknown configuration is skipped, and a malformed file is refused with nothing applied."""
+    import paper_2605_01464_amd as q
+
+    path, path2 = tmp_path / "tune.txt", tmp_path / "tune2.txt"
+    with q.Context(0) as a:
+        c32, _ = q.qpinv_autotune(a.handle, q.GEMM_PREC["f32"], 96, 80, 64)
+        c64, _ = q.qpinv_autotune(a.handle, q.GEMM_PREC["f64"], 33, 17, 29)
+        assert c32 >= 0 and c64 >= 0
+        assert a.save_tuning(path) == 2
+    text = path.read_text()
+    lines = text.splitlines()
+    assert lines[0].startswith("qpinv-tune 1 ") and len(lines) == 3
+    assert f"gemm 1 96 80 64 {q.qpinv_tile_config_name(q.GEMM_PREC['f32'], c32)}" in lines
+    assert f"gemm 0 33 17 29 {q.qpinv_tile_config_name(q.GEMM_PREC['f64'], c64)}" in lines
+    with q.Context(0) as b:
+        assert b.load_tuning(path) == 2
+        assert b.save_tuning(path2) == 2
+        assert path2.read_text() == text
+        other = tmp_path / "other.txt"
+        other.write_text("qpinv-tune 1 gfx000:1cu\n" + "\n".join(lines[1:]) + "\n")
+        assert b.load_tuning(other) == 0
+        unknown = tmp_path / "unknown.txt"
+        unknown.write_text(text + "gemm 1 5 5 5 no_such_config\n")
+        assert b.load_tuning(unknown) == 2
+        bad = tmp_path / "bad.txt"
+        bad.write_text(lines[0] + "\ngemm 1 7 7 7 " + q.qpinv_tile_config_name(q.GEMM_PREC["f32"], 0) + "\ngemm 1 x\n")
+        with pytest.raises(q.QpinvError):
+            b.load_tuning(bad)
+        assert b.save_tuning(path2) == 2  # nothing of the malformed file was applied
+        with pytest.raises(q.QpinvError):
+            b.load_tuning(tmp_path / "missing.txt")
