@@ -349,7 +349,7 @@ def _small_vs_regular(qctx, shape, method, order, stop, scaling):
         assert info["e1_rel"] <= tol
 
 
-@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("ns", 2), ("qrapid", 5)])
+@pytest.mark.parametrize("method,order", [("qhpi19", 19), ("ns", 2), ("qsai", 10), ("qrapid", 5)])
 def test_small_path_fp32(qctx, method, order):
     """FP32 one-launch solves of a 100 x 70 matrix: the regular path's update count, and both within FP32
     rounding of the oracle's iterate."""
