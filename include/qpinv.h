@@ -156,7 +156,9 @@ int qpinv_init(qpinv_ctx** ctx, int device, const char* config);
  * batched form: 1 (default) workgroups claim work items from a counter, 0 workgroup g takes items
  * g, g + G, ...; the results are the same), small_path (0/1, default 1: single FP64 or FP32 solves of
  * NS, QSAI, QHPI19 or QRAPID(N <= 8) with at most 128 rows and columns run as one persistent launch),
- * fault_small_giveup
+ * small_gram (0/1, default 1: in such an FP64 solve the workgroups idle during the set-up form A^H A, or
+ * A A^H on the right side, and the first update's side product alpha times it becomes an element-wise
+ * step, one product phase fewer; the sums round differently from the product X_0 A), fault_small_giveup
  * (0/1, a test hook: the one-launch solve's grid-barrier give-up flag is raised before its launch, so every
  * workgroup leaves at its first barrier and the call returns QPINV_ETIMEOUT without waiting; the next
  * solve clears the flag), verbose (0/1), penrose_finish (projection of the returned

@@ -55,6 +55,13 @@ int prec_check(int gemm_prec) {
 
 int storage_for(int gemm_prec) { return gemm_prec == QPINV_GEMM_F64 ? QPINV_F64 : QPINV_F32; }
 
+// The device token of a tune cache: architecture name and compute-unit count.
+std::string tune_device(int dev) {
+  hipDeviceProp_t pr{};
+  QP_HIP(hipGetDeviceProperties(&pr, dev));
+  return std::string(pr.gcnArchName) + ":" + std::to_string(pr.multiProcessorCount) + "cu";
+}
+
 void set_option(qp::Ctx& c, const std::string& key, double v) {
   auto need = [&](bool ok) {
     if (!ok) throw qp::Error(QPINV_EINVAL, "option " + key + ": value out of range");
@@ -80,6 +87,9 @@ void set_option(qp::Ctx& c, const std::string& key, double v) {
   } else if (key == "small_path") {
     need(v == 0 || v == 1);
     c.opt.small_path = (int)v;
+  } else if (key == "small_gram") {
+    need(v == 0 || v == 1);
+    c.opt.small_gram = (int)v;
   } else if (key == "fault_small_giveup") {
     need(v == 0 || v == 1);
     c.opt.fault_small_giveup = (int)v;
@@ -514,15 +524,6 @@ int qpinv_autotune(qpinv_ctx* c, int gemm_prec, int64_t M, int64_t N, int64_t K,
   });
   return st == QPINV_OK ? cfg : st;
 }
-
-namespace {
-// The device token of a tune cache: architecture name and compute-unit count.
-std::string tune_device(int dev) {
-  hipDeviceProp_t pr{};
-  QP_HIP(hipGetDeviceProperties(&pr, dev));
-  return std::string(pr.gcnArchName) + ":" + std::to_string(pr.multiProcessorCount) + "cu";
-}
-}  // namespace
 
 int qpinv_tune_save(qpinv_ctx* c, const char* path) {
   return guarded([&]() {

@@ -96,6 +96,12 @@ struct SmParams {
   unsigned int* bar;     // [0] arrivals, [1] generation, [2] give-up flag
   unsigned long long* trace;  // optional (option verbose): workgroup 0 stamps wall_clock64() after each barrier
   int trace_cap;
+  // gram = 1 (left side, A^H A) or 2 (right side, A A^H): while workgroup 0 runs the set-up, the others form
+  // that Gram matrix (gram_item: the input matrix as both operands, conjugate-transposed as sm_block's CT =
+  // gram) into the first output of the update's side product, which for X_0 = alpha A^H is alpha times it;
+  // the first update then takes that product's epilogue from it and starts at its second phase.  0: off.
+  int gram;
+  SmItem<T> gram_item;
   // every product of the program, per phase and product (built on the host, read from LDS by each phase with
   // independent loads).  Last: the host uploads, and the kernel copies, only the program's phases of it.
   SmItem<T> gp[SM_MAXPH][2];
@@ -370,7 +376,9 @@ constexpr int sm_stage_elems() {
   return 4 * 16 * (SM_KB + 1) + 4 * SM_KB * 17;
 }
 
-template <class T, class MM>
+// CT: 0 the operands as given; 1 the left operand is the conjugate transpose of the matrix G.A points at
+// (element (r, k) = conj(G.A(k, r)), G.M and G.K the transpose's shape); 2 the same for the right operand.
+template <class T, class MM, int CT = 0>
 __device__ void sm_block(const GemmParams<T>& G, int tm, int tn, T* stage, typename MM::Acc* red, double& s_d,
                          double& s_x) {
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -407,16 +415,21 @@ __device__ void sm_block(const GemmParams<T>& G, int tm, int tn, T* stage, typen
       const int qb = e >> 10, kkb = (e >> 4) & 63, cc = e & 15;
       const int col = cb + cc;
       const bool okb = kkb < kr && col < G.N;
-      va[u] = gload(G.A, oka ? qa * G.psa + (int64_t)row * G.lda + (k0 + kka) : 0);
-      vb[u] = gload(G.B, okb ? qb * G.psb + (int64_t)(k0 + kkb) * G.ldb + col : 0);
+      const int64_t offa = CT == 1 ? (int64_t)(k0 + kka) * G.lda + row : (int64_t)row * G.lda + (k0 + kka);
+      const int64_t offb = CT == 2 ? (int64_t)col * G.ldb + (k0 + kkb) : (int64_t)(k0 + kkb) * G.ldb + col;
+      va[u] = gload(G.A, oka ? qa * G.psa + offa : 0);
+      vb[u] = gload(G.B, okb ? qb * G.psb + offb : 0);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int e = tid + u * SM_THREADS;
       const bool oka = (e & 63) < kr && rb + ((e >> 6) & 15) < G.M;
       const bool okb = ((e >> 4) & 63) < kr && cb + (e & 15) < G.N;
-      As[((e >> 10) * 16 + ((e >> 6) & 15)) * (SM_KB + 1) + (e & 63)] = oka ? va[u] : T(0);
-      Bs[((e >> 10) * SM_KB + ((e >> 4) & 63)) * 17 + (e & 15)] = okb ? vb[u] : T(0);
+      // a conjugated operand's planes i, j, k change sign
+      const T xa = CT == 1 && (e >> 10) > 0 ? -va[u] : va[u];
+      const T xb = CT == 2 && (e >> 10) > 0 ? -vb[u] : vb[u];
+      As[((e >> 10) * 16 + ((e >> 6) & 15)) * (SM_KB + 1) + (e & 63)] = oka ? xa : T(0);
+      Bs[((e >> 10) * SM_KB + ((e >> 4) & 63)) * 17 + (e & 15)] = okb ? xb : T(0);
     }
     __syncthreads();
     const int r16 = lane & 15, kl = lane >> 4;
@@ -682,6 +695,18 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
       P->state[S_ALPHA] = alpha;
       P->state[S_S1SQ] = s1sq;
     }
+  } else if (P->gram != 0) {
+    // the Gram matrix meanwhile, by workgroups 1 .. (its blocks read only A)
+    GemmParams<T> gq = P->gram_item.g;
+    sm_bind(gq, P->gram_item.sub, static_cast<T*>(P->buf[1].p), static_cast<T*>(P->buf[2].p), call);
+    make_uniform(gq);
+    for (int t = blockIdx.x - 1; t < gq.tiles_m * gq.tiles_n; t += G - 1) {
+      double s_d = 0.0, s_x = 0.0;
+      if (P->gram == 1)
+        sm_block<T, MM, 1>(gq, t / gq.tiles_n, t % gq.tiles_n, stage, red, s_d, s_x);
+      else
+        sm_block<T, MM, 2>(gq, t / gq.tiles_n, t % gq.tiles_n, stage, red, s_d, s_x);
+    }
   }
   if (!sm_sync(P->bar, G, call.bar_base, nbar)) return;
   stamp();
@@ -718,6 +743,32 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
       }
     }
   }
+  if (P->gram != 0 && normA > 0.0) {
+    // the first update's side product X_0 A (A X_0) = alpha times the Gram matrix: its epilogue applied to
+    // alpha G element by element (in place over G, which is its first output), the values loaded first
+    GemmParams<T> g0 = P->gp[0][0].g;
+    sm_bind(g0, P->gp[0][0].sub, static_cast<T*>(P->buf[1].p), static_cast<T*>(P->buf[2].p), call);
+    make_uniform(g0);
+    constexpr int EPT = 4 * 16 * 16 / SM_THREADS;
+    static_assert(EPT * SM_THREADS == 4 * 16 * 16, "a 16 x 16 block of four planes per pass");
+    for (int t = blockIdx.x; t < g0.tiles_m * g0.tiles_n; t += G) {
+      const int rb = (t / g0.tiles_n) * 16, cb = (t % g0.tiles_n) * 16;
+      T gv[EPT];
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * SM_THREADS, p = e >> 8, row = rb + ((e >> 4) & 15), col = cb + (e & 15);
+        const bool ok = row < g0.M && col < g0.N;
+        gv[u] = gload(g0.out[0], ok ? p * g0.pso[0] + (int64_t)row * g0.ldo[0] + col : 0);
+      }
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * SM_THREADS, p = e >> 8, row = rb + ((e >> 4) & 15), col = cb + (e & 15);
+        const T inv[3] = {T(0), T(0), T(0)};
+        double s_d = 0.0, s_x = 0.0;
+        epilogue_apply(g0, p, row, col, (T)(alpha * (double)gv[u]), inv, s_d, s_x);
+      }
+    }
+  }
   if (!sm_sync(P->bar, G, call.bar_base, nbar)) return;
   stamp();
 
@@ -731,7 +782,7 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
   while (!done) {
     T* const xc = static_cast<T*>(P->buf[1 + cur].p);
     T* const xn = static_cast<T*>(P->buf[2 - cur].p);
-    for (int ph = 0; ph < P->nphase && !done; ++ph) {
+    for (int ph = j == 0 && P->gram != 0 ? 1 : 0; ph < P->nphase && !done; ++ph) {
       const int np = P->nprod[ph];
       // output blocks of the phase's products (X_0's E1 is never needed)
       int tiles[2] = {0, 0};
@@ -1209,6 +1260,26 @@ int small_solve_t(Ctx& c, int method, int order, const Mat& A0, int scaling, dou
     grid = std::max(grid, t);
   }
   grid = std::min(grid, SM_MAXG);
+  // The Gram matrix during the set-up (FP64; a side product of one plain output set, and enough other
+  // workgroups for one Gram block each).
+  {
+    const SmProd& d = prog.prod[0][0];
+    const int st = (int)((sd + 15) / 16) * (int)((sd + 15) / 16);
+    if (c.opt.small_gram && dtype == QPINV_F64 && prog.nprod[0] == 1 && d.nin == 0 && d.reduce == 0 && grid - 1 >= st) {
+      SmProd dg = d;
+      dg.a = dg.b = B_A;
+      dg.nout = 1;
+      dg.ca[0] = 1.0;
+      dg.cg[0] = 0.0;
+      dg.ref = 3;
+      P.gram_item = resolve_product(&P, dg);
+      GemmParams<T>& g = P.gram_item.g;
+      g.M = g.N = (int)sd;
+      g.K = (int)(left ? m : n);
+      g.tiles_m = g.tiles_n = (int)((sd + 15) / 16);
+      P.gram = left ? 1 : 2;
+    }
+  }
   // The parameter block goes to device memory through the context's pinned staging area, and only when
   // its bytes differ from the block already there (repeated solves of one shape reuse it; the input
   // matrix, the output and the record pointer go by value).  No-allocation calls share their scratch with

@@ -41,6 +41,7 @@ struct Options {
   int finish_method = QPINV_NS;  // method of the FP64 finish updates (-1: the solve's own method)
   int penrose_finish = 0;        // FP64 projection of the returned iterate: 0 none, 1 X A X, 2 (X A)^H X (A X)^H
   int small_path = 1;            // single solves of at most 128 per side in one launch (small.hip) when eligible
+  int small_gram = 1;            // one-launch FP64 solves: the Gram matrix formed during the set-up (small.hip)
   int fault_small_giveup = 0;    // test hook: the one-launch solve starts with its barrier's give-up flag raised
   double mixed_switch = 1e-2;
   int mixed_rnorm_steps = 6;
