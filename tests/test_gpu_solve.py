@@ -323,6 +323,31 @@ def test_small_path_qrapid_runs_one_launch(qctx, capfd):
     assert "small solve" in err8 and "small solve" not in err9
 
 
+@pytest.mark.parametrize("shape", [(64, 48), (29, 37), (128, 97)])
+@pytest.mark.parametrize("method,order", [("ns", 2), ("qhpi19", 19), ("qrapid", 5)])
+def test_small_path_gram_setup_matches_plain_setup(qctx, shape, method, order):
+    """The Gram matrix formed during the set-up (option small_gram = 1, the default; A^H A on the left side,
+    A A^H on the right) against the first side product formed from X_0 (0): the same update count, and
+    iterates within 1e-12 of each other and of the oracle from the same alpha."""
+    import paper_2605_01464_amd as q
+
+    A = np.random.default_rng(46 + shape[0]).standard_normal((4,) + shape)
+    kw = dict(scaling="power", tol=1e-12, stop="e1_rel", precision="f64", max_iter=100)
+    Ad = to_dev(A, "f64")
+    X1, i1 = q.solve(qctx, Ad, method, order, **kw)
+    try:
+        qctx.set("small_gram", 0)
+        X0, i0 = q.solve(qctx, Ad, method, order, **kw)
+    finally:
+        qctx.set("small_gram", 1)
+    assert i1["status"] == i0["status"] == q.OK
+    assert i1["iters"] == i0["iters"] and i1["alpha_used"] == i0["alpha_used"]
+    assert rel_fro(to_np(X1), to_np(X0)) <= 1e-12
+    side = "left" if shape[0] > shape[1] else "right"
+    ro = M.solve(A, method, order, alpha=i1["alpha_used"], tol=1e-12, stop="e1_rel", side=side, max_iter=100)
+    assert i1["iters"] == ro.iters and rel_fro(to_np(X1), ro.X) <= 1e-12
+
+
 def _small_vs_regular(qctx, shape, method, order, stop, scaling):
     import paper_2605_01464_amd as q
 
