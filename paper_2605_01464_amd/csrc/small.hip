@@ -93,7 +93,7 @@ struct SmParams {
   double tol;
   double* partial;       // [2][2][SM_MAXG * 2]: per item reduction terms (slot by phase kind)
   double* state;         // the set-up's results, broadcast to the workgroups (record slots)
-  unsigned int* bar;     // [0] arrivals, [1] generation, [2] give-up flag
+  unsigned int* bar;     // [0] arrivals, [1] Gram blocks written (set-up), [2] give-up flag
   unsigned long long* trace;  // optional (option verbose): workgroup 0 stamps wall_clock64() after each barrier
   int trace_cap;
   // gram = 1 (left side, A^H A) or 2 (right side, A A^H): while workgroup 0 runs the set-up, the others form
@@ -470,7 +470,8 @@ __device__ void sm_block(const GemmParams<T>& G, int tm, int tn, T* stage, typen
 // lane l of the group taking the columns l, l + L, ...; the group's sums meet in a fixed order (group_sum).
 // Returns the sum of |w_i|^2 over the rows this lane wrote (nonzero on the groups' first lanes only).
 template <bool ADJ, class AP>
-__device__ double sm_gemv(AP a, int64_t lda, int64_t psa, int m, int n, double c, const double* v, double* w) {
+__device__ __forceinline__ double sm_gemv(AP a, int64_t lda, int64_t psa, int m, int n, double c, const double* v,
+                                          double* w, double* dot = nullptr) {
   const int tid = threadIdx.x;
   const int rows = ADJ ? n : m, cols = ADJ ? m : n;
   const int lgl = min(6, 31 - __clz((int)blockDim.x / rows));  // rows <= 128, 512 threads: L >= 4
@@ -500,15 +501,17 @@ __device__ double sm_gemv(AP a, int64_t lda, int64_t psa, int m, int n, double c
   }
 #pragma unroll
   for (int pl = 0; pl < 4; ++pl) s[pl] = group_sum(s[pl], L);
-  double nrm = 0.0;
+  double nrm = 0.0, vw = 0.0;
   if (i < rows && l == 0) {
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) {
       const double x = c * s[pl];
       w[pl * rows + i] = x;
       nrm += x * x;
+      if (dot) vw += v[pl * cols + i] * x;
     }
   }
+  if (dot) *dot = vw;
   return nrm;
 }
 
@@ -534,7 +537,7 @@ __device__ __forceinline__ double sm_tile_sum(const double* v, int count, int st
 // the product (w = (A v) / ||v||), ||v||^2 and ||w||^2 ride along as wave partials, so a step is two
 // workgroup barriers.  Returns the last step's ||w||^2.
 template <class AP>
-__device__ double sm_power(AP a, int64_t lda, int64_t psa, int m, int n, int steps, uint64_t seed, double* vs,
+__device__ __forceinline__ double sm_power(AP a, int64_t lda, int64_t psa, int m, int n, int steps, uint64_t seed, double* vs,
                            double* wsv, double* shv, double* shw) {
   const int tid = threadIdx.x, wv = tid >> 6;
   double vv = 0.0;
@@ -558,6 +561,65 @@ __device__ double sm_power(AP a, int64_t lda, int64_t psa, int m, int n, int ste
     __syncthreads();
   }
   return s1sq;
+}
+
+// The same power iteration on the Gram matrix Gm = A^H A (n x n): per step v <- v / ||v||, u = Gm v, the
+// sigma_1^2 estimate (v . u) / ||v|| (= ||A v||^2 / ||v||^2 in exact arithmetic), v <- u, so one product and one
+// workgroup barrier per step.  The per-wave partials alternate between two slots of shv / shd (8 waves each),
+// so a wave that starts the next step cannot overwrite what a slower one still reads.
+template <class AP>
+__device__ __forceinline__ double sm_power_gram(AP g, int64_t ldg, int64_t psg, int n, int steps, uint64_t seed, double* vs,
+                                double* us, double* shv, double* shd) {
+  const int tid = threadIdx.x, wv = tid >> 6;
+  double vv = 0.0;
+  for (int e = tid; e < 4 * n; e += blockDim.x) {
+    const double x = (double)(sm_splitmix64((uint64_t)e, seed) >> 11) * 0x1p-52 - 1.0;
+    vs[e] = x;
+    vv += x * x;
+  }
+  vv = wave_sum(vv);
+  if ((tid & 63) == 0) shv[wv] = vv;
+  __syncthreads();
+  double s1sq = 0.0;
+  double *v = vs, *u = us;
+  for (int it = 0; it < steps; ++it) {
+    const int rd = (it & 1) * 8, wr = 8 - rd;
+    const double inv = 1.0 / sqrt(sm_sum_partials(shv + rd));
+    double dot = 0.0;
+    const double nu = wave_sum(sm_gemv<false>(g, ldg, psg, n, n, inv, v, u, &dot));
+    dot = wave_sum(dot);
+    if ((tid & 63) == 0) {
+      shv[wr + wv] = nu;
+      shd[rd + wv] = dot;
+    }
+    __syncthreads();
+    s1sq = sm_sum_partials(shd + rd) * inv;
+    double* t = v;
+    v = u;
+    u = t;
+  }
+  return s1sq;
+}
+
+// Waits (thread 0, bounded by the give-up rule of sm_sync) until *cnt >= target, then acquires.  False if the
+// wait gave up (the flag is raised; the next grid barrier then returns false everywhere).
+__device__ bool sm_wait_count(unsigned int* cnt, unsigned int target, unsigned int* bar) {
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    long long spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > SM_SPIN_MAX) {
+        __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
 }
 
 // The result record, written into pinned host memory by one thread at the end of the solve.
@@ -646,7 +708,10 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
     // the LDS copy's row stride is n rounded up to 8 mod 16 elements when that fits: the lanes of a wave that
     // read one column in different rows (both products of a power step) then fall on different banks
     const int ldp = ((n + 7) >> 4) * 16 + 8, ldc = 4 * m * ldp <= ACOPY_ELEMS ? ldp : n;
-    const bool in_lds = P->scaling == QPINV_ALPHA_POWER && 4 * m * ldc <= ACOPY_ELEMS;
+    // with the Gram matrix A^H A formed meanwhile (left side), the power steps run on it instead (padded the
+    // same way in LDS), one product per step
+    const bool gram_pw = P->scaling == QPINV_ALPHA_POWER && P->gram == 1 && 4 * n * ldp <= ACOPY_ELEMS;
+    const bool in_lds = P->scaling == QPINV_ALPHA_POWER && !gram_pw && 4 * m * ldc <= ACOPY_ELEMS;
     double fro = 0.0, bad = 0.0;
     {
       const int lgw = lg_ceil(n), slots = (4 * m) << lgw;
@@ -675,7 +740,31 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
     bad = sm_sum(bad, sh);
     double alpha = 0.0, s1sq = 0.0;
     if (bad == 0.0 && fro > 0.0) {
-      if (P->scaling == QPINV_ALPHA_POWER) {
+      if (gram_pw) {
+        const GemmParams<T>& gg = P->gram_item.g;
+        if (sm_wait_count(&P->bar[1], (unsigned int)(gg.tiles_m * gg.tiles_n), P->bar)) {
+          // Gm into LDS: its 4 n rows on slots of 2^lgw >= n columns, SM_SU loads in flight per thread
+          const T* gp = gg.out[0];
+          const int lgw = lg_ceil(n), slots = (4 * n) << lgw;
+          for (int e0 = tid; e0 < slots; e0 += SM_SU * (int)blockDim.x) {
+            T v[SM_SU];
+#pragma unroll
+            for (int u = 0; u < SM_SU; ++u) {
+              const int e = e0 + u * (int)blockDim.x, row = e >> lgw, c = e & ((1 << lgw) - 1), pl = plane_of(row, n);
+              v[u] = gload(gp, e < slots && c < n ? pl * gg.pso[0] + (int64_t)(row - pl * n) * gg.ldo[0] + c : 0);
+            }
+#pragma unroll
+            for (int u = 0; u < SM_SU; ++u) {
+              const int e = e0 + u * (int)blockDim.x, row = e >> lgw, c = e & ((1 << lgw) - 1);
+              if (e < slots && c < n) acopy[row * ldp + c] = v[u];
+            }
+          }
+          __syncthreads();
+          s1sq = sm_power_gram((const __attribute__((address_space(3))) T*)acopy, ldp, (int64_t)n * ldp, n,
+                               P->power_steps, P->seed, vs, wsv, sh, sh + 16);
+          alpha = (P->mu > 0.0 ? P->mu : 1.0) / s1sq;
+        }
+      } else if (P->scaling == QPINV_ALPHA_POWER) {
         if (in_lds)
           s1sq = sm_power((const __attribute__((address_space(3))) T*)acopy, ldc, (int64_t)m * ldc, m, n,
                           P->power_steps, P->seed, vs, wsv, sh, sh + 16);
@@ -700,16 +789,23 @@ __global__ void __launch_bounds__(SM_THREADS) small_solve_kernel(const SmParams<
     GemmParams<T> gq = P->gram_item.g;
     sm_bind(gq, P->gram_item.sub, static_cast<T*>(P->buf[1].p), static_cast<T*>(P->buf[2].p), call);
     make_uniform(gq);
+    unsigned int done_blocks = 0;
     for (int t = blockIdx.x - 1; t < gq.tiles_m * gq.tiles_n; t += G - 1) {
       double s_d = 0.0, s_x = 0.0;
       if (P->gram == 1)
         sm_block<T, MM, 1>(gq, t / gq.tiles_n, t % gq.tiles_n, stage, red, s_d, s_x);
       else
         sm_block<T, MM, 2>(gq, t / gq.tiles_n, t % gq.tiles_n, stage, red, s_d, s_x);
+      ++done_blocks;
     }
+    // the blocks are counted (released) for workgroup 0, which may run the power steps on them
+    if (tid == 0 && done_blocks)
+      __hip_atomic_fetch_add(&P->bar[1], done_blocks, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (!sm_sync(P->bar, G, call.bar_base, nbar)) return;
   stamp();
+  // every Gram block was counted before the barrier: the count starts from zero in the next solve
+  if (P->gram != 0 && blockIdx.x == 0 && tid == 0) __hip_atomic_store(&P->bar[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double bad = __hip_atomic_load(&P->state[S_NONFINITE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double fro = __hip_atomic_load(&P->state[S_NORMA2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const double alpha = __hip_atomic_load(&P->state[S_ALPHA], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
