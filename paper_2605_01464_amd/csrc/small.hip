@@ -567,6 +567,7 @@ __device__ __forceinline__ double sm_power(AP a, int64_t lda, int64_t psa, int m
 // sigma_1^2 estimate (v . u) / ||v|| (= ||A v||^2 / ||v||^2 in exact arithmetic), v <- u, so one product and one
 // workgroup barrier per step.  The per-wave partials alternate between two slots of shv / shd (8 waves each),
 // so a wave that starts the next step cannot overwrite what a slower one still reads.
+static_assert(SM_THREADS / 64 == 8, "two slots of 8 per-wave partials in sh[32]");
 template <class AP>
 __device__ __forceinline__ double sm_power_gram(AP g, int64_t ldg, int64_t psg, int n, int steps, uint64_t seed, double* vs,
                                 double* us, double* shv, double* shd) {
